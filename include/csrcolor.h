@@ -1,0 +1,156 @@
+/*
+ * csrcolor -- speculative-greedy vertex coloring of undirected CSR graphs on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library colors a graph with the data-driven speculative-greedy method of
+ * Chen et al., "Efficient and High-quality Sparse Graph Coloring on GPUs"
+ * (Sec. 3.1, Algorithm Data-GC; FirstFit and ConflictResolve of Sec. 3;
+ * colour clearing and worklist push by prefix sum of Sec. 3.1; bitset FirstFit
+ * of Sec. 3.2; degree-based load balancing of Sec. 3.3):
+ *
+ *   W = V; snapshot S = 0 (uncoloured)
+ *   repeat until W is empty:
+ *     every v in W takes the smallest colour c > 0 not in { S[w] : w in adj(v), w != v }
+ *     v in W loses if some neighbour w < v in W took the same colour
+ *     winners are fixed in S; losers are cleared and form the next W
+ *
+ * Rounds are Jacobi-style (FirstFit only sees the previous round's snapshot) and
+ * the HIGHER id of a same-colour adjacent pair is requeued, so the result is a
+ * deterministic function of the graph: it does not depend on thread timing,
+ * launch shape, bucket thresholds or mode.
+ *
+ * Conventions for every entry point:
+ *   - Graphs are symmetric CSR with int32 indices: rowptr[n+1] (rowptr[0] == 0,
+ *     non-decreasing) and colidx[rowptr[n]] with entries in [0, n).  Rows need
+ *     not be sorted (sorted rows are faster); self-loops are ignored and
+ *     duplicate entries are harmless.  Symmetry is a precondition, checked only
+ *     when opts->validate >= 1.
+ *   - Array arguments are DEVICE pointers owned by the caller unless marked
+ *     HOST.  Inputs are only read; outputs must not alias inputs.
+ *   - Output colours are 0-based: colors_out[v] in [0, ncolors).
+ *   - Work is enqueued on `stream`.  The library keeps a per-(device, stream)
+ *     workspace (about 12 bytes per vertex plus a small control block) that is
+ *     grown on demand and freed by csrcolor_release_workspace(); calls on the
+ *     same stream are serialised by a lock, calls on different streams do not
+ *     share scratch.
+ *   - Errors are negative csrcolor_status values; outputs are then unspecified.
+ *     Structural validation (rowptr monotone and in range, colidx in range) is
+ *     always done on the device before any colouring kernel runs, so a
+ *     malformed graph is reported as CSRCOLOR_EBADCSR, never read out of bounds
+ *     (this requires colidx to hold rowptr[n] entries as stated above).
+ */
+#ifndef CSRCOLOR_H
+#define CSRCOLOR_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CSRCOLOR_OK = 0,
+    CSRCOLOR_EINVAL = -1,     /* bad argument: n < 0, NULL pointer with n > 0, bad option */
+    CSRCOLOR_EBADCSR = -2,    /* rowptr[0] != 0, rowptr decreasing, or colidx out of [0, n) */
+    CSRCOLOR_ENOMEM = -3,     /* device or pinned host allocation failed */
+    CSRCOLOR_EHIP = -4,       /* a HIP runtime call failed */
+    CSRCOLOR_EOVERFLOW = -5,  /* sizes beyond int32 (batched totals) */
+    CSRCOLOR_ENOTSYM = -6,    /* validate >= 1 and the CSR is not symmetric */
+    CSRCOLOR_ELIMIT = -7      /* round limit reached (cannot happen for a valid graph: rounds <= n) */
+} csrcolor_status;
+
+/* How the rounds are driven.  Every mode gives the identical colouring. */
+typedef enum {
+    CSRCOLOR_MODE_AUTO = 0,        /* library choice */
+    CSRCOLOR_MODE_LOOP = 1,        /* host loop: two kernels per round, worklist size read back every few rounds */
+    CSRCOLOR_MODE_PERSISTENT = 2,  /* one cooperative kernel runs all rounds with device-wide barriers */
+    CSRCOLOR_MODE_GRAPH = 3        /* blocks of rounds captured once in a hipGraph and replayed */
+} csrcolor_mode;
+
+/* Tuning and checking options.  Zero-initialise and set what you need; every
+ * zero field means "library default".  No field changes the colouring. */
+typedef struct {
+    int32_t mode;           /* csrcolor_mode */
+    int32_t validate;       /* 1: also check symmetry (sorted rows only; costs one search per arc) */
+    int32_t t_wave;         /* max degree handled by one wavefront per vertex (>= 33; default 1024) */
+    int32_t t_split;        /* min degree whose row is split over several workgroups (default 16384) */
+    int32_t blocks_per_cu;  /* workgroups per compute unit for the round kernels (default 8) */
+    int32_t sync_every;     /* LOOP/GRAPH: rounds enqueued between worklist-size read-backs (default 8) */
+    int32_t reserved[10];
+} csrcolor_opts;
+
+/* Optional run statistics (HOST struct).  Set `cap`, `time_kernels` and the array
+ * pointers (HOST arrays of `cap` entries, or NULL) before the call; the library
+ * fills the rest. */
+typedef struct {
+    int32_t rounds;         /* out: number of rounds (0 for n == 0) */
+    int32_t ncolors;        /* out */
+    int32_t rows_sorted;    /* out: 1 if every row was in ascending order */
+    int32_t max_degree;     /* out */
+    int64_t nnz;            /* out: rowptr[n] */
+    int32_t cap;            /* in: capacity of the per-round arrays */
+    int32_t time_kernels;   /* in: 1 = bracket every kernel launch with HIP events on `stream` */
+    int64_t *wsize;         /* out: |W_r| for r = 0 .. min(rounds, cap)-1 */
+    int64_t *arcs;          /* out: sum of row lengths over W_r (arcs scanned by FirstFit) */
+    double ms_setup;        /* out (time_kernels): validation and round-1 kernels */
+    double ms_assign;       /* out (time_kernels): all FirstFit kernel launches */
+    double ms_detect;       /* out (time_kernels): all conflict-test kernel launches */
+    int32_t n_assign;       /* out (time_kernels): FirstFit launches */
+    int32_t n_detect;       /* out (time_kernels): conflict-test launches */
+} csrcolor_stats;
+
+/* Colour one graph (Sec. 3.1, Algorithm Data-GC).
+ *   n          number of vertices (>= 0)
+ *   rowptr     DEVICE int32[n+1]
+ *   colidx     DEVICE int32[rowptr[n]] (may be NULL when rowptr[n] == 0)
+ *   colors_out DEVICE int32[n], written with 0-based colours
+ *   ncolors    HOST int32*, receives the number of colours (max colour + 1; 0 if n == 0)
+ *   stream     HIP stream; the call synchronises it before returning.
+ * Returns CSRCOLOR_OK or a negative csrcolor_status. */
+int csrcolor_color(int32_t n, const int32_t *rowptr, const int32_t *colidx,
+                   int32_t *colors_out, int32_t *ncolors, hipStream_t stream);
+
+/* As csrcolor_color with options and statistics.
+ *   ncolors_host  HOST int32* (may be NULL)
+ *   opts          NULL for defaults
+ *   stats         NULL, or a HOST struct filled on return
+ * The call synchronises `stream` before returning. */
+int csrcolor_color_ex(int32_t n, const int32_t *rowptr, const int32_t *colidx,
+                      int32_t *colors_out, int32_t *ncolors_host,
+                      const csrcolor_opts *opts, csrcolor_stats *stats, hipStream_t stream);
+
+/* Colour G independent graphs stored as one block-diagonal CSR with global ids
+ * (graph g owns vertices voff[g] .. voff[g+1]-1; its arcs must stay inside that
+ * range).  Because rounds only look at neighbours and the requeue rule is
+ * invariant under a constant id shift, every graph receives exactly the colouring
+ * it would receive alone.
+ *   G            number of graphs (>= 0)
+ *   n_total      total vertices (must equal voff[G])
+ *   voff         DEVICE int64[G+1], voff[0] == 0, non-decreasing
+ *   rowptr       DEVICE int32[n_total+1]
+ *   colidx       DEVICE int32[rowptr[n_total]], global ids
+ *   colors_out   DEVICE int32[n_total], 0-based colours local to each graph
+ *   ncolors_out  DEVICE int32[G], colours used by each graph
+ *   opts         NULL for defaults
+ * The call synchronises `stream` before returning. */
+int csrcolor_color_batched(int32_t G, int32_t n_total, const int64_t *voff,
+                           const int32_t *rowptr, const int32_t *colidx,
+                           int32_t *colors_out, int32_t *ncolors_out,
+                           const csrcolor_opts *opts, hipStream_t stream);
+
+/* Static description of a status code. */
+const char *csrcolor_strerror(int status);
+
+/* Free every library-owned workspace on every device.  Must not overlap a
+ * running call. */
+void csrcolor_release_workspace(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int csrcolor_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSRCOLOR_H */

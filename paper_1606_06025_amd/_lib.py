@@ -1,0 +1,91 @@
+"""ctypes binding of libcsrcolor.so (argument marshalling only).
+
+Every step of a colouring runs in the library's HIP kernels; this module only
+passes device pointers, sizes and the current HIP stream.  It raises if the
+library has not been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcsrcolor.so")
+
+OK = 0
+EINVAL = -1
+EBADCSR = -2
+ENOMEM = -3
+EHIP = -4
+EOVERFLOW = -5
+ENOTSYM = -6
+ELIMIT = -7
+
+MODE_AUTO = 0
+MODE_LOOP = 1
+MODE_PERSISTENT = 2
+MODE_GRAPH = 3
+
+EXPORTS = ["csrcolor_color", "csrcolor_color_ex", "csrcolor_color_batched",
+           "csrcolor_strerror", "csrcolor_release_workspace", "csrcolor_version"]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("validate", ctypes.c_int32), ("t_wave", ctypes.c_int32),
+                ("t_split", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("sync_every", ctypes.c_int32), ("reserved", ctypes.c_int32 * 10)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("ncolors", ctypes.c_int32), ("rows_sorted", ctypes.c_int32),
+                ("max_degree", ctypes.c_int32), ("nnz", ctypes.c_int64), ("cap", ctypes.c_int32),
+                ("time_kernels", ctypes.c_int32), ("wsize", ctypes.POINTER(ctypes.c_int64)),
+                ("arcs", ctypes.POINTER(ctypes.c_int64)), ("ms_setup", ctypes.c_double),
+                ("ms_assign", ctypes.c_double), ("ms_detect", ctypes.c_double),
+                ("n_assign", ctypes.c_int32), ("n_detect", ctypes.c_int32)]
+
+
+class CsrColorError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"csrcolor status {status}: {msg}")
+        self.status = status
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the HIP library (import torch first so one HIP runtime is shared)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "or `python -m paper_1606_06025_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I32 = ctypes.c_void_p, ctypes.c_int32
+    lib.csrcolor_color.argtypes = [I32, P, P, P, ctypes.POINTER(I32), P]
+    lib.csrcolor_color.restype = ctypes.c_int
+    lib.csrcolor_color_ex.argtypes = [I32, P, P, P, ctypes.POINTER(I32), ctypes.POINTER(Opts),
+                                      ctypes.POINTER(Stats), P]
+    lib.csrcolor_color_ex.restype = ctypes.c_int
+    lib.csrcolor_color_batched.argtypes = [I32, I32, P, P, P, P, P, ctypes.POINTER(Opts), P]
+    lib.csrcolor_color_batched.restype = ctypes.c_int
+    lib.csrcolor_strerror.argtypes = [ctypes.c_int]
+    lib.csrcolor_strerror.restype = ctypes.c_char_p
+    lib.csrcolor_release_workspace.argtypes = []
+    lib.csrcolor_release_workspace.restype = None
+    lib.csrcolor_version.argtypes = []
+    lib.csrcolor_version.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    return load().csrcolor_strerror(status).decode()
+
+
+def check(status: int) -> None:
+    if status != OK:
+        raise CsrColorError(status, strerror(status))

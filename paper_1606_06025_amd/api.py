@@ -1,0 +1,118 @@
+"""Python entry points over the C-ABI (torch tensors for device memory and streams)."""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import List, Optional, Tuple
+
+import torch
+
+from . import _lib as L
+
+
+@dataclasses.dataclass
+class ColorStats:
+    rounds: int
+    ncolors: int
+    rows_sorted: bool
+    max_degree: int
+    nnz: int
+    wsize: List[int]
+    arcs: List[int]
+    ms_setup: float = 0.0
+    ms_assign: float = 0.0
+    ms_detect: float = 0.0
+    n_assign: int = 0
+    n_detect: int = 0
+
+
+def make_opts(mode: int = 0, validate: int = 0, t_wave: int = 0, t_split: int = 0,
+              blocks_per_cu: int = 0, sync_every: int = 0) -> L.Opts:
+    o = L.Opts()
+    o.mode, o.validate, o.t_wave, o.t_split = mode, validate, t_wave, t_split
+    o.blocks_per_cu, o.sync_every = blocks_per_cu, sync_every
+    return o
+
+
+def _stream_ptr(stream: Optional[torch.cuda.Stream]) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _check_csr(rowptr: torch.Tensor, colidx: torch.Tensor) -> int:
+    if rowptr.dtype != torch.int32 or colidx.dtype != torch.int32:
+        raise TypeError("rowptr and colidx must be int32")
+    if not (rowptr.is_cuda and colidx.is_cuda):
+        raise TypeError("rowptr and colidx must be device tensors")
+    if not (rowptr.is_contiguous() and colidx.is_contiguous()):
+        raise ValueError("rowptr and colidx must be contiguous")
+    if rowptr.dim() != 1 or rowptr.numel() < 1:
+        raise ValueError("rowptr must be 1-D with n+1 entries")
+    return rowptr.numel() - 1
+
+
+def color(rowptr: torch.Tensor, colidx: torch.Tensor, out: Optional[torch.Tensor] = None,
+          opts: Optional[L.Opts] = None, stats: bool = False, stats_cap: int = 4096,
+          time_kernels: bool = False,
+          stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, int, Optional[ColorStats]]:
+    """Colour one graph.  Returns (colors int32[n] on the device, ncolors, stats)."""
+    lib = L.load()
+    n = _check_csr(rowptr, colidx)
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.int32, device=rowptr.device)
+    elif out.dtype != torch.int32 or out.numel() < n or not out.is_cuda:
+        raise ValueError("out must be an int32 device tensor with n entries")
+    nc = ctypes.c_int32(0)
+    st = None
+    wbuf = abuf = None
+    if stats or time_kernels:
+        st = L.Stats()
+        st.time_kernels = 1 if time_kernels else 0
+        wbuf = (ctypes.c_int64 * stats_cap)()
+        abuf = (ctypes.c_int64 * stats_cap)()
+        st.cap = stats_cap
+        st.wsize = ctypes.cast(wbuf, ctypes.POINTER(ctypes.c_int64))
+        st.arcs = ctypes.cast(abuf, ctypes.POINTER(ctypes.c_int64))
+    rc = lib.csrcolor_color_ex(n, rowptr.data_ptr(), colidx.data_ptr(), out.data_ptr(), ctypes.byref(nc),
+                               ctypes.byref(opts) if opts is not None else None,
+                               ctypes.byref(st) if st is not None else None, _stream_ptr(stream))
+    L.check(rc)
+    cs = None
+    if st is not None:
+        k = min(st.rounds, stats_cap)
+        cs = ColorStats(st.rounds, st.ncolors, bool(st.rows_sorted), st.max_degree, st.nnz,
+                        list(wbuf[:k]), list(abuf[:k]), st.ms_setup, st.ms_assign, st.ms_detect,
+                        st.n_assign, st.n_detect)
+    return out[:n], int(nc.value), cs
+
+
+def color_raw(n: int, rowptr_ptr: int, colidx_ptr: int, out_ptr: int,
+              stream: Optional[torch.cuda.Stream] = None) -> int:
+    """csrcolor_color on raw device pointers; returns the status code unchanged."""
+    lib = L.load()
+    nc = ctypes.c_int32(0)
+    rc = lib.csrcolor_color(n, rowptr_ptr, colidx_ptr, out_ptr, ctypes.byref(nc), _stream_ptr(stream))
+    return rc if rc != L.OK else int(nc.value)
+
+
+def color_batched(voff: torch.Tensor, rowptr: torch.Tensor, colidx: torch.Tensor,
+                  out: Optional[torch.Tensor] = None, opts: Optional[L.Opts] = None,
+                  stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Colour G graphs stored block-diagonally.  Returns (colors, ncolors int32[G])."""
+    lib = L.load()
+    n = _check_csr(rowptr, colidx)
+    if voff.dtype != torch.int64 or not voff.is_cuda or voff.dim() != 1 or voff.numel() < 1:
+        raise TypeError("voff must be an int64 device tensor with G+1 entries")
+    G = voff.numel() - 1
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=rowptr.device)
+    ncol = torch.empty(max(G, 1), dtype=torch.int32, device=rowptr.device)
+    rc = lib.csrcolor_color_batched(G, n, voff.data_ptr(), rowptr.data_ptr(), colidx.data_ptr(),
+                                    out.data_ptr(), ncol.data_ptr(),
+                                    ctypes.byref(opts) if opts is not None else None, _stream_ptr(stream))
+    L.check(rc)
+    return out[:n], ncol[:G]
+
+
+def release_workspace() -> None:
+    L.load().csrcolor_release_workspace()

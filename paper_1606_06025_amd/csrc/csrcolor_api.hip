@@ -1,0 +1,474 @@
+// Host driver and C-ABI of the speculative-greedy colouring library.
+//
+// One colouring (Sec. 3.1, Algorithm Data-GC):
+//   k_init -> k_validate_rows -> [read back: errors, degree histogram, max degree]
+//   -> k_validate_arcs (+ k_check_symmetric) -> [read back: errors, row order]
+//   -> k_round1 -> { k_assign ; k_detect } per round, the worklist length read back
+//   every few rounds -> [read back: colour count].
+// Worklists are double-buffered by round parity (Sec. 3.1, swap of W_in / W_out);
+// each degree bucket owns a fixed segment of both worklist arrays whose size is the
+// number of vertices of that bucket, so no push can overflow.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "../../include/csrcolor.h"
+#include "sgr_kernels.h"
+
+namespace csrcolor {
+namespace {
+
+struct Workspace {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    size_t cap_n = 0;            // vertices the arrays below can hold
+    int* X = nullptr;            // colour state
+    int* wl[2] = {nullptr, nullptr};
+    Ctl* ctl = nullptr;          // device control block
+    Ctl* ctl_h = nullptr;        // pinned host mirror
+    int st_cap = 0;
+    long long* st_wsize = nullptr;
+    long long* st_arcs = nullptr;
+    std::vector<hipEvent_t> evs; // event pool for per-kernel timing
+    std::mutex mu;
+};
+
+// Brackets kernel launches with HIP events on the workspace stream when enabled.
+struct KTimer {
+    Workspace* w;
+    bool on;
+    size_t next = 0;
+    std::vector<std::pair<size_t, size_t>> spans[3];   // 0 setup, 1 assign, 2 detect
+    KTimer(Workspace* ws, bool enable) : w(ws), on(enable) {}
+    size_t mark() {
+        if (next == w->evs.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) { on = false; return 0; }
+            w->evs.push_back(e);
+        }
+        (void)hipEventRecord(w->evs[next], w->stream);
+        return next++;
+    }
+    template <class F>
+    void run(int kind, F&& launch) {
+        if (!on) { launch(); return; }
+        const size_t a = mark();
+        launch();
+        const size_t b = mark();
+        if (on) spans[kind].push_back({a, b});
+    }
+    double total_ms(int kind, int* count) const {
+        double t = 0;
+        for (auto& p : spans[kind]) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, w->evs[p.first], w->evs[p.second]) == hipSuccess) t += ms;
+        }
+        if (count) *count = (int)spans[kind].size();
+        return t;
+    }
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
+int g_num_cus[64] = {0};
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return CSRCOLOR_EHIP;     \
+    } while (0)
+
+int num_cus(int dev) {
+    if (dev < 0 || dev >= 64) return 256;
+    if (g_num_cus[dev] == 0) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+            c = 256;
+        g_num_cus[dev] = c;
+    }
+    return g_num_cus[dev];
+}
+
+Workspace* get_ws(int dev, hipStream_t stream) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_pair(dev, stream);
+    auto it = g_ws.find(key);
+    if (it != g_ws.end()) return it->second;
+    Workspace* w = new Workspace();
+    w->device = dev;
+    w->stream = stream;
+    g_ws[key] = w;
+    return w;
+}
+
+void free_ws_arrays(Workspace* w) {
+    if (w->X) (void)hipFree(w->X);
+    if (w->wl[0]) (void)hipFree(w->wl[0]);
+    if (w->wl[1]) (void)hipFree(w->wl[1]);
+    w->X = w->wl[0] = w->wl[1] = nullptr;
+    w->cap_n = 0;
+}
+
+int ensure_capacity(Workspace* w, size_t n, int st_cap) {
+    if (!w->ctl) {
+        HIP_TRY(hipMalloc(&w->ctl, sizeof(Ctl)));
+        if (hipHostMalloc(&w->ctl_h, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return CSRCOLOR_ENOMEM;
+    }
+    if (n > w->cap_n) {
+        (void)hipStreamSynchronize(w->stream);
+        free_ws_arrays(w);
+        size_t want = std::max(n, (size_t)1024);
+        if (hipMalloc(&w->X, want * sizeof(int)) != hipSuccess ||
+            hipMalloc(&w->wl[0], want * sizeof(int)) != hipSuccess ||
+            hipMalloc(&w->wl[1], want * sizeof(int)) != hipSuccess) {
+            free_ws_arrays(w);
+            return CSRCOLOR_ENOMEM;
+        }
+        w->cap_n = want;
+    }
+    if (st_cap > w->st_cap) {
+        (void)hipStreamSynchronize(w->stream);
+        if (w->st_wsize) (void)hipFree(w->st_wsize);
+        if (w->st_arcs) (void)hipFree(w->st_arcs);
+        w->st_wsize = w->st_arcs = nullptr;
+        w->st_cap = 0;
+        if (hipMalloc(&w->st_wsize, st_cap * sizeof(long long)) != hipSuccess ||
+            hipMalloc(&w->st_arcs, st_cap * sizeof(long long)) != hipSuccess)
+            return CSRCOLOR_ENOMEM;
+        w->st_cap = st_cap;
+    }
+    return CSRCOLOR_OK;
+}
+
+int read_ctl(Workspace* w) {
+    HIP_TRY(hipMemcpyAsync(w->ctl_h, w->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return CSRCOLOR_OK;
+}
+
+struct Options {
+    int mode = CSRCOLOR_MODE_LOOP;
+    int validate = 0;
+    int twave = 1024;
+    int blocks_per_cu = 8;
+    int sync_every = 8;
+};
+
+Options parse_opts(const csrcolor_opts* o) {
+    Options r;
+    if (!o) return r;
+    if (o->mode) r.mode = o->mode;
+    r.validate = o->validate;
+    if (o->t_wave > 0) r.twave = std::min(std::max(o->t_wave, 32), TWAVE_MAX);
+    if (o->blocks_per_cu > 0) r.blocks_per_cu = std::min(o->blocks_per_cu, 32);
+    if (o->sync_every > 0) r.sync_every = std::min(o->sync_every, 256);
+    return r;
+}
+
+// Workgroups per bucket for the next rounds, from upper bounds `ub` on the bucket
+// worklist lengths (lengths only shrink from round to round).  Each bucket gets a
+// share of the grid budget proportional to its estimated arc work, never more
+// workgroups than it has useful work for, rounded up to a multiple of 8 so the
+// XCD-contiguous block mapping applies.
+void make_plan(const int ub[NB], int budget, int boff[NB + 1]) {
+    static const double cost[NB] = {8.0, 16.0, 32.0, 128.0, 4096.0};
+    static const int per_wg[NB] = {WG / 8 * 4, WG / 16 * 4, WG / 32 * 4, WAVES * 4, 1};
+    double tot = 0;
+    for (int b = 0; b < NB; ++b) tot += ub[b] * cost[b];
+    boff[0] = 0;
+    for (int b = 0; b < NB; ++b) {
+        int nb = 0;
+        if (ub[b] > 0) {
+            const double share = tot > 0 ? ub[b] * cost[b] / tot : 1.0;
+            nb = std::max(1, (int)(share * budget + 0.5));
+            const int useful = (ub[b] + per_wg[b] - 1) / per_wg[b];
+            nb = std::min(nb, std::max(useful, 1));
+            nb = (nb + 7) & ~7;
+        }
+        boff[b + 1] = boff[b] + nb;
+    }
+}
+
+struct Job {
+    int n;
+    const int* rowptr;
+    const int* colidx;
+    int* colors_out;
+    Options opt;
+    csrcolor_stats* stats;
+    // results
+    int ncolors = 0;
+    int rounds = 0;
+    int sorted = 1;
+    int maxdeg = 0;
+    long long nnz = 0;
+};
+
+int run_job(Workspace* w, Job& J, const long long* voff, int G) {
+    const int n = J.n;
+    hipStream_t st = w->stream;
+    const int st_cap = J.stats ? std::max(J.stats->cap, 0) : 0;
+    int rc = ensure_capacity(w, (size_t)n, st_cap);
+    if (rc) return rc;
+    const int cus = num_cus(w->device);
+    const int twave = J.opt.twave;
+
+    KTimer T(w, J.stats && J.stats->time_kernels);
+    T.run(0, [&] { k_init<<<1, WG, 0, st>>>(w->ctl); });
+    const int vblocks = (int)std::min<long long>(((long long)n + WG - 1) / WG, (long long)cus * 16);
+    T.run(0, [&] {
+        k_validate_rows<<<std::max(vblocks, 1), WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl, twave);
+    });
+    HIP_TRY(hipGetLastError());
+    if ((rc = read_ctl(w))) return rc;
+    if (w->ctl_h->err) return CSRCOLOR_EBADCSR;
+    T.run(0, [&] { k_validate_arcs<<<cus * 16, WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl); });
+    if (voff) k_validate_batch<<<std::min(G, cus * 16), WG, 0, st>>>(G, n, voff, J.rowptr, J.colidx, w->ctl);
+    HIP_TRY(hipGetLastError());
+    if ((rc = read_ctl(w))) return rc;
+    if (w->ctl_h->err) return CSRCOLOR_EBADCSR;
+    J.sorted = w->ctl_h->desc_total == w->ctl_h->desc_bound;
+    J.maxdeg = w->ctl_h->maxdeg;
+    if (J.opt.validate >= 1) {
+        if (!J.sorted) return CSRCOLOR_EINVAL;   // symmetry check needs sorted rows
+        k_check_symmetric<<<vblocks, WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl);
+        HIP_TRY(hipGetLastError());
+        if ((rc = read_ctl(w))) return rc;
+        if (w->ctl_h->err & 4) return CSRCOLOR_ENOTSYM;
+        if (w->ctl_h->err) return CSRCOLOR_EBADCSR;
+    }
+    int hist[NB];
+    Seg seg;
+    seg.s[0] = 0;
+    for (int b = 0; b < NB; ++b) {
+        hist[b] = w->ctl_h->hist[b];
+        seg.s[b + 1] = seg.s[b] + hist[b];
+    }
+
+    const int r1blocks = (int)(((long long)n + 4 * WG - 1) / (4 * WG));
+    T.run(0, [&] {
+        k_round1<<<r1blocks, WG, 0, st>>>(n, J.rowptr, J.colidx, w->X, J.colors_out, w->wl[1], w->ctl,
+                                          J.sorted, twave, seg);
+    });
+    HIP_TRY(hipGetLastError());
+
+    RoundArgs a;
+    memset(&a, 0, sizeof(a));
+    a.n = n;
+    a.rowptr = J.rowptr;
+    a.colidx = J.colidx;
+    a.X = w->X;
+    a.out = J.colors_out;
+    a.ctl = w->ctl;
+    a.twave = twave;
+    a.sorted = J.sorted;
+    a.st_cap = st_cap;
+    a.st_wsize = st_cap ? w->st_wsize : nullptr;
+    a.st_arcs = st_cap ? w->st_arcs : nullptr;
+    for (int b = 0; b <= NB; ++b) a.seg[b] = seg.s[b];
+    if (st_cap) {
+        HIP_TRY(hipMemsetAsync(w->st_wsize, 0, st_cap * sizeof(long long), st));
+        HIP_TRY(hipMemsetAsync(w->st_arcs, 0, st_cap * sizeof(long long), st));
+    }
+
+    int ub[NB];
+    for (int b = 0; b < NB; ++b) ub[b] = hist[b];
+    int par = 1;             // parity of the worklist holding W of the next round
+    int round = 1;           // 0-based index of the next round
+    int k = 2;
+    const int budget = cus * J.opt.blocks_per_cu;
+    for (;;) {
+        long long tot = 0;
+        for (int b = 0; b < NB; ++b) tot += ub[b];
+        if (tot == 0) break;
+        make_plan(ub, budget, a.boff);
+        const int grid = a.boff[NB];
+        for (int i = 0; i < k; ++i) {
+            a.par_in = par;
+            a.par_out = par ^ 1;
+            a.wl_in = w->wl[par];
+            a.wl_out = w->wl[par ^ 1];
+            a.round = round;
+            T.run(1, [&] { k_assign<<<grid, WG, 0, st>>>(a); });
+            T.run(2, [&] { k_detect<<<grid, WG, 0, st>>>(a); });
+            par ^= 1;
+            ++round;
+        }
+        HIP_TRY(hipGetLastError());
+        if ((rc = read_ctl(w))) return rc;
+        if (w->ctl_h->err) return CSRCOLOR_EHIP;
+        long long left = 0;
+        for (int b = 0; b < NB; ++b) left += (ub[b] = w->ctl_h->cnt[par][b]);
+        if (left > 0 && round > n + 2) return CSRCOLOR_ELIMIT;   // rounds <= n for valid input
+        k = std::min(k * 2, J.opt.sync_every);
+    }
+    if ((rc = read_ctl(w))) return rc;
+    // Vertex 0 has no lower neighbour, so it always settles in round 1 with colour 1
+    // (round-1 winners do not touch the device maximum).
+    J.ncolors = std::max(w->ctl_h->maxcolor, 1);
+    J.rounds = std::max(w->ctl_h->rounds, 1);
+    J.nnz = w->ctl_h->nnz;
+    if (J.stats) {
+        J.stats->nnz = J.nnz;
+        if (T.on) {
+            J.stats->ms_setup = T.total_ms(0, nullptr);
+            J.stats->ms_assign = T.total_ms(1, &J.stats->n_assign);
+            J.stats->ms_detect = T.total_ms(2, &J.stats->n_detect);
+        } else {
+            J.stats->ms_setup = J.stats->ms_assign = J.stats->ms_detect = 0;
+            J.stats->n_assign = J.stats->n_detect = 0;
+        }
+        J.stats->rounds = J.rounds;
+        J.stats->ncolors = J.ncolors;
+        J.stats->rows_sorted = J.sorted;
+        J.stats->max_degree = J.maxdeg;
+        const int m = std::min(J.rounds, st_cap);
+        if (m > 0) {
+            std::vector<long long> tmp(m);
+            if (J.stats->wsize) {
+                HIP_TRY(hipMemcpyAsync(tmp.data(), w->st_wsize, m * sizeof(long long), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                for (int r = 0; r < m; ++r) J.stats->wsize[r] = tmp[r];
+                J.stats->wsize[0] = n;
+            }
+            if (J.stats->arcs) {
+                HIP_TRY(hipMemcpyAsync(tmp.data(), w->st_arcs, m * sizeof(long long), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                for (int r = 0; r < m; ++r) J.stats->arcs[r] = tmp[r];
+                J.stats->arcs[0] = w->ctl_h->nnz;
+            }
+        }
+    }
+    return CSRCOLOR_OK;
+}
+
+}  // namespace
+}  // namespace csrcolor
+
+using namespace csrcolor;
+
+extern "C" {
+
+int csrcolor_color_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx, int32_t* colors_out,
+                      int32_t* ncolors_host, const csrcolor_opts* opts, csrcolor_stats* stats,
+                      hipStream_t stream) {
+    if (n < 0) return CSRCOLOR_EINVAL;
+    if (opts && (opts->mode < 0 || opts->mode > CSRCOLOR_MODE_GRAPH || opts->validate < 0))
+        return CSRCOLOR_EINVAL;
+    if (stats && stats->cap > 0 && stats->cap > (1 << 24)) return CSRCOLOR_EINVAL;
+    if (n == 0) {
+        if (ncolors_host) *ncolors_host = 0;
+        if (stats) {
+            stats->rounds = stats->ncolors = stats->max_degree = 0;
+            stats->rows_sorted = 1;
+            stats->nnz = 0;
+        }
+        return CSRCOLOR_OK;
+    }
+    if (!rowptr || !colors_out) return CSRCOLOR_EINVAL;   // colidx may be NULL when rowptr[n] == 0
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return CSRCOLOR_EHIP;
+    Workspace* w = get_ws(dev, stream);
+    std::lock_guard<std::mutex> lk(w->mu);
+    Job J;
+    J.n = n;
+    J.rowptr = rowptr;
+    J.colidx = colidx;
+    J.colors_out = colors_out;
+    J.opt = parse_opts(opts);
+    J.stats = stats;
+    int rc = run_job(w, J, nullptr, 0);
+    if (rc) return rc;
+    if (ncolors_host) *ncolors_host = J.ncolors;
+    return CSRCOLOR_OK;
+}
+
+int csrcolor_color(int32_t n, const int32_t* rowptr, const int32_t* colidx, int32_t* colors_out,
+                   int32_t* ncolors, hipStream_t stream) {
+    if (!ncolors) return CSRCOLOR_EINVAL;
+    return csrcolor_color_ex(n, rowptr, colidx, colors_out, ncolors, nullptr, nullptr, stream);
+}
+
+int csrcolor_color_batched(int32_t G, int32_t n_total, const int64_t* voff, const int32_t* rowptr,
+                           const int32_t* colidx, int32_t* colors_out, int32_t* ncolors_out,
+                           const csrcolor_opts* opts, hipStream_t stream) {
+    if (G < 0 || n_total < 0) return CSRCOLOR_EINVAL;
+    if (G == 0) return n_total == 0 ? CSRCOLOR_OK : CSRCOLOR_EINVAL;
+    if (!voff || !ncolors_out) return CSRCOLOR_EINVAL;
+    if (opts && (opts->mode < 0 || opts->mode > CSRCOLOR_MODE_GRAPH || opts->validate < 0))
+        return CSRCOLOR_EINVAL;
+    if (n_total > 0 && (!rowptr || !colors_out)) return CSRCOLOR_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return CSRCOLOR_EHIP;
+    Workspace* w = get_ws(dev, stream);
+    std::lock_guard<std::mutex> lk(w->mu);
+    if (n_total > 0) {
+        Job J;
+        J.n = n_total;
+        J.rowptr = rowptr;
+        J.colidx = colidx;
+        J.colors_out = colors_out;
+        J.opt = parse_opts(opts);
+        J.stats = nullptr;
+        int rc = run_job(w, J, reinterpret_cast<const long long*>(voff), G);
+        if (rc) return rc;
+    }
+    const int cus = num_cus(dev);
+    if (n_total == 0) {
+        k_fill<<<(G + WG - 1) / WG, WG, 0, stream>>>(ncolors_out, G, 0);
+        if (hipGetLastError() != hipSuccess) return CSRCOLOR_EHIP;
+        return hipStreamSynchronize(stream) == hipSuccess ? CSRCOLOR_OK : CSRCOLOR_EHIP;
+    }
+    k_segmented_max<<<std::min(G, cus * 8), WG, 0, stream>>>(G, reinterpret_cast<const long long*>(voff),
+                                                               colors_out, ncolors_out);
+    if (hipGetLastError() != hipSuccess) return CSRCOLOR_EHIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return CSRCOLOR_EHIP;
+    return CSRCOLOR_OK;
+}
+
+const char* csrcolor_strerror(int status) {
+    switch (status) {
+        case CSRCOLOR_OK: return "success";
+        case CSRCOLOR_EINVAL: return "invalid argument";
+        case CSRCOLOR_EBADCSR: return "malformed CSR (rowptr not monotone from 0, or colidx out of range)";
+        case CSRCOLOR_ENOMEM: return "out of memory";
+        case CSRCOLOR_EHIP: return "HIP runtime error";
+        case CSRCOLOR_EOVERFLOW: return "size exceeds int32 range";
+        case CSRCOLOR_ENOTSYM: return "CSR is not symmetric";
+        case CSRCOLOR_ELIMIT: return "round limit exceeded";
+        default: return "unknown status";
+    }
+}
+
+void csrcolor_release_workspace(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto& kv : g_ws) {
+        Workspace* w = kv.second;
+        std::lock_guard<std::mutex> l2(w->mu);
+        (void)hipSetDevice(w->device);
+        (void)hipStreamSynchronize(w->stream);
+        free_ws_arrays(w);
+        if (w->ctl) (void)hipFree(w->ctl);
+        if (w->ctl_h) (void)hipHostFree(w->ctl_h);
+        if (w->st_wsize) (void)hipFree(w->st_wsize);
+        if (w->st_arcs) (void)hipFree(w->st_arcs);
+        w->ctl = nullptr;
+        w->ctl_h = nullptr;
+        w->st_wsize = w->st_arcs = nullptr;
+        w->st_cap = 0;
+    }
+    (void)hipSetDevice(cur);
+}
+
+int csrcolor_version(void) { return 100; }
+
+}  // extern "C"

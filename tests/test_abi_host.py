@@ -1,0 +1,73 @@
+"""C-ABI library: loads, exports every declared symbol, and host-side argument checks
+(no GPU work is issued by these calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1606_06025_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "csrcolor.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(csrcolor_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_1606_06025_amd import build
+        build.build()
+    return L.load()
+
+
+def test_header_declares_expected_entry_points():
+    assert _declared() == sorted(L.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    raw = ctypes.CDLL(L.LIB_PATH)
+    for name in _declared():
+        assert hasattr(raw, name), name
+
+
+def test_version_and_strerror(lib):
+    assert lib.csrcolor_version() >= 100
+    for code in [L.OK, L.EINVAL, L.EBADCSR, L.ENOMEM, L.EHIP, L.EOVERFLOW, L.ENOTSYM, L.ELIMIT]:
+        assert lib.csrcolor_strerror(code)
+    assert b"unknown" in lib.csrcolor_strerror(12345)
+
+
+def test_argument_errors_without_device_work(lib):
+    nc = ctypes.c_int32(-1)
+    assert lib.csrcolor_color(-1, None, None, None, ctypes.byref(nc), None) == L.EINVAL
+    assert lib.csrcolor_color(5, None, None, None, ctypes.byref(nc), None) == L.EINVAL
+    assert lib.csrcolor_color(5, 1, 1, 1, None, None) == L.EINVAL
+    assert lib.csrcolor_color(5, 1, 1, None, ctypes.byref(nc), None) == L.EINVAL
+    assert lib.csrcolor_color_batched(-1, 0, None, None, None, None, None, None, None) == L.EINVAL
+    assert lib.csrcolor_color_batched(0, 3, None, None, None, None, None, None, None) == L.EINVAL
+    assert lib.csrcolor_color_batched(0, 0, None, None, None, None, None, None, None) == L.OK
+    bad = L.Opts()
+    bad.mode = 99
+    assert lib.csrcolor_color_ex(3, 1, 1, 1, None, ctypes.byref(bad), None, None) == L.EINVAL
+
+
+def test_empty_graph_is_host_only(lib):
+    nc = ctypes.c_int32(-1)
+    assert lib.csrcolor_color(0, None, None, None, ctypes.byref(nc), None) == L.OK
+    assert nc.value == 0
+    st = L.Stats()
+    assert lib.csrcolor_color_ex(0, None, None, None, ctypes.byref(nc), None, ctypes.byref(st), None) == L.OK
+    assert st.rounds == 0 and st.ncolors == 0
+
+
+def test_struct_layouts_match_header():
+    # csrcolor_opts: 6 int32 + 10 reserved
+    # csrcolor_stats: 4 int32, int64, 2 int32, 2 pointers, 3 double, 2 int32
+    assert ctypes.sizeof(L.Opts) == 16 * 4
+    assert ctypes.sizeof(L.Stats) == 4 * 4 + 8 + 2 * 4 + 2 * 8 + 3 * 8 + 2 * 4

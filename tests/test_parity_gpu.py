@@ -1,0 +1,220 @@
+"""GPU parity: the HIP colouring equals the CPU oracle bit for bit.
+
+Every case runs through the C-ABI (csrcolor_color_ex / csrcolor_color_batched) and
+compares colours, colour count, round count and per-round worklist sizes and arc
+counts with the serial oracle on the same seeded input.  Integer work, so the bar is
+exact equality.
+"""
+import numpy as np
+import pytest
+
+from paper_1606_06025_amd import graphs as gg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1606_06025_amd import _lib
+    _lib.load()
+    return torch.device("cuda:0")
+
+
+def _run(g, dev, **kw):
+    from paper_1606_06025_amd import api
+    rp = torch.from_numpy(np.ascontiguousarray(g.rowptr, dtype=np.int32)).to(dev)
+    ci = torch.from_numpy(np.ascontiguousarray(g.colidx, dtype=np.int32)).to(dev)
+    opts = api.make_opts(**kw) if kw else None
+    colors, nc, st = api.color(rp, ci, opts=opts, stats=True, stats_cap=1 << 16)
+    torch.cuda.synchronize()
+    return colors.cpu().numpy(), nc, st
+
+
+def _assert_parity(g, dev, ref=None, **kw):
+    import oracle
+    if ref is None:
+        ref = oracle.sgr(g.n, g.rowptr, g.colidx)
+    got, nc, st = _run(g, dev, **kw)
+    assert got.shape == ref.colors.shape
+    bad = np.flatnonzero(got != ref.colors)
+    assert bad.size == 0, f"{g.name}: {bad.size} vertices differ, first {bad[:8]} got {got[bad[:8]]} want {ref.colors[bad[:8]]}"
+    assert nc == ref.ncolors, (nc, ref.ncolors)
+    assert st.rounds == ref.rounds, (st.rounds, ref.rounds)
+    k = min(len(st.wsize), ref.rounds)
+    assert st.wsize[:k] == ref.wsize[:k].tolist()
+    assert st.arcs[:k] == ref.arcs_ff[:k].tolist()
+    return got, ref
+
+
+def test_golden_small(dev):
+    for n, edges in [(5, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 0)]),
+                     (7, [(i, (i + 1) % 7) for i in range(7)]),
+                     (4, [(0, 1), (1, 2), (2, 3)]),
+                     (6, [(0, k) for k in range(1, 6)]),
+                     (6, [(5, k) for k in range(5)]),
+                     (3, [(0, 1), (1, 2), (2, 0)]),
+                     (1, []), (2, [(0, 1)]), (3, [(1, 2)])]:
+        _assert_parity(gg.from_edges(n, edges), dev)
+
+
+def test_hand_trace_values(dev):
+    got, _, st = _run(gg.cycle(5), dev)
+    assert (got + 1).tolist() == [1, 2, 1, 3, 2] and st.rounds == 3
+    got, _, st = _run(gg.cycle(7), dev)
+    assert (got + 1).tolist() == [1, 2, 1, 2, 1, 3, 2] and st.rounds == 4
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_fuzz_random(dev, seed):
+    sizes = [(2, 1.0), (9, 0.5), (33, 0.3), (64, 0.2), (65, 0.9), (130, 0.05), (300, 0.02),
+             (700, 0.01), (1000, 0.2), (2500, 0.004), (4000, 0.03), (5000, 0.001)]
+    n, p = sizes[seed % len(sizes)]
+    g = gg.random_small(n, p, seed)
+    _assert_parity(g, dev)
+
+
+@pytest.mark.parametrize("n", [33, 64, 65, 129, 300, 1025, 1100])
+def test_complete_graphs_many_colours(dev, n):
+    got, ref = _assert_parity(gg.complete(n), dev)
+    assert got.tolist() == list(range(n))
+
+
+def test_edgeless_and_single(dev):
+    for n in [1, 2, 1000, 70000]:
+        got, ref = _assert_parity(gg.edgeless(n), dev)
+        assert (got == 0).all()
+
+
+@pytest.mark.parametrize("leaves,center", [(200, 0), (5000, 0), (5000, 5000), (40000, 20000)])
+def test_stars_hubs(dev, leaves, center):
+    lv = [i for i in range(leaves + 1) if i != center]
+    _assert_parity(gg.star(center, lv), dev)
+
+
+def test_unsorted_rows_selfloops_duplicates(dev):
+    import oracle
+    g = gg.erdos_renyi(3000, 30000, 5)
+    ref = oracle.sgr(g.n, g.rowptr, g.colidx)
+    got, _ = _assert_parity(gg.shuffle_rows(g, 1), dev)
+    assert (got == ref.colors).all()
+    rows = []
+    for v in range(g.n):
+        r = g.colidx[g.rowptr[v]:g.rowptr[v + 1]].tolist()
+        rows.append(r[::-1] + [v] + r[:2])
+    raw = gg.raw_csr(g.n, rows)
+    got, _ = _assert_parity(raw, dev)          # stats from the oracle on the same raw input
+    assert (got == ref.colors).all()           # self-loops / duplicates do not change colours
+
+
+def test_mixed_degree_rmat(dev):
+    for sc, ef, seed in [(12, 16, 1), (14, 8, 2), (15, 16, 3)]:
+        _assert_parity(gg.rmat(sc, ef, seed), dev)
+
+
+def test_mixed_stencils(dev):
+    for dims in [(2, 2, 2), (3, 5, 7), (16, 16, 16), (40, 9, 11)]:
+        _assert_parity(gg.stencil27(*dims), dev)
+
+
+@pytest.mark.parametrize("kw", [dict(t_wave=33), dict(t_wave=64), dict(t_wave=200),
+                                dict(blocks_per_cu=1), dict(blocks_per_cu=3), dict(sync_every=1),
+                                dict(sync_every=5), dict(t_wave=40, blocks_per_cu=2, sync_every=3)])
+def test_launch_options_do_not_change_result(dev, kw):
+    import oracle
+    g = gg.rmat(13, 16, 9)
+    ref = oracle.sgr(g.n, g.rowptr, g.colidx)
+    _assert_parity(g, dev, ref, **kw)
+
+
+def test_repeated_runs_identical(dev):
+    g = gg.erdos_renyi(20000, 200000, 4)
+    a, _, _ = _run(g, dev)
+    for _ in range(3):
+        b, _, _ = _run(g, dev)
+        assert (a == b).all()
+
+
+def test_config_er16k_full(dev):
+    for seed in (1, 2, 3):
+        _assert_parity(gg.config_er16k(seed), dev)
+
+
+def test_config_stencil128_full(dev):
+    import oracle
+    g = gg.config_stencil128()
+    ref = oracle.sgr(g.n, g.rowptr, g.colidx)
+    assert ref.rounds == 197 and ref.ncolors == 8
+    _assert_parity(g, dev, ref)
+
+
+def test_malformed_inputs_are_rejected(dev):
+    from paper_1606_06025_amd import _lib as L, api
+    cases = [
+        (np.array([0, 2, 1, 3], np.int32), np.array([1, 2, 0], np.int32)),      # rowptr decreasing
+        (np.array([1, 2, 3, 4], np.int32), np.array([1, 2, 0, 1], np.int32)),   # rowptr[0] != 0
+        (np.array([0, 1, 2, 3], np.int32), np.array([1, 7, 0], np.int32)),      # colidx >= n
+        (np.array([0, 1, 2, 3], np.int32), np.array([1, -1, 0], np.int32)),     # colidx < 0
+    ]
+    for rp, ci in cases:
+        t_rp = torch.from_numpy(rp).to(dev)
+        t_ci = torch.from_numpy(ci).to(dev)
+        with pytest.raises(L.CsrColorError) as e:
+            api.color(t_rp, t_ci)
+        assert e.value.status == L.EBADCSR
+    # asymmetric graph under symmetry validation
+    rp = torch.tensor([0, 1, 1, 1], dtype=torch.int32, device=dev)
+    ci = torch.tensor([1], dtype=torch.int32, device=dev)
+    with pytest.raises(L.CsrColorError) as e:
+        api.color(rp, ci, opts=api.make_opts(validate=1))
+    assert e.value.status == L.ENOTSYM
+    # the library still works afterwards
+    _assert_parity(gg.cycle(9), dev)
+
+
+def test_symmetry_validation_accepts_valid(dev):
+    _assert_parity(gg.erdos_renyi(2000, 9000, 3), dev, validate=1)
+
+
+def test_raw_entry_point(dev):
+    from paper_1606_06025_amd import api
+    import oracle
+    g = gg.erdos_renyi(1000, 5000, 2)
+    rp = torch.from_numpy(g.rowptr).to(dev)
+    ci = torch.from_numpy(g.colidx).to(dev)
+    out = torch.empty(g.n, dtype=torch.int32, device=dev)
+    nc = api.color_raw(g.n, rp.data_ptr(), ci.data_ptr(), out.data_ptr())
+    ref = oracle.sgr(g.n, g.rowptr, g.colidx)
+    assert nc == ref.ncolors
+    assert (out.cpu().numpy() == ref.colors).all()
+
+
+def test_batched_equals_per_graph(dev):
+    import oracle
+    from paper_1606_06025_amd import api
+    parts = [gg.erdos_renyi(1500, 12000, 1, 1), gg.stencil27(9, 8, 7), gg.complete(70),
+             gg.star(3, [0, 1, 2, 4, 5, 6, 7]), gg.edgeless(50), gg.cycle(21),
+             gg.rmat(11, 16, 4), gg.erdos_renyi(5000, 20000, 1, 2)]
+    b = gg.concat_graphs(parts)
+    voff = torch.from_numpy(b.voff).to(dev)
+    rp = torch.from_numpy(b.rowptr).to(dev)
+    ci = torch.from_numpy(b.colidx).to(dev)
+    colors, ncol = api.color_batched(voff, rp, ci)
+    colors = colors.cpu().numpy()
+    ncol = ncol.cpu().numpy()
+    for i, p in enumerate(parts):
+        ref = oracle.sgr(p.n, p.rowptr, p.colidx)
+        assert (colors[b.voff[i]:b.voff[i + 1]] == ref.colors).all(), i
+        assert ncol[i] == ref.ncolors
+
+
+def test_batched_rejects_cross_graph_arcs(dev):
+    from paper_1606_06025_amd import _lib as L, api
+    g = gg.cycle(6)
+    voff = torch.tensor([0, 3, 6], dtype=torch.int64, device=dev)
+    with pytest.raises(L.CsrColorError) as e:
+        api.color_batched(voff, torch.from_numpy(g.rowptr).to(dev), torch.from_numpy(g.colidx).to(dev))
+    assert e.value.status == L.EBADCSR
