@@ -76,6 +76,11 @@ def main() -> int:
     ap.add_argument("--workload", default="stencil128")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--mode", type=int, default=0, help="csrcolor_mode (0 = library default)")
+    ap.add_argument("--lane-assign", type=int, default=0, help="csrcolor_opts.lane_assign (0 = default)")
+    ap.add_argument("--lane-detect", type=int, default=0, help="csrcolor_opts.lane_detect (0 = default)")
+    ap.add_argument("--t-wave", type=int, default=0)
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--sync-every", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     args = ap.parse_args()
@@ -101,7 +106,9 @@ def main() -> int:
     rp = torch.from_numpy(g.rowptr).to(dev)
     ci = torch.from_numpy(g.colidx).to(dev)
     out = torch.empty(g.n, dtype=torch.int32, device=dev)
-    opts = api.make_opts(mode=args.mode) if args.mode else None
+    tuned = dict(mode=args.mode, lane_assign=args.lane_assign, lane_detect=args.lane_detect,
+                 t_wave=args.t_wave, blocks_per_cu=args.blocks_per_cu, sync_every=args.sync_every)
+    opts = api.make_opts(**tuned) if any(tuned.values()) else None
 
     # warmup (also allocates the library workspace)
     for _ in range(args.warmup):
@@ -180,7 +187,7 @@ def main() -> int:
         "config": {"workload": g.name, "n": g.n, "nnz": g.nnz, "rounds": st.rounds,
                    "ncolors": ncolors, "serial_ff_colors": ff_colors,
                    "colors_vs_serial_ff": round(ncolors / ff_colors, 4) if ff_colors else None,
-                   "mode": args.mode, **kern},
+                   **{k: v for k, v in tuned.items() if v}, **kern},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -34,7 +34,8 @@ EXPORTS = ["csrcolor_color", "csrcolor_color_ex", "csrcolor_color_batched",
 class Opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("validate", ctypes.c_int32), ("t_wave", ctypes.c_int32),
                 ("t_split", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("sync_every", ctypes.c_int32), ("reserved", ctypes.c_int32 * 10)]
+                ("sync_every", ctypes.c_int32), ("lane_assign", ctypes.c_int32),
+                ("lane_detect", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
 
 
 class Stats(ctypes.Structure):

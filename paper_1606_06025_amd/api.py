@@ -27,10 +27,12 @@ class ColorStats:
 
 
 def make_opts(mode: int = 0, validate: int = 0, t_wave: int = 0, t_split: int = 0,
-              blocks_per_cu: int = 0, sync_every: int = 0) -> L.Opts:
+              blocks_per_cu: int = 0, sync_every: int = 0, lane_assign: int = 0,
+              lane_detect: int = 0) -> L.Opts:
     o = L.Opts()
     o.mode, o.validate, o.t_wave, o.t_split = mode, validate, t_wave, t_split
     o.blocks_per_cu, o.sync_every = blocks_per_cu, sync_every
+    o.lane_assign, o.lane_detect = lane_assign, lane_detect
     return o
 
 

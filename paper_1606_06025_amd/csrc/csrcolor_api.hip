@@ -36,7 +36,17 @@ struct Workspace {
     int st_cap = 0;
     long long* st_wsize = nullptr;
     long long* st_arcs = nullptr;
+    // split-row bucket scratch: cstart[2] and hub flags sized by hub count, owner[2] by chunk count
+    int* split = nullptr;
+    size_t split_cap = 0;        // ints
     std::vector<hipEvent_t> evs; // event pool for per-kernel timing
+    // graph mode: private capture stream, the instantiated two-round graph and the
+    // arguments it was captured with
+    hipStream_t gstream = nullptr;
+    hipEvent_t gev = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    RoundArgs gargs;
+    int gbudget = 0;
     std::mutex mu;
 };
 
@@ -109,6 +119,9 @@ Workspace* get_ws(int dev, hipStream_t stream) {
 }
 
 void free_ws_arrays(Workspace* w) {
+    if (w->split) (void)hipFree(w->split);
+    w->split = nullptr;
+    w->split_cap = 0;
     if (w->X) (void)hipFree(w->X);
     if (w->wl[0]) (void)hipFree(w->wl[0]);
     if (w->wl[1]) (void)hipFree(w->wl[1]);
@@ -147,6 +160,18 @@ int ensure_capacity(Workspace* w, size_t n, int st_cap) {
     return CSRCOLOR_OK;
 }
 
+int ensure_split(Workspace* w, size_t ints) {
+    if (ints <= w->split_cap) return CSRCOLOR_OK;
+    (void)hipStreamSynchronize(w->stream);
+    if (w->split) (void)hipFree(w->split);
+    w->split = nullptr;
+    w->split_cap = 0;
+    const size_t want = std::max(ints, (size_t)4096);
+    if (hipMalloc(&w->split, want * sizeof(int)) != hipSuccess) return CSRCOLOR_ENOMEM;
+    w->split_cap = want;
+    return CSRCOLOR_OK;
+}
+
 int read_ctl(Workspace* w) {
     HIP_TRY(hipMemcpyAsync(w->ctl_h, w->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, w->stream));
     HIP_TRY(hipStreamSynchronize(w->stream));
@@ -159,6 +184,9 @@ struct Options {
     int twave = 1024;
     int blocks_per_cu = 8;
     int sync_every = 8;
+    int tsplit = 2048;
+    int lane_assign = 0;      // tile buckets run with 2/4/8/16 lanes per vertex
+    int lane_detect = 0xF;    // lane-per-vertex conflict test (early exit) in every tile bucket
 };
 
 Options parse_opts(const csrcolor_opts* o) {
@@ -166,31 +194,31 @@ Options parse_opts(const csrcolor_opts* o) {
     if (!o) return r;
     if (o->mode) r.mode = o->mode;
     r.validate = o->validate;
-    if (o->t_wave > 0) r.twave = std::min(std::max(o->t_wave, 32), TWAVE_MAX);
+    if (o->t_wave > 0) r.twave = std::min(std::max(o->t_wave, TWAVE_MIN), TWAVE_MAX);
     if (o->blocks_per_cu > 0) r.blocks_per_cu = std::min(o->blocks_per_cu, 32);
     if (o->sync_every > 0) r.sync_every = std::min(o->sync_every, 256);
+    if (o->t_split > 0) r.tsplit = std::max(o->t_split, TSPLIT_MIN);
+    r.tsplit = std::max(r.tsplit, r.twave);
+    if (o->lane_assign) r.lane_assign = o->lane_assign < 0 ? 0 : (o->lane_assign & 0xF);
+    if (o->lane_detect) r.lane_detect = o->lane_detect < 0 ? 0 : (o->lane_detect & 0xF);
     return r;
 }
 
-// Workgroups per bucket for the next rounds, from upper bounds `ub` on the bucket
-// worklist lengths (lengths only shrink from round to round).  Each bucket gets a
-// share of the grid budget proportional to its estimated arc work, never more
-// workgroups than it has useful work for, rounded up to a multiple of 8 so the
-// XCD-contiguous block mapping applies.
+// Workgroups per bucket for the next rounds of the host loop, from upper bounds `ub`
+// on the queue sizes (sizes only shrink from round to round; ub[BSPLIT] counts
+// chunks).  Each bucket gets a share of the budget proportional to its estimated arc
+// work (plan_cost), never more workgroups than it has units for.
 void make_plan(const int ub[NB], int budget, int boff[NB + 1]) {
-    static const double cost[NB] = {8.0, 16.0, 32.0, 128.0, 4096.0};
-    static const int per_wg[NB] = {WG / 8 * 4, WG / 16 * 4, WG / 32 * 4, WAVES * 4, 1};
     double tot = 0;
-    for (int b = 0; b < NB; ++b) tot += ub[b] * cost[b];
+    for (int b = 0; b < NB; ++b) tot += (double)ub[b] * plan_cost(b);
     boff[0] = 0;
     for (int b = 0; b < NB; ++b) {
         int nb = 0;
         if (ub[b] > 0) {
-            const double share = tot > 0 ? ub[b] * cost[b] / tot : 1.0;
+            const double share = tot > 0 ? ub[b] * plan_cost(b) / tot : 1.0;
             nb = std::max(1, (int)(share * budget + 0.5));
-            const int useful = (ub[b] + per_wg[b] - 1) / per_wg[b];
+            const int useful = (ub[b] + plan_units_per_block(b) - 1) / plan_units_per_block(b);
             nb = std::min(nb, std::max(useful, 1));
-            nb = (nb + 7) & ~7;
         }
         boff[b + 1] = boff[b] + nb;
     }
@@ -211,6 +239,127 @@ struct Job {
     long long nnz = 0;
 };
 
+// Host loop: k_assign + k_detect per round with a host-computed partition; the queue
+// sizes are read back every few rounds (2, 4, 8, ... up to sync_every).  Rounds
+// launched past the end find empty queues and do nothing.
+int drive_loop(Workspace* w, Job& J, RoundArgs& a, int ub[NB], int budget, KTimer& T) {
+    hipStream_t st = w->stream;
+    int par = 1;             // parity of the worklist holding W of the next round
+    long long launched = 1;
+    int k = 2;
+    a.dev_plan = 0;
+    for (;;) {
+        long long tot = 0;
+        for (int b = 0; b < NB; ++b) tot += ub[b];
+        if (tot == 0) break;
+        make_plan(ub, budget, a.boff);
+        const int grid = a.boff[NB];
+        for (int i = 0; i < k; ++i) {
+            a.par_in = par;
+            a.par_out = par ^ 1;
+            a.wl_in = w->wl[par];
+            a.wl_out = w->wl[par ^ 1];
+            T.run(1, [&] { k_assign<<<grid, WG, 0, st>>>(a); });
+            T.run(2, [&] { k_detect<<<grid, WG, 0, st>>>(a); });
+            par ^= 1;
+            ++launched;
+        }
+        HIP_TRY(hipGetLastError());
+        int rc = read_ctl(w);
+        if (rc) return rc;
+        if (w->ctl_h->err) return CSRCOLOR_EHIP;
+        long long left = 0;
+        for (int b = 0; b < NB; ++b) left += (ub[b] = w->ctl_h->cnt[par][b]);
+        ub[BSPLIT] = w->ctl_h->ccnt[par];
+        if (left > 0 && launched > (long long)J.n + 2) return CSRCOLOR_ELIMIT;   // rounds <= n
+        k = std::min(k * 2, J.opt.sync_every);
+    }
+    return CSRCOLOR_OK;
+}
+
+// Persistent mode: one cooperative launch runs every remaining round; the grid is the
+// co-resident block count (capped by blocks_per_cu per CU).
+int drive_persistent(Workspace* w, Job& J, RoundArgs& a, int budget, KTimer& T) {
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_persistent, WG, 0));
+    const int cus = num_cus(w->device);
+    const int grid = std::min(std::max(per_cu, 1) * cus, budget);
+    a.dev_plan = 1;
+    a.par_in = 1;
+    a.par_out = 0;
+    a.wl_in = w->wl[1];
+    a.wl_out = w->wl[0];
+    a.round = 1;
+    int maxr = J.n + 2;
+    void* args[] = {&a, &maxr};
+    hipError_t e = hipSuccess;
+    T.run(1, [&] {
+        e = hipLaunchCooperativeKernel((const void*)k_persistent, dim3(grid), dim3(WG), args, 0, w->stream);
+    });
+    HIP_TRY(e);
+    int rc = read_ctl(w);
+    if (rc) return rc;
+    if (w->ctl_h->err) return CSRCOLOR_EHIP;
+    if (!w->ctl_h->pdone) return CSRCOLOR_ELIMIT;
+    return CSRCOLOR_OK;
+}
+
+// Graph mode: two rounds (parity 1 -> 0 -> 1) with device-side partitions are captured
+// once into a hipGraph on a private stream and replayed; the queue sizes are read
+// back every few replays.  The capture is reused while the kernel arguments stay the
+// same (same arrays, sizes and options).
+int drive_graph(Workspace* w, Job& J, RoundArgs& a, int budget) {
+    a.dev_plan = 1;
+    if (!w->gstream) {
+        HIP_TRY(hipStreamCreateWithFlags(&w->gstream, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&w->gev, hipEventDisableTiming));
+    }
+    const bool reuse = w->gexec && w->gbudget == budget && memcmp(&w->gargs, &a, sizeof(a)) == 0;
+    if (!reuse) {
+        if (w->gexec) (void)hipGraphExecDestroy(w->gexec);
+        w->gexec = nullptr;
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(w->gstream, hipStreamCaptureModeThreadLocal));
+        RoundArgs r = a;
+        for (int par = 1, i = 0; i < 2; ++i, par ^= 1) {
+            r.par_in = par;
+            r.par_out = par ^ 1;
+            r.wl_in = w->wl[par];
+            r.wl_out = w->wl[par ^ 1];
+            k_assign<<<budget, WG, 0, w->gstream>>>(r);
+            k_detect<<<budget, WG, 0, w->gstream>>>(r);
+        }
+        hipError_t ce = hipStreamEndCapture(w->gstream, &g);
+        if (ce != hipSuccess) return CSRCOLOR_EHIP;
+        ce = hipGraphInstantiate(&w->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ce != hipSuccess) {
+            w->gexec = nullptr;
+            return CSRCOLOR_EHIP;
+        }
+        w->gargs = a;
+        w->gbudget = budget;
+    }
+    // the private stream waits for setup and round 1 on the caller's stream
+    HIP_TRY(hipEventRecord(w->gev, w->stream));
+    HIP_TRY(hipStreamWaitEvent(w->gstream, w->gev, 0));
+    long long launched = 1;
+    int k = 1;
+    for (;;) {
+        for (int i = 0; i < k; ++i) HIP_TRY(hipGraphLaunch(w->gexec, w->gstream));
+        launched += 2 * k;
+        HIP_TRY(hipMemcpyAsync(w->ctl_h, w->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, w->gstream));
+        HIP_TRY(hipStreamSynchronize(w->gstream));
+        if (w->ctl_h->err) return CSRCOLOR_EHIP;
+        long long left = 0;
+        for (int b = 0; b < NB; ++b) left += w->ctl_h->cnt[1][b];
+        if (left == 0) break;
+        if (launched > (long long)J.n + 2) return CSRCOLOR_ELIMIT;
+        k = std::min(k * 2, std::max(1, J.opt.sync_every / 2));
+    }
+    return CSRCOLOR_OK;
+}
+
 int run_job(Workspace* w, Job& J, const long long* voff, int G) {
     const int n = J.n;
     hipStream_t st = w->stream;
@@ -222,14 +371,13 @@ int run_job(Workspace* w, Job& J, const long long* voff, int G) {
 
     KTimer T(w, J.stats && J.stats->time_kernels);
     T.run(0, [&] { k_init<<<1, WG, 0, st>>>(w->ctl); });
-    const int vblocks = (int)std::min<long long>(((long long)n + WG - 1) / WG, (long long)cus * 16);
+    const int vblocks = (int)std::min<long long>(((long long)n + WG - 1) / WG, (long long)cus * 4);
     T.run(0, [&] {
-        k_validate_rows<<<std::max(vblocks, 1), WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl, twave);
+        k_validate_rows<<<std::max(vblocks, 1), WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl, twave,
+                                                             J.opt.tsplit);
     });
-    HIP_TRY(hipGetLastError());
-    if ((rc = read_ctl(w))) return rc;
-    if (w->ctl_h->err) return CSRCOLOR_EBADCSR;
-    T.run(0, [&] { k_validate_arcs<<<cus * 16, WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl); });
+    // the arc pass skips itself when the row pass found an error, so one read-back covers both
+    T.run(0, [&] { k_validate_arcs<<<cus * 4, WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl); });
     if (voff) k_validate_batch<<<std::min(G, cus * 16), WG, 0, st>>>(G, n, voff, J.rowptr, J.colidx, w->ctl);
     HIP_TRY(hipGetLastError());
     if ((rc = read_ctl(w))) return rc;
@@ -252,10 +400,25 @@ int run_job(Workspace* w, Job& J, const long long* voff, int G) {
         seg.s[b + 1] = seg.s[b] + hist[b];
     }
 
+    // split-row scratch: cstart[2] (hubs), owner[2] (chunks), hub bitmaps, done counters, lost flags
+    const int nhub = hist[BSPLIT];
+    const int nchunk = w->ctl_h->hchunks;
+    const size_t split_ints = 2 * (size_t)nhub + 2 * (size_t)nchunk + (size_t)nhub * (HW + 2);
+    if ((rc = ensure_split(w, split_ints))) return rc;
+    int* cstart0 = w->split;
+    int* cstart1 = cstart0 + nhub;
+    int* owner0 = cstart1 + nhub;
+    int* owner1 = owner0 + nchunk;
+    int* hubflags = owner1 + nchunk;   // HW bitmap words + done + lost per hub
+    if (nhub > 0) {
+        const int cnt = nhub * (HW + 2);
+        k_fill<<<std::min((cnt + WG - 1) / WG, cus * 4), WG, 0, st>>>(hubflags, cnt, 0);
+    }
+
     const int r1blocks = (int)(((long long)n + 4 * WG - 1) / (4 * WG));
     T.run(0, [&] {
         k_round1<<<r1blocks, WG, 0, st>>>(n, J.rowptr, J.colidx, w->X, J.colors_out, w->wl[1], w->ctl,
-                                          J.sorted, twave, seg);
+                                          J.sorted, twave, J.opt.tsplit, seg, cstart1, owner1);
     });
     HIP_TRY(hipGetLastError());
 
@@ -269,6 +432,17 @@ int run_job(Workspace* w, Job& J, const long long* voff, int G) {
     a.ctl = w->ctl;
     a.twave = twave;
     a.sorted = J.sorted;
+    a.nnz = w->ctl_h->nnz;
+    a.lane_mode_assign = J.opt.lane_assign;
+    a.lane_mode_detect = J.opt.lane_detect;
+    a.tsplit = J.opt.tsplit;
+    a.cstart[0] = cstart0;
+    a.cstart[1] = cstart1;
+    a.owner[0] = owner0;
+    a.owner[1] = owner1;
+    a.hubbm = reinterpret_cast<unsigned*>(hubflags);
+    a.hubdone = hubflags + (size_t)nhub * HW;
+    a.hublost = a.hubdone + nhub;
     a.st_cap = st_cap;
     a.st_wsize = st_cap ? w->st_wsize : nullptr;
     a.st_arcs = st_cap ? w->st_arcs : nullptr;
@@ -278,37 +452,18 @@ int run_job(Workspace* w, Job& J, const long long* voff, int G) {
         HIP_TRY(hipMemsetAsync(w->st_arcs, 0, st_cap * sizeof(long long), st));
     }
 
-    int ub[NB];
-    for (int b = 0; b < NB; ++b) ub[b] = hist[b];
-    int par = 1;             // parity of the worklist holding W of the next round
-    int round = 1;           // 0-based index of the next round
-    int k = 2;
     const int budget = cus * J.opt.blocks_per_cu;
-    for (;;) {
-        long long tot = 0;
-        for (int b = 0; b < NB; ++b) tot += ub[b];
-        if (tot == 0) break;
-        make_plan(ub, budget, a.boff);
-        const int grid = a.boff[NB];
-        for (int i = 0; i < k; ++i) {
-            a.par_in = par;
-            a.par_out = par ^ 1;
-            a.wl_in = w->wl[par];
-            a.wl_out = w->wl[par ^ 1];
-            a.round = round;
-            T.run(1, [&] { k_assign<<<grid, WG, 0, st>>>(a); });
-            T.run(2, [&] { k_detect<<<grid, WG, 0, st>>>(a); });
-            par ^= 1;
-            ++round;
-        }
-        HIP_TRY(hipGetLastError());
-        if ((rc = read_ctl(w))) return rc;
-        if (w->ctl_h->err) return CSRCOLOR_EHIP;
-        long long left = 0;
-        for (int b = 0; b < NB; ++b) left += (ub[b] = w->ctl_h->cnt[par][b]);
-        if (left > 0 && round > n + 2) return CSRCOLOR_ELIMIT;   // rounds <= n for valid input
-        k = std::min(k * 2, J.opt.sync_every);
+    if (J.opt.mode == CSRCOLOR_MODE_PERSISTENT) {
+        rc = drive_persistent(w, J, a, budget, T);
+    } else if (J.opt.mode == CSRCOLOR_MODE_GRAPH) {
+        rc = drive_graph(w, J, a, budget);
+    } else {
+        int ub[NB];
+        for (int b = 0; b < NB; ++b) ub[b] = hist[b];
+        ub[BSPLIT] = nchunk;
+        rc = drive_loop(w, J, a, ub, budget, T);
     }
+    if (rc) return rc;
     if ((rc = read_ctl(w))) return rc;
     // Vertex 0 has no lower neighbour, so it always settles in round 1 with colour 1
     // (round-1 winners do not touch the device maximum).
@@ -461,6 +616,8 @@ void csrcolor_release_workspace(void) {
         if (w->ctl_h) (void)hipHostFree(w->ctl_h);
         if (w->st_wsize) (void)hipFree(w->st_wsize);
         if (w->st_arcs) (void)hipFree(w->st_arcs);
+        if (w->gexec) (void)hipGraphExecDestroy(w->gexec);
+        w->gexec = nullptr;
         w->ctl = nullptr;
         w->ctl_h = nullptr;
         w->st_wsize = w->st_arcs = nullptr;

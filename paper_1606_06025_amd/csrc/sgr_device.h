@@ -19,19 +19,32 @@ namespace csrcolor {
 
 constexpr int WG = 256;               // threads per workgroup (4 wavefronts of 64)
 constexpr int WAVES = WG / 64;
-constexpr int NB = 5;                 // degree buckets
+constexpr int NB = 7;                 // degree buckets
 constexpr int FLAG = (int)0x80000000;
 constexpr int CMASK = 0x7fffffff;
 constexpr int WAVE_CAP = 512;         // per-wavefront loser buffer (LDS entries)
 constexpr int SUB = WAVES * WAVE_CAP; // worklist entries per LDS flush
 constexpr int OVW = 32;               // overflow bitmap words per wavefront (colours 65..1088)
+constexpr int TWAVE_MIN = 61;         // t_wave = 61 leaves the wavefront bucket empty
 constexpr int TWAVE_MAX = 1024;       // largest degree handled by one wavefront
+constexpr int TSPLIT_MIN = 1024;      // rows above t_split are split (t_split >= t_wave)
 constexpr int BMW = 1024;             // workgroup bitmap words (32768 colours per window)
+constexpr int AU = 2;                 // arc-loop unroll of the wavefront / workgroup buckets
 
-// Bucket b handles degrees (lo_b, hi_b]: 0:(0,8] 1:(8,16] 2:(16,32] 3:(32,t_wave] 4:(t_wave,inf)
-__host__ __device__ inline int bucket_of(int deg, int twave) {
-    return deg <= 8 ? 0 : deg <= 16 ? 1 : deg <= 32 ? 2 : deg <= twave ? 3 : 4;
+// Degree buckets.  Buckets 0..3 are "tile" buckets: L = 2, 4, 8, 16 lanes per vertex,
+// each lane reading one aligned 16-byte quad of the row, so a row of degree
+// <= 4L - 3 is covered whatever its alignment: degrees 1-5, 6-13, 14-29, 30-61.
+// Bucket 4: one wavefront per vertex (62 .. t_wave); bucket 5: one workgroup per
+// vertex (t_wave .. t_split); bucket 6: rows split into SPLIT_CH-arc chunks, one
+// workgroup per chunk.  Degree-0 vertices settle in round 1 and are never queued.
+constexpr int NTILE = 4;
+constexpr int BSPLIT = 6;
+constexpr int SPLIT_CH = 2048;        // arcs per chunk of a split row
+constexpr int HW = 32;                // words of a split row's colour bitmap (colours 1..1024)
+__host__ __device__ inline int bucket_of(int deg, int twave, int tsplit) {
+    return deg <= 5 ? 0 : deg <= 13 ? 1 : deg <= 29 ? 2 : deg <= 61 ? 3 : deg <= twave ? 4 : deg <= tsplit ? 5 : 6;
 }
+__host__ __device__ inline int split_chunks(int deg) { return (deg + SPLIT_CH - 1) / SPLIT_CH; }
 
 // Device-resident control block.
 struct Ctl {
@@ -45,7 +58,14 @@ struct Ctl {
     int maxdeg;
     int rounds;         // number of non-empty rounds so far
     int nnz;            // rowptr[n]
-    int pad;
+    int hchunks;        // chunks over all split-bucket vertices
+    int ccnt[2];        // chunks queued in the split bucket, by round parity
+    int pdone;          // persistent mode: set when a round found every queue empty
+    int pad[4];
+    // device-wide barrier of the persistent mode, each counter on its own 128-byte line
+    int bar[8][32];
+    int bar_top[32];
+    int bar_gen[32];
 };
 
 struct Seg {
@@ -65,7 +85,19 @@ struct RoundArgs {
     int par_out;
     int twave;
     int sorted;         // 1: every row ascending -> conflict scans stop at the first w >= v
-    int round;          // 0-based round index (round 0 is the round-1 shortcut)
+    int round;          // persistent mode: 0-based index of the first round it runs
+    int nnz;            // rowptr[n], bounds the 16-byte row reads
+    int lane_mode_assign;  // bit b: tile bucket b runs FirstFit lane-per-vertex
+    int lane_mode_detect;  // bit b: tile bucket b runs the conflict test lane-per-vertex
+    int tsplit;            // largest degree handled without splitting the row
+    int dev_plan;          // 1: every block derives the bucket partition from the device queue sizes
+    // split bucket: per queued hub its first chunk; per chunk the hub's queue entry;
+    // per queue entry a colour bitmap, a finished-chunk counter and a lost flag
+    int* cstart[2];
+    int* owner[2];
+    unsigned* hubbm;
+    int* hubdone;
+    int* hublost;
     int st_cap;
     long long* st_wsize;
     long long* st_arcs;
@@ -135,6 +167,20 @@ __device__ __forceinline__ int block_min(int x, int* s) {
     int r = s[0];
 #pragma unroll
     for (int k = 1; k < WAVES; ++k) r = min(r, s[k]);
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int block_sum(int x, int* s) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    const int wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (__lane_id() == 0) s[wv] = x;
+    __syncthreads();
+    int r = 0;
+#pragma unroll
+    for (int k = 0; k < WAVES; ++k) r += s[k];
     __syncthreads();
     return r;
 }

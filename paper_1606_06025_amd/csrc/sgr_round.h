@@ -1,0 +1,905 @@
+// Round kernels: FirstFit (k_assign) and conflict test + clearing + compaction
+// (k_detect), one launch each per round, every degree bucket in the same grid.
+//
+// Cost model that shapes them: on gfx950 a wave64 vector-memory instruction costs
+// the compute unit's address unit about the same whatever its lanes do, so the
+// kernels minimise VMEM instructions per arc:
+//   * per-vertex metadata (worklist entry, rowptr pair, own colour) is loaded once,
+//     one lane per vertex, and handed to the lanes that need it by cross-lane moves;
+//   * row entries are read as aligned 16-byte quads (four arcs per lane per load);
+//   * one neighbour-colour gather per arc is the only per-arc instruction left.
+#pragma once
+
+#include "sgr_device.h"
+
+namespace csrcolor {
+
+struct RoundLds {
+    union {
+        int lbuf[WAVES * WAVE_CAP];   // detect: per-wavefront loser buffers
+        unsigned ovf[WAVES * OVW];    // assign, wavefront bucket: overflow colour bitmaps
+        unsigned bm[BMW];             // assign, workgroup bucket: colour window bitmap
+    };
+    int res[WAVES * 64];              // per-wavefront staging of per-vertex results
+    int wcnt[WAVES];
+    int wbase[WAVES];
+    int red[WAVES];
+    long long red64[WAVES];
+    int sh[4];
+};
+
+// Bucket of block `bid` under the partition boff, its index j inside the bucket and
+// the bucket's block count.  Blocks are dispatched round-robin over the 8 XCDs, so
+// the index is remapped to give every XCD one contiguous slice of the bucket's
+// worklist: neighbouring vertices then share an L2.
+__device__ __forceinline__ void block_bucket(const int* boff, int bid, int& b, int& j, int& nbk) {
+    b = 0;
+#pragma unroll
+    for (int k = 1; k < NB; ++k)
+        if (bid >= boff[k]) b = k;
+    const int s0 = boff[b];
+    nbk = boff[b + 1] - s0;
+    const int jj = bid - s0;
+    if (nbk >= 8) {
+        const int x = (s0 + jj) & 7;          // XCD of this block
+        int before = 0;                       // blocks of the range on XCDs < x
+        for (int y = 0; y < x; ++y) {
+            const int j0 = (y - s0) & 7;
+            before += nbk > j0 ? (nbk - j0 + 7) >> 3 : 0;
+        }
+        const int j0 = (x - s0) & 7;
+        j = before + ((jj - j0) >> 3);
+    } else {
+        j = jj;
+    }
+}
+
+// Per-bucket cost weights (arc work per queued unit) and the most blocks a bucket can
+// use per unit, shared by the host plan and the device plan.
+__host__ __device__ inline int plan_cost(int b) {
+    constexpr int c[NB] = {4, 10, 22, 45, 200, 1500, 2048};
+    return c[b];
+}
+__host__ __device__ inline int plan_units_per_block(int b) {
+    constexpr int u[NB] = {WG, WG, WG, WG, WAVES, 1, 1};
+    return u[b];
+}
+
+// Partition of nblk blocks over the buckets for queue sizes cnt[] (chunks for the
+// split bucket): one block per non-empty bucket, the rest in proportion to the
+// estimated arc work, capped by what a bucket can use.  Integer arithmetic only,
+// so every block that evaluates it gets the same answer.
+__device__ __forceinline__ void device_plan(const int* cnt, int nblk, int* boff) {
+    long long tot = 0;
+    int nz = 0;
+    for (int b = 0; b < NB; ++b) {
+        tot += (long long)cnt[b] * plan_cost(b);
+        nz += cnt[b] > 0;
+    }
+    const long long rem = nblk > nz ? nblk - nz : 0;
+    boff[0] = 0;
+    for (int b = 0; b < NB; ++b) {
+        int nb = 0;
+        if (cnt[b] > 0) {
+            const long long extra = tot > 0 ? rem * cnt[b] * plan_cost(b) / tot : 0;
+            const int useful = (cnt[b] + plan_units_per_block(b) - 1) / plan_units_per_block(b);
+            nb = (int)min((long long)useful, 1 + extra);
+        }
+        boff[b + 1] = boff[b] + nb;
+    }
+}
+
+// Quad q of row [beg, end): the q-th 16-byte aligned group of four colidx entries,
+// counted from the group holding colidx[beg] (alignment of the absolute address).
+// Entries outside the row come back as -1.  The 16-byte load is used only when the
+// whole group lies inside colidx[0, nnz); otherwise entries are read one by one.
+__device__ __forceinline__ void load_quad(const int* __restrict__ colidx, int nnz, int beg, int end, int q,
+                                          int w[4]) {
+    const int mis = (int)((reinterpret_cast<uintptr_t>(colidx) >> 2) & 3);
+    const int qs = ((beg + mis) & ~3) - mis + 4 * q;
+    if (qs >= end) {
+        w[0] = w[1] = w[2] = w[3] = -1;
+        return;
+    }
+    if (qs >= 0 && qs + 4 <= nnz) {
+        const int4 t = *reinterpret_cast<const int4*>(colidx + qs);
+        w[0] = t.x;
+        w[1] = t.y;
+        w[2] = t.z;
+        w[3] = t.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int e = qs + k;
+            w[k] = (e >= 0 && e < nnz) ? colidx[e] : -1;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (qs + k < beg || qs + k >= end) w[k] = -1;
+}
+
+// Contiguous slice [wlo, whi) of [lo, hi) for the calling wavefront.
+__device__ __forceinline__ void wave_slice(int lo, int hi, int& wlo, int& whi) {
+    const int wv = threadIdx.x >> 6;
+    const int q = (hi - lo + WAVES - 1) / WAVES;
+    wlo = min(hi, lo + wv * q);
+    whi = min(hi, wlo + q);
+}
+
+// ---------------------------------------------------------------------------
+// FirstFit (Sec. 3, FirstFit routine, with the bitset of Sec. 3.2): colour =
+// smallest c > 0 whose bit c-1 is clear in the OR of the neighbours' settled
+// colours (X > 0).  Written as FLAG | c.
+// ---------------------------------------------------------------------------
+
+// Tile buckets: a wavefront takes 64 worklist entries at a time; L lanes per vertex,
+// 64/L vertices per sub-step, L sub-steps.  Degree <= 4L-3 <= 61, so the mex is
+// <= 62 and a single 64-bit register mask is exact.
+template <int L>
+__device__ __forceinline__ void assign_tiles(const RoundArgs& a, const int* list, int lo, int hi,
+                                             int* res, long long& arcs) {
+    constexpr int V = 64 / L;
+    const int lane = __lane_id();
+    const int q = lane & (L - 1);
+    const int jsub = lane / L;
+    int wlo, whi;
+    wave_slice(lo, hi, wlo, whi);
+    for (int t0 = wlo; t0 < whi; t0 += 64) {
+        const int nv = min(64, whi - t0);
+        const int i = t0 + lane;
+        const int v_l = lane < nv ? list[i] : -1;
+        int beg_l = 0, end_l = 0;
+        if (v_l >= 0) {
+            beg_l = a.rowptr[v_l];
+            end_l = a.rowptr[v_l + 1];
+        }
+        const int nsub = (nv + V - 1) / V;
+        for (int sstep = 0; sstep < nsub; ++sstep) {
+            const int j = sstep * V + jsub;
+            const int beg = __shfl(beg_l, j, 64);
+            const int end = __shfl(end_l, j, 64);
+            int w[4];
+            load_quad(a.colidx, a.nnz, beg, end, q, w);
+            int x[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) x[k] = w[k] >= 0 ? a.X[w[k]] : 0;
+            unsigned long long m = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (x[k] > 0 && x[k] <= 64) m |= 1ull << (x[k] - 1);
+            m = group_or<L>(m);
+            if (q == 0) res[j] = __ffsll((long long)~m);
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (v_l >= 0) {
+            a.X[v_l] = FLAG | res[lane];
+            arcs += end_l - beg_l;
+            if (end_l - beg_l > 4 * L - 3) atomicOr(&a.ctl->err, 8);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Lane-per-vertex FirstFit for the tile buckets (degree <= 61): every lane walks its
+// own row quad by quad; the mask stays in the lane, no cross-lane reduction.  On
+// meshes the k-th neighbours of consecutive vertices are consecutive, so the colour
+// gathers of a wavefront coalesce.
+__device__ __forceinline__ void assign_lanes(const RoundArgs& a, const int* list, int lo, int hi,
+                                             long long& arcs) {
+    const int lane = __lane_id();
+    int wlo, whi;
+    wave_slice(lo, hi, wlo, whi);
+    for (int t0 = wlo; t0 < whi; t0 += 64) {
+        const int nv = min(64, whi - t0);
+        const int v_l = lane < nv ? list[t0 + lane] : -1;
+        int beg = 0, end = 0;
+        if (v_l >= 0) {
+            beg = a.rowptr[v_l];
+            end = a.rowptr[v_l + 1];
+        }
+        const int mis = (int)((reinterpret_cast<uintptr_t>(a.colidx) >> 2) & 3);
+        const int nq = end > beg ? (((end - 1 + mis) >> 2) - ((beg + mis) >> 2) + 1) : 0;
+        unsigned long long m = 0;
+        for (int q = 0; q < nq; ++q) {
+            int w[4];
+            load_quad(a.colidx, a.nnz, beg, end, q, w);
+            int x[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) x[k] = w[k] >= 0 ? a.X[w[k]] : 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (x[k] > 0 && x[k] <= 64) m |= 1ull << (x[k] - 1);
+        }
+        if (v_l >= 0) {
+            a.X[v_l] = FLAG | __ffsll((long long)~m);
+            arcs += end - beg;
+            if (end - beg > 63) atomicOr(&a.ctl->err, 8);
+        }
+    }
+}
+
+// Wavefront bucket (62 .. t_wave <= 1024): metadata for 64 vertices at a time, then
+// the whole wavefront scans one row with 16-byte quads; colours 1..64 in a register
+// mask, 65..1088 in a per-wavefront LDS bitmap.
+__device__ __forceinline__ void assign_wave(const RoundArgs& a, const int* list, int lo, int hi,
+                                            unsigned* ovf, int* res, long long& arcs) {
+    const int lane = __lane_id();
+    const int wv = threadIdx.x >> 6;
+    unsigned* my = ovf + wv * OVW;
+    int wlo, whi;
+    wave_slice(lo, hi, wlo, whi);
+    for (int t0 = wlo; t0 < whi; t0 += 64) {
+        const int nv = min(64, whi - t0);
+        const int v_l = lane < nv ? list[t0 + lane] : -1;
+        int beg_l = 0, end_l = 0;
+        if (v_l >= 0) {
+            beg_l = a.rowptr[v_l];
+            end_l = a.rowptr[v_l + 1];
+        }
+        for (int j = 0; j < nv; ++j) {
+            const int beg = __builtin_amdgcn_readlane(beg_l, j);
+            const int end = __builtin_amdgcn_readlane(end_l, j);
+            if (lane < OVW) my[lane] = 0;
+            __builtin_amdgcn_wave_barrier();
+            unsigned long long m = 0;
+            const int nq = ((end - beg) + 3 + 3) / 4 + 1;     // quads that can overlap the row
+            for (int q0 = 0; q0 < nq; q0 += 64) {
+                int w[4];
+                load_quad(a.colidx, a.nnz, beg, end, q0 + lane, w);
+                int x[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) x[k] = w[k] >= 0 ? a.X[w[k]] : 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (x[k] > 0) {
+                        if (x[k] <= 64) {
+                            m |= 1ull << (x[k] - 1);
+                        } else {
+                            const int kk = x[k] - 65;
+                            if (kk < OVW * 32) atomicOr(&my[kk >> 5], 1u << (kk & 31));
+                        }
+                    }
+                }
+            }
+            m = group_or<64>(m);
+            __builtin_amdgcn_wave_barrier();
+            int c;
+            if (~m) {
+                c = __ffsll((long long)~m);
+            } else {
+                const unsigned word = lane < OVW ? my[lane] : 0xffffffffu;
+                const unsigned long long z = __ballot(word != 0xffffffffu);
+                if (z == 0) {
+                    if (lane == 0) atomicOr(&a.ctl->err, 8);
+                    c = 1;
+                } else {
+                    const int l = __ffsll((long long)z) - 1;
+                    const unsigned wl = __shfl(word, l, 64);
+                    c = 65 + 32 * l + __ffs(~wl) - 1;
+                }
+            }
+            if (lane == 0) res[j] = c;
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (v_l >= 0) {
+            a.X[v_l] = FLAG | res[lane];
+            arcs += end_l - beg_l;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Smallest colour > base0 absent from the settled neighbours of row [beg, end),
+// computed by the whole workgroup over LDS bitmap windows of 32768 colours (a
+// further window only if one is completely forbidden).  Every thread must call.
+__device__ __forceinline__ int wg_mex_window(const RoundArgs& a, int beg, int end, int base0, RoundLds& s) {
+    const int nq = ((end - beg) + 3 + 3) / 4 + 1;
+    int base = base0, c = 0;
+    for (;;) {
+        for (int k = threadIdx.x; k < BMW; k += WG) s.bm[k] = 0;
+        __syncthreads();
+        for (int q0 = 0; q0 < nq; q0 += WG) {
+            int w[4];
+            load_quad(a.colidx, a.nnz, beg, end, q0 + (int)threadIdx.x, w);
+            int x[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) x[k] = w[k] >= 0 ? a.X[w[k]] : 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int kk = x[k] - 1 - base;
+                if (x[k] > 0 && (unsigned)kk < (unsigned)(BMW * 32)) atomicOr(&s.bm[kk >> 5], 1u << (kk & 31));
+            }
+        }
+        __syncthreads();
+        int best = 0x7fffffff;
+        for (int k = threadIdx.x; k < BMW; k += WG) {
+            const unsigned wd = s.bm[k];
+            if (wd != 0xffffffffu) best = min(best, k * 32 + __ffs(~wd) - 1);
+        }
+        best = block_min(best, s.red);
+        if (best != 0x7fffffff) {
+            c = base + best + 1;
+            break;
+        }
+        base += BMW * 32;
+    }
+    return c;
+}
+
+// Workgroup bucket (t_wave .. t_split): one workgroup per vertex, taken dynamically.
+__device__ __forceinline__ void assign_wg(const RoundArgs& a, const int* list, int cnt, RoundLds& s,
+                                          long long& arcs) {
+    for (;;) {
+        if (threadIdx.x == 0) s.sh[0] = atomicAdd(&a.ctl->dyn[0][5], 1);
+        __syncthreads();
+        const int i = s.sh[0];
+        __syncthreads();
+        if (i >= cnt) break;
+        const int v = list[i];
+        const int beg = a.rowptr[v], end = a.rowptr[v + 1];
+        const int c = wg_mex_window(a, beg, end, 0, s);
+        if (threadIdx.x == 0) {
+            a.X[v] = FLAG | c;
+            arcs += end - beg;
+        }
+    }
+}
+
+__device__ __forceinline__ unsigned ld_agent(const unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_agent(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Split bucket (> t_split): the row of a queued hub is cut into SPLIT_CH-arc chunks,
+// one workgroup per chunk (chunk t belongs to queue entry owner[t]).  Each chunk ORs
+// the colours it sees (1..32*HW) into the hub's bitmap with device atomics, then
+// counts itself done; the chunk that completes the count picks the colour.  If all
+// colours 1..32*HW are forbidden it rescans the whole row for higher ones.
+__device__ __forceinline__ void assign_split(const RoundArgs& a, const int* list, int nchunks, int j, int nbk,
+                                             RoundLds& s, long long& arcs) {
+    const int* cstart = a.cstart[a.par_in];
+    const int* owner = a.owner[a.par_in];
+    const int tid = threadIdx.x;
+    for (int t = j; t < nchunks; t += nbk) {
+        const int p = owner[t];
+        const int v = list[p];
+        const int k = t - cstart[p];
+        const int rb = a.rowptr[v], re = a.rowptr[v + 1];
+        const int nch = split_chunks(re - rb);
+        const int beg = rb + k * SPLIT_CH, end = min(beg + SPLIT_CH, re);
+        if (tid < HW) s.bm[tid] = 0;
+        __syncthreads();
+        const int nq = ((end - beg) + 3 + 3) / 4 + 1;
+        for (int q0 = 0; q0 < nq; q0 += WG) {
+            int w[4];
+            load_quad(a.colidx, a.nnz, beg, end, q0 + tid, w);
+            int x[4];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) x[kk] = w[kk] >= 0 ? a.X[w[kk]] : 0;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int cb = x[kk] - 1;
+                if (x[kk] > 0 && cb < HW * 32) atomicOr(&s.bm[cb >> 5], 1u << (cb & 31));
+            }
+        }
+        __syncthreads();
+        if (tid < HW) {
+            const unsigned wd = s.bm[tid];
+            if (wd) atomicOr(&a.hubbm[p * HW + tid], wd);
+        }
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) s.sh[1] = atomicAdd(&a.hubdone[p], 1) == nch - 1;
+        __syncthreads();
+        if (s.sh[1]) {
+            __threadfence();
+            const unsigned wd = tid < HW ? ld_agent(&a.hubbm[p * HW + tid]) : 0xffffffffu;
+            int best = wd != 0xffffffffu ? tid * 32 + __ffs(~wd) - 1 : 0x7fffffff;
+            best = block_min(best, s.red);
+            const int c = best != 0x7fffffff ? best + 1 : wg_mex_window(a, rb, re, HW * 32, s);
+            if (tid < HW) a.hubbm[p * HW + tid] = 0;
+            if (tid == 0) {
+                a.hubdone[p] = 0;
+                a.X[v] = FLAG | c;
+                arcs += re - rb;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// One FirstFit phase for the block `bid` of a grid partitioned by boff.
+__device__ __forceinline__ void assign_phase(const RoundArgs& a, RoundLds& s, int bid, const int* boff) {
+    int b, j, nbk;
+    block_bucket(boff, bid, b, j, nbk);
+    if (bid == 0 && threadIdx.x == 0) {
+        for (int k = 0; k < NB; ++k) {
+            a.ctl->cnt[a.par_out][k] = 0;
+            a.ctl->dyn[1][k] = 0;
+        }
+        a.ctl->ccnt[a.par_out] = 0;
+    }
+    if (bid >= boff[NB]) return;
+    const int cnt = a.ctl->cnt[a.par_in][b];
+    const int* list = a.wl_in + a.seg[b];
+    const int lo = (int)((long long)j * cnt / nbk);
+    const int hi = (int)((long long)(j + 1) * cnt / nbk);
+    int* res = s.res + (threadIdx.x >> 6) * 64;
+    long long arcs = 0;
+    if (b < NTILE && (a.lane_mode_assign >> b & 1)) {
+        assign_lanes(a, list, lo, hi, arcs);
+    } else {
+        switch (b) {
+            case 0: assign_tiles<2>(a, list, lo, hi, res, arcs); break;
+            case 1: assign_tiles<4>(a, list, lo, hi, res, arcs); break;
+            case 2: assign_tiles<8>(a, list, lo, hi, res, arcs); break;
+            case 3: assign_tiles<16>(a, list, lo, hi, res, arcs); break;
+            case 4: assign_wave(a, list, lo, hi, s.ovf, res, arcs); break;
+            case 5: assign_wg(a, list, cnt, s, arcs); break;
+            default: assign_split(a, list, a.ctl->ccnt[a.par_in], j, nbk, s, arcs); break;
+        }
+    }
+    if (a.st_arcs) {
+        // 0-based index of this round: the rounds completed so far (stable during FirstFit)
+        const int ridx = ld_agent(&a.ctl->rounds);
+        const long long t = block_sum64(arcs, s.red64);
+        if (threadIdx.x == 0 && t && ridx < a.st_cap)
+            atomicAdd((unsigned long long*)&a.st_arcs[ridx], (unsigned long long)t);
+    }
+}
+
+// Queue sizes of the round that reads parity `par` (the split bucket counted in chunks).
+__device__ __forceinline__ void queue_sizes(const Ctl* ctl, int par, int* cnt) {
+    for (int b = 0; b < NB; ++b) cnt[b] = ctl->cnt[par][b];
+    cnt[BSPLIT] = ctl->ccnt[par];
+}
+
+__global__ __launch_bounds__(WG) void k_assign(RoundArgs a) {
+    __shared__ RoundLds s;
+    __shared__ int boff[NB + 1];
+    if (threadIdx.x == 0) {
+        if (a.dev_plan) {
+            int cnt[NB];
+            queue_sizes(a.ctl, a.par_in, cnt);
+            device_plan(cnt, gridDim.x, boff);
+        } else {
+            for (int k = 0; k <= NB; ++k) boff[k] = a.boff[k];
+        }
+    }
+    __syncthreads();
+    assign_phase(a, s, blockIdx.x, boff);
+}
+
+// ---------------------------------------------------------------------------
+// Conflict test (Sec. 3, ConflictResolve, requeue direction fixed to the higher
+// id) + colour clearing + worklist push by prefix sums (Sec. 3.1).  A vertex loses
+// iff some neighbour w < v holds the same tentative colour.  Winners write their
+// final colour and the 0-based output; a loser's X keeps the FLAG (uncoloured for
+// the next FirstFit) and its id goes to the next worklist.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void settle(const RoundArgs& a, int v, int cv, int& cmax) {
+    a.X[v] = cv;
+    a.out[v] = cv - 1;
+    cmax = max(cmax, cv);
+}
+
+// Writes the per-wavefront loser buffers to the global worklist with one atomic per
+// workgroup.  `wc` is the calling wavefront's count (uniform).  Buffers hold
+// ascending worklist positions and wavefronts own ascending slices, so each flush
+// is one run in worklist order.
+__device__ __forceinline__ void flush_losers(RoundLds& s, int wc, int* outl, int* cnt_out) {
+    const int lane = __lane_id();
+    const int wv = threadIdx.x >> 6;
+    if (lane == 0) s.wcnt[wv] = wc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < WAVES; ++w) tot += s.wcnt[w];
+        int base = tot ? atomicAdd(cnt_out, tot) : 0;
+        for (int w = 0; w < WAVES; ++w) {
+            s.wbase[w] = base;
+            base += s.wcnt[w];
+        }
+    }
+    __syncthreads();
+    const int* src = s.lbuf + wv * WAVE_CAP;
+    int* dst = outl + s.wbase[wv];
+    for (int k = lane; k < wc; k += 64) dst[k] = src[k];
+    __syncthreads();
+}
+
+// Appends the losers among this wavefront's 64 tile entries (one per lane) to the
+// wavefront buffer in lane order.
+__device__ __forceinline__ void push_losers(int v_l, bool lost_l, int* mybuf, int& wc) {
+    const unsigned long long lm = __ballot(v_l >= 0 && lost_l);
+    if (v_l >= 0 && lost_l) mybuf[wc + __popcll(lm & lanemask_lt())] = v_l;
+    wc += __popcll(lm);
+}
+
+template <int L>
+__device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list, int lo, int hi, RoundLds& s,
+                                             int* outl, int* cnt_out, int& cmax) {
+    constexpr int V = 64 / L;
+    const int lane = __lane_id();
+    const int wv = threadIdx.x >> 6;
+    const int q = lane & (L - 1);
+    const int jsub = lane / L;
+    const unsigned long long gmask = (L == 64) ? ~0ull : ((1ull << L) - 1ull);
+    const int gshift = lane & ~(L - 1);
+    int* mybuf = s.lbuf + wv * WAVE_CAP;
+    int* res = s.res + wv * 64;
+    for (int s0 = lo; s0 < hi; s0 += SUB) {
+        const int s1 = min(s0 + SUB, hi);
+        int wlo, whi;
+        wave_slice(s0, s1, wlo, whi);      // <= WAVE_CAP entries per wavefront
+        int wc = 0;
+        for (int t0 = wlo; t0 < whi; t0 += 64) {
+            const int nv = min(64, whi - t0);
+            const int v_l = lane < nv ? list[t0 + lane] : -1;
+            int beg_l = 0, end_l = 0, cv_l = 0;
+            if (v_l >= 0) {
+                beg_l = a.rowptr[v_l];
+                end_l = a.rowptr[v_l + 1];
+                cv_l = a.X[v_l] & CMASK;
+            }
+            const int nsub = (nv + V - 1) / V;
+            for (int sstep = 0; sstep < nsub; ++sstep) {
+                const int j = sstep * V + jsub;
+                const int v = __shfl(v_l, j, 64);
+                const int beg = __shfl(beg_l, j, 64);
+                const int end = __shfl(end_l, j, 64);
+                const int cv = __shfl(cv_l, j, 64);
+                int w[4];
+                load_quad(a.colidx, a.nnz, beg, end, q, w);
+                bool hit = false;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) hit |= w[k] >= 0 && w[k] < v && (a.X[w[k]] & CMASK) == cv;
+                const bool lost = ((__ballot(hit) >> gshift) & gmask) != 0;
+                if (q == 0) res[j] = lost;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const bool lost_l = res[lane] != 0;
+            __builtin_amdgcn_wave_barrier();
+            if (v_l >= 0 && !lost_l) settle(a, v_l, cv_l, cmax);
+            push_losers(v_l, lost_l, mybuf, wc);
+        }
+        flush_losers(s, wc, outl, cnt_out);
+    }
+}
+
+// Lane-per-vertex conflict test for the tile buckets: every lane walks the lower part
+// of its own row quad by quad and stops at its first conflict (or, for sorted rows,
+// at its first w >= v); the wavefront moves on when all its lanes have stopped.
+__device__ __forceinline__ void detect_lanes(const RoundArgs& a, const int* list, int lo, int hi, RoundLds& s,
+                                             int* outl, int* cnt_out, int& cmax) {
+    const int lane = __lane_id();
+    const int wv = threadIdx.x >> 6;
+    int* mybuf = s.lbuf + wv * WAVE_CAP;
+    const int mis = (int)((reinterpret_cast<uintptr_t>(a.colidx) >> 2) & 3);
+    for (int s0 = lo; s0 < hi; s0 += SUB) {
+        const int s1 = min(s0 + SUB, hi);
+        int wlo, whi;
+        wave_slice(s0, s1, wlo, whi);
+        int wc = 0;
+        for (int t0 = wlo; t0 < whi; t0 += 64) {
+            const int nv = min(64, whi - t0);
+            const int v_l = lane < nv ? list[t0 + lane] : -1;
+            int beg = 0, end = 0, cv = 0;
+            if (v_l >= 0) {
+                beg = a.rowptr[v_l];
+                end = a.rowptr[v_l + 1];
+                cv = a.X[v_l] & CMASK;
+            }
+            const int nq = end > beg ? (((end - 1 + mis) >> 2) - ((beg + mis) >> 2) + 1) : 0;
+            bool lost = false;
+            for (int q = 0; q < nq; ++q) {
+                int w[4];
+                load_quad(a.colidx, a.nnz, beg, end, q, w);
+                bool stop = false;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (w[k] >= 0) {
+                        if (w[k] < v_l) {
+                            if ((a.X[w[k]] & CMASK) == cv) lost = true;
+                        } else if (a.sorted) {
+                            stop = true;
+                        }
+                    }
+                }
+                if (lost || stop) break;
+            }
+            if (v_l >= 0 && !lost) settle(a, v_l, cv, cmax);
+            push_losers(v_l, lost, mybuf, wc);
+        }
+        flush_losers(s, wc, outl, cnt_out);
+    }
+}
+
+// Wavefront bucket: metadata for 64 vertices at a time, then the wavefront scans the
+// lower part of one row at a time (256 arcs per step; for sorted rows the scan stops
+// at the first w >= v, and at the first conflict in any case).
+__device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list, int lo, int hi, RoundLds& s,
+                                            int* outl, int* cnt_out, int& cmax) {
+    const int lane = __lane_id();
+    const int wv = threadIdx.x >> 6;
+    int* mybuf = s.lbuf + wv * WAVE_CAP;
+    for (int s0 = lo; s0 < hi; s0 += SUB) {
+        const int s1 = min(s0 + SUB, hi);
+        int wlo, whi;
+        wave_slice(s0, s1, wlo, whi);
+        int wc = 0;
+        for (int t0 = wlo; t0 < whi; t0 += 64) {
+            const int nv = min(64, whi - t0);
+            const int v_l = lane < nv ? list[t0 + lane] : -1;
+            int beg_l = 0, end_l = 0, cv_l = 0;
+            if (v_l >= 0) {
+                beg_l = a.rowptr[v_l];
+                end_l = a.rowptr[v_l + 1];
+                cv_l = a.X[v_l] & CMASK;
+            }
+            bool lost_l = false;
+            for (int j = 0; j < nv; ++j) {
+                const int v = __builtin_amdgcn_readlane(v_l, j);
+                const int beg = __builtin_amdgcn_readlane(beg_l, j);
+                const int end = __builtin_amdgcn_readlane(end_l, j);
+                const int cv = __builtin_amdgcn_readlane(cv_l, j);
+                const int nq = ((end - beg) + 3 + 3) / 4 + 1;
+                bool lost = false;
+                for (int q0 = 0; q0 < nq; q0 += 64) {
+                    int w[4];
+                    load_quad(a.colidx, a.nnz, beg, end, q0 + lane, w);
+                    bool hit = false, stop = false;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        hit |= w[k] >= 0 && w[k] < v && (a.X[w[k]] & CMASK) == cv;
+                        stop |= a.sorted && w[k] >= v;
+                    }
+                    if (__ballot(hit)) {
+                        lost = true;
+                        break;
+                    }
+                    if (__ballot(stop)) break;
+                }
+                if (lane == j) lost_l = lost;
+            }
+            if (v_l >= 0 && !lost_l) settle(a, v_l, cv_l, cmax);
+            push_losers(v_l, lost_l, mybuf, wc);
+        }
+        flush_losers(s, wc, outl, cnt_out);
+    }
+}
+
+__device__ __forceinline__ void detect_wg(const RoundArgs& a, const int* list, int cnt, RoundLds& s,
+                                          int* outl, int* cnt_out, int& cmax) {
+    for (;;) {
+        if (threadIdx.x == 0) s.sh[0] = atomicAdd(&a.ctl->dyn[1][5], 1);
+        __syncthreads();
+        const int i = s.sh[0];
+        __syncthreads();
+        if (i >= cnt) break;
+        const int v = list[i];
+        const int beg = a.rowptr[v], end = a.rowptr[v + 1];
+        const int cv = a.X[v] & CMASK;
+        const int nq = ((end - beg) + 3 + 3) / 4 + 1;
+        bool lost = false;
+        for (int q0 = 0; q0 < nq; q0 += WG) {
+            int w[4];
+            load_quad(a.colidx, a.nnz, beg, end, q0 + (int)threadIdx.x, w);
+            bool hit = false, stop = false;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                hit |= w[k] >= 0 && w[k] < v && (a.X[w[k]] & CMASK) == cv;
+                stop |= a.sorted && w[k] >= v;
+            }
+            const int anyhit = __syncthreads_or(hit);
+            const int anystop = __syncthreads_or(stop);
+            if (anyhit) {
+                lost = true;
+                break;
+            }
+            if (anystop) break;
+        }
+        if (threadIdx.x == 0) {
+            if (lost) {
+                const int p = atomicAdd(cnt_out, 1);
+                outl[p] = v;
+            } else {
+                settle(a, v, cv, cmax);
+            }
+        }
+    }
+}
+
+// Split bucket conflict test: each chunk tests its part of the row (skipped when a
+// sibling chunk already found a conflict, or when a sorted chunk starts at w >= v)
+// and ORs its verdict into the hub's lost flag; the chunk that completes the
+// finished-chunk count settles the hub or requeues it with a fresh chunk range.
+__device__ __forceinline__ void detect_split(const RoundArgs& a, const int* list, int nchunks, int j, int nbk,
+                                             RoundLds& s, int* outl, int* cnt_out, int& cmax) {
+    const int* cstart = a.cstart[a.par_in];
+    const int* owner = a.owner[a.par_in];
+    int* cstart_out = a.cstart[a.par_out];
+    int* owner_out = a.owner[a.par_out];
+    const int tid = threadIdx.x;
+    for (int t = j; t < nchunks; t += nbk) {
+        const int p = owner[t];
+        const int v = list[p];
+        const int k = t - cstart[p];
+        const int rb = a.rowptr[v], re = a.rowptr[v + 1];
+        const int nch = split_chunks(re - rb);
+        const int beg = rb + k * SPLIT_CH, end = min(beg + SPLIT_CH, re);
+        const int cv = a.X[v] & CMASK;
+        bool hit = false;
+        const bool skip = ld_agent(&a.hublost[p]) != 0 || (a.sorted && a.colidx[beg] >= v);
+        if (!skip) {
+            const int nq = ((end - beg) + 3 + 3) / 4 + 1;
+            for (int q0 = 0; q0 < nq; q0 += WG) {
+                int w[4];
+                load_quad(a.colidx, a.nnz, beg, end, q0 + tid, w);
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) hit |= w[kk] >= 0 && w[kk] < v && (a.X[w[kk]] & CMASK) == cv;
+            }
+        }
+        const int anyhit = __syncthreads_or(hit);
+        if (tid == 0 && anyhit) atomicOr(&a.hublost[p], 1);
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) s.sh[1] = atomicAdd(&a.hubdone[p], 1) == nch - 1;
+        __syncthreads();
+        if (s.sh[1]) {
+            if (tid == 0) {
+                __threadfence();
+                const bool lost = ld_agent(&a.hublost[p]) != 0;
+                a.hublost[p] = 0;
+                a.hubdone[p] = 0;
+                s.sh[2] = -1;
+                if (lost) {
+                    const int qn = atomicAdd(cnt_out, 1);
+                    const int cs = atomicAdd(&a.ctl->ccnt[a.par_out], nch);
+                    outl[qn] = v;
+                    cstart_out[qn] = cs;
+                    s.sh[2] = qn;
+                    s.sh[3] = cs;
+                } else {
+                    settle(a, v, cv, cmax);
+                }
+            }
+            __syncthreads();
+            if (s.sh[2] >= 0)
+                for (int i = tid; i < nch; i += WG) owner_out[s.sh[3] + i] = s.sh[2];
+        }
+        __syncthreads();
+    }
+}
+
+// One conflict-test phase for the block `bid` of a grid partitioned by boff.
+__device__ __forceinline__ void detect_phase(const RoundArgs& a, RoundLds& s, int bid, const int* boff, int& cmax) {
+    int b, j, nbk;
+    block_bucket(boff, bid, b, j, nbk);
+    if (bid == 0 && threadIdx.x == 0) {
+        int tot = 0;
+        for (int k = 0; k < NB; ++k) {
+            tot += a.ctl->cnt[a.par_in][k];
+            a.ctl->dyn[0][k] = 0;
+        }
+        if (tot > 0) {
+            const int ridx = a.ctl->rounds;
+            if (a.st_wsize && ridx < a.st_cap) a.st_wsize[ridx] = tot;
+            a.ctl->rounds = ridx + 1;
+        }
+    }
+    if (bid >= boff[NB]) return;
+    const int cnt = a.ctl->cnt[a.par_in][b];
+    const int* list = a.wl_in + a.seg[b];
+    int* outl = a.wl_out + a.seg[b];
+    int* cnt_out = &a.ctl->cnt[a.par_out][b];
+    const int lo = (int)((long long)j * cnt / nbk);
+    const int hi = (int)((long long)(j + 1) * cnt / nbk);
+    if (b < NTILE && (a.lane_mode_detect >> b & 1)) {
+        detect_lanes(a, list, lo, hi, s, outl, cnt_out, cmax);
+    } else {
+        switch (b) {
+            case 0: detect_tiles<2>(a, list, lo, hi, s, outl, cnt_out, cmax); break;
+            case 1: detect_tiles<4>(a, list, lo, hi, s, outl, cnt_out, cmax); break;
+            case 2: detect_tiles<8>(a, list, lo, hi, s, outl, cnt_out, cmax); break;
+            case 3: detect_tiles<16>(a, list, lo, hi, s, outl, cnt_out, cmax); break;
+            case 4: detect_wave(a, list, lo, hi, s, outl, cnt_out, cmax); break;
+            case 5: detect_wg(a, list, cnt, s, outl, cnt_out, cmax); break;
+            default: detect_split(a, list, a.ctl->ccnt[a.par_in], j, nbk, s, outl, cnt_out, cmax); break;
+        }
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_detect(RoundArgs a) {
+    __shared__ RoundLds s;
+    __shared__ int boff[NB + 1];
+    if (threadIdx.x == 0) {
+        if (a.dev_plan) {
+            int cnt[NB];
+            queue_sizes(a.ctl, a.par_in, cnt);
+            device_plan(cnt, gridDim.x, boff);
+        } else {
+            for (int k = 0; k <= NB; ++k) boff[k] = a.boff[k];
+        }
+    }
+    __syncthreads();
+    int cmax = 0;
+    detect_phase(a, s, blockIdx.x, boff, cmax);
+    cmax = block_max(cmax, s.red);
+    if (threadIdx.x == 0 && cmax > 0) atomicMax(&a.ctl->maxcolor, cmax);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent mode (the kernel fusion of Sec. 3.3): every round of a colouring in
+// one cooperative launch, FirstFit and the conflict test separated by device-wide
+// barriers.  The barrier is two-level: blocks first meet on a counter of their XCD
+// group (blockIdx mod 8), the last of each group meets the others on a top counter,
+// and the last overall advances the generation all blocks wait for.  Counters only
+// grow within a run, so no reset is needed between barriers.  The agent-scope fences
+// on both sides make the colours and worklists written by one XCD visible to the
+// others.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void grid_sync(Ctl* ctl, int& gen) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nblk = gridDim.x;
+        const int ngrp = nblk < 8 ? nblk : 8;
+        const int grp = blockIdx.x & 7;
+        const int gsize = (nblk - grp + 7) / 8;
+        const int target = gen + 1;
+        __threadfence();
+        const int old = atomicAdd(&ctl->bar[grp][0], 1);
+        if (old == gsize * target - 1) {
+            const int t = atomicAdd(&ctl->bar_top[0], 1);
+            if (t == ngrp * target - 1) __hip_atomic_store(&ctl->bar_gen[0], target, __ATOMIC_RELEASE,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+        }
+        while (__hip_atomic_load(&ctl->bar_gen[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target)
+            __builtin_amdgcn_s_sleep(1);
+        __threadfence();
+    }
+    gen += 1;
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(WG) void k_persistent(RoundArgs a, int max_rounds) {
+    __shared__ RoundLds s;
+    __shared__ int boff[NB + 1];
+    __shared__ int total;
+    int gen = 0;
+    int cmax = 0;
+    for (int r = a.round; r < max_rounds; ++r) {
+        if (threadIdx.x == 0) {
+            int cnt[NB];
+            for (int b = 0; b < NB; ++b) cnt[b] = ld_agent(&a.ctl->cnt[a.par_in][b]);
+            cnt[BSPLIT] = ld_agent(&a.ctl->ccnt[a.par_in]);
+            int t = 0;
+            for (int b = 0; b < NB; ++b) t += cnt[b];
+            total = t;
+            device_plan(cnt, gridDim.x, boff);
+        }
+        __syncthreads();
+        if (total == 0) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->pdone = 1;
+            break;
+        }
+        assign_phase(a, s, blockIdx.x, boff);
+        grid_sync(a.ctl, gen);
+        detect_phase(a, s, blockIdx.x, boff, cmax);
+        grid_sync(a.ctl, gen);
+        const int t = a.par_in;
+        a.par_in = a.par_out;
+        a.par_out = t;
+        const int* tl = a.wl_in;
+        a.wl_in = a.wl_out;
+        a.wl_out = const_cast<int*>(tl);
+    }
+    cmax = block_max(cmax, s.red);
+    if (threadIdx.x == 0 && cmax > 0) atomicMax(&a.ctl->maxcolor, cmax);
+}
+
+}  // namespace csrcolor

@@ -172,45 +172,73 @@ def stencil27_arcs(X: int, Y: int, Z: int) -> int:
 RMAT_DEFAULT = (0.57, 0.19, 0.19, 0.05)
 
 
+def _rmat_chunk(key: np.uint64, start: int, cnt: int, scale: int, nh: int,
+                t1: np.uint32, t2: np.uint32, t3: np.uint32) -> Tuple[np.ndarray, np.ndarray]:
+    """Endpoints of R-MAT samples start .. start+cnt-1 (uint32 ids).
+
+    Sample s uses draws s*nh + 1 .. s*nh + nh of the stream; each 64-bit draw gives two
+    32-bit level values (high half first).  Per level: value < t1 -> quadrant (0,0),
+    < t2 -> (0,1), < t3 -> (1,0), else (1,1); the quadrant appends one bit to the row
+    id and one to the column id."""
+    idx = np.arange(start, start + cnt, dtype=np.uint64) * _U64(nh)
+    u = np.zeros(cnt, dtype=np.uint32)
+    v = np.zeros(cnt, dtype=np.uint32)
+    level = 0
+    with np.errstate(over="ignore"):
+        for j in range(nh):
+            h = mix64((idx + _U64(j + 1)) * _GOLDEN + key)
+            for half in ((h >> _U64(32)).astype(np.uint32), h.astype(np.uint32)):
+                if level >= scale:
+                    break
+                a2 = half >= t2
+                bv = ((half >= t1) & ~a2) | (half >= t3)
+                u <<= np.uint32(1)
+                u |= a2
+                v <<= np.uint32(1)
+                v |= bv
+                level += 1
+    return u, v
+
+
 def rmat(scale: int, edge_factor: int, seed: int, abcd: Sequence[float] = RMAT_DEFAULT,
-         permute: bool = True, sub: int = 0, chunk: int = 1 << 23) -> CSR:
+         permute: bool = True, sub: int = 0, chunk: int = 1 << 22, threads: Optional[int] = None) -> CSR:
     """R-MAT graph (Sec. 4): 2^scale vertices, edge_factor * 2^scale edge samples.
 
     Each sample picks one of four quadrants per level with probabilities (a, b, c, d)
     (32-bit thresholds), which fixes one bit of the row and one of the column.  No
     noise is added.  With ``permute`` the vertex ids are relabelled by a seeded random
-    permutation.  The samples are symmetrised; self-loops and duplicates dropped."""
+    permutation.  The samples are symmetrised; self-loops and duplicates dropped.
+    Chunks of samples are drawn on a thread pool; the result does not depend on the
+    chunk size or the thread count (counter-based draws)."""
+    import concurrent.futures
+    import os
+    if scale > 30:
+        raise ValueError("scale must be <= 30 for int32 ids")
     n = 1 << scale
     m = edge_factor * n
     a, b, c, _d = abcd
-    t1 = _U64(min(int(a * 2 ** 32), 2 ** 32 - 1))
-    t2 = _U64(min(int((a + b) * 2 ** 32), 2 ** 32 - 1))
-    t3 = _U64(min(int((a + b + c) * 2 ** 32), 2 ** 32 - 1))
+    t1 = np.uint32(min(int(a * 2 ** 32), 2 ** 32 - 1))
+    t2 = np.uint32(min(int((a + b) * 2 ** 32), 2 ** 32 - 1))
+    t3 = np.uint32(min(int((a + b + c) * 2 ** 32), 2 ** 32 - 1))
     key = stream_key(seed, STREAM_RMAT_BITS, sub)
     nh = (scale + 1) // 2                      # two 32-bit level draws per uint64
-    us, vs = [], []
-    for start in range(0, m, chunk):
-        cnt = min(chunk, m - start)
-        u = np.zeros(cnt, dtype=np.int64)
-        v = np.zeros(cnt, dtype=np.int64)
-        level = 0
-        for j in range(nh):
-            # draw index layout: sample-major, nh draws per sample
-            idx = (np.arange(start, start + cnt, dtype=np.uint64) * _U64(nh) + _U64(j + 1))
-            with np.errstate(over="ignore"):
-                h = mix64(idx * _GOLDEN + key)
-            for half in (h >> _U64(32), h & _U64(0xFFFFFFFF)):
-                if level >= scale:
-                    break
-                bu = (half >= t2).astype(np.int64)
-                bv = ((half >= t1) & (half < t2) | (half >= t3)).astype(np.int64)
-                u = (u << 1) | bu
-                v = (v << 1) | bv
-                level += 1
-        us.append(u)
-        vs.append(v)
-    u = np.concatenate(us) if us else np.zeros(0, np.int64)
-    v = np.concatenate(vs) if vs else np.zeros(0, np.int64)
+    starts = list(range(0, m, chunk))
+    nthr = threads or min(16, os.cpu_count() or 1)
+    u = np.empty(m, dtype=np.int64)
+    v = np.empty(m, dtype=np.int64)
+
+    def work(st: int) -> None:
+        cnt = min(chunk, m - st)
+        cu, cv = _rmat_chunk(key, st, cnt, scale, nh, t1, t2, t3)
+        u[st:st + cnt] = cu
+        v[st:st + cnt] = cv
+
+    if nthr > 1 and len(starts) > 1:
+        with concurrent.futures.ThreadPoolExecutor(nthr) as ex:
+            list(ex.map(work, starts))
+    else:
+        for st in starts:
+            work(st)
     if permute:
         pk = draws(stream_key(seed, STREAM_RMAT_PERM, sub), 0, n)
         order = np.argsort(pk, kind="stable")

@@ -67,7 +67,7 @@ def test_empty_graph_is_host_only(lib):
 
 
 def test_struct_layouts_match_header():
-    # csrcolor_opts: 6 int32 + 10 reserved
+    # csrcolor_opts: 8 int32 + 8 reserved
     # csrcolor_stats: 4 int32, int64, 2 int32, 2 pointers, 3 double, 2 int32
     assert ctypes.sizeof(L.Opts) == 16 * 4
     assert ctypes.sizeof(L.Stats) == 4 * 4 + 8 + 2 * 4 + 2 * 8 + 3 * 8 + 2 * 4

@@ -120,9 +120,9 @@ def test_mixed_stencils(dev):
         _assert_parity(gg.stencil27(*dims), dev)
 
 
-@pytest.mark.parametrize("kw", [dict(t_wave=33), dict(t_wave=64), dict(t_wave=200),
+@pytest.mark.parametrize("kw", [dict(t_wave=61), dict(t_wave=64), dict(t_wave=200),
                                 dict(blocks_per_cu=1), dict(blocks_per_cu=3), dict(sync_every=1),
-                                dict(sync_every=5), dict(t_wave=40, blocks_per_cu=2, sync_every=3)])
+                                dict(sync_every=5), dict(t_wave=70, blocks_per_cu=2, sync_every=3)])
 def test_launch_options_do_not_change_result(dev, kw):
     import oracle
     g = gg.rmat(13, 16, 9)
@@ -218,3 +218,117 @@ def test_batched_rejects_cross_graph_arcs(dev):
     with pytest.raises(L.CsrColorError) as e:
         api.color_batched(voff, torch.from_numpy(g.rowptr).to(dev), torch.from_numpy(g.colidx).to(dev))
     assert e.value.status == L.EBADCSR
+
+
+def _degree_ladder(degs, seed=0):
+    """A graph with one hub per requested degree (hub joined to its own leaves) plus a
+    random sprinkle of extra edges, so rows of every bucket boundary occur at
+    assorted alignments."""
+    edges = []
+    nxt = len(degs)
+    for h, d in enumerate(degs):
+        for _ in range(d):
+            edges.append((h, nxt))
+            nxt += 1
+    n = nxt
+    h = len(degs)
+    # random edges among the leaves only, so every hub keeps exactly its degree
+    g0 = gg.random_small(n - h, 2.0 / max(n - h, 1), seed)
+    src = np.concatenate([np.array([e[0] for e in edges], np.int64),
+                          np.repeat(np.arange(n - h), np.diff(g0.rowptr)) + h])
+    dst = np.concatenate([np.array([e[1] for e in edges], np.int64), g0.colidx.astype(np.int64) + h])
+    return gg.csr_from_arcs(n, src, dst, symmetrize=True, name="ladder")
+
+
+def test_bucket_boundary_degrees(dev):
+    degs = [1, 2, 4, 5, 6, 7, 12, 13, 14, 15, 28, 29, 30, 31, 60, 61, 62, 63, 64, 65, 127, 128,
+            1023, 1024, 1025, 2000]
+    for seed in range(3):
+        _assert_parity(_degree_ladder(degs, seed), dev)
+
+
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_misaligned_colidx_view(dev, shift):
+    import oracle
+    from paper_1606_06025_amd import api
+    for g in [gg.erdos_renyi(3000, 40000, shift), _degree_ladder([5, 13, 29, 61, 300, 1500], shift)]:
+        ref = oracle.sgr(g.n, g.rowptr, g.colidx)
+        buf = torch.zeros(g.nnz + 8, dtype=torch.int32, device=dev)
+        buf[shift:shift + g.nnz] = torch.from_numpy(g.colidx).to(dev)
+        ci = buf[shift:shift + g.nnz]
+        assert ci.data_ptr() % 16 == 4 * shift
+        rp = torch.from_numpy(g.rowptr).to(dev)
+        colors, nc, st = api.color(rp, ci, stats=True)
+        assert (colors.cpu().numpy() == ref.colors).all()
+        assert nc == ref.ncolors and st.rounds == ref.rounds
+
+
+@pytest.mark.parametrize("n", [1030, 1500])
+def test_split_rows_beyond_hub_bitmap(dev, n):
+    """With t_split at its minimum every vertex of K_n (degree n-1 > 1024) is a split
+    row, and its colour exceeds the 1024 colours a hub bitmap covers."""
+    got, ref = _assert_parity(gg.complete(n), dev, t_split=1024, t_wave=61)
+    assert got.tolist() == list(range(n))
+
+
+def test_split_rows_ladder(dev):
+    degs = [2047, 2048, 2049, 3000, 4096, 4097, 9000, 20000]
+    for seed in range(2):
+        g = _degree_ladder(degs, seed)
+        _assert_parity(g, dev)
+        _assert_parity(g, dev, t_split=1024)
+
+
+def test_split_rmat(dev):
+    g = gg.rmat(16, 16, 5)
+    import oracle
+    ref = oracle.sgr(g.n, g.rowptr, g.colidx)
+    for kw in [dict(), dict(t_split=1024), dict(t_split=1 << 20), dict(t_wave=61, t_split=1024)]:
+        _assert_parity(g, dev, ref, **kw)
+
+
+def _golden(name):
+    import json
+    import os
+    p = os.path.join(os.path.dirname(__file__), "golden", f"{name}_s1.json")
+    if not os.path.exists(p):
+        pytest.skip(f"{p} not generated")
+    with open(p) as f:
+        return json.load(f)
+
+
+def _digest(a):
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=np.int32).tobytes()).hexdigest()
+
+
+def test_config_rmat23_full_against_stored_oracle(dev):
+    """R-MAT scale 23 at full size: the oracle takes minutes here, so its result was
+    stored (tests/golden/make_golden.py) as digests plus per-round statistics."""
+    gold = _golden("rmat23")
+    g = gg.config_rmat23(1)
+    assert _digest(g.rowptr) == gold["rowptr_sha256"] and _digest(g.colidx) == gold["colidx_sha256"]
+    got, nc, st = _run(g, dev)
+    assert nc == gold["ncolors"] and st.rounds == gold["rounds"]
+    assert st.wsize == gold["wsize"] and st.arcs == gold["arcs_ff"]
+    assert _digest(got) == gold["colors_sha256"]
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_drive_modes_match_oracle(dev, mode):
+    """Host loop (1), one persistent cooperative launch (2) and replayed hipGraph
+    rounds (3) give the oracle's colouring, round count and per-round statistics."""
+    graphs = [gg.erdos_renyi(20000, 160000, 3), gg.rmat(13, 16, 2), gg.stencil27(20, 17, 9),
+              gg.complete(70), gg.star(1500, [i for i in range(3001) if i != 1500]),
+              _degree_ladder([5, 13, 29, 61, 300, 1500, 2500, 9000], 1), gg.cycle(101), gg.edgeless(9)]
+    for g in graphs:
+        _assert_parity(g, dev, mode=mode)
+
+
+@pytest.mark.parametrize("mode", [2, 3])
+def test_drive_modes_repeat_and_shrink(dev, mode):
+    """Consecutive calls in one mode, the second on a smaller graph (graph mode must
+    not replay a capture made for other arguments)."""
+    for g in [gg.erdos_renyi(30000, 300000, 8), gg.erdos_renyi(30000, 300000, 8), gg.erdos_renyi(5000, 30000, 9),
+              gg.rmat(12, 8, 3)]:
+        _assert_parity(g, dev, mode=mode)
