@@ -45,11 +45,39 @@ def make_graph(workload: str, seed: int):
     raise SystemExit(f"unknown workload {workload}")
 
 
-def assign_bytes(wsize, arcs) -> int:
-    """Algorithmic bytes of every FirstFit launch (rounds 2..R): per worklist vertex
-    16 B (its id, the rowptr pair, the colour write) + per scanned arc 8 B (colidx
-    entry + the neighbour's colour)."""
+def assign_bytes(wsize, arcs, push: bool) -> int:
+    """Algorithmic bytes of all FirstFit launches (rounds 2..R).
+    Rescan variant: per worklist vertex 16 B (its id, the rowptr pair, the colour
+    write) + per scanned arc 8 B (colidx entry + the neighbour's colour).
+    Push variant: per worklist vertex 20 B (id, rowptr pair, one bitmap word, colour
+    write); no per-arc traffic."""
+    if push:
+        return sum(20 * int(w) for w in wsize[1:])
     return sum(16 * int(w) + 8 * int(a) for w, a in zip(wsize[1:], arcs[1:]))
+
+
+def detect_bytes(wsize, arcs_cr, pushed_arcs: int, push: bool) -> int:
+    """Algorithmic bytes of all conflict-test launches (rounds 2..R): per worklist
+    vertex 20 B (id, rowptr pair, own colour, colour/output write) + 8 B per examined
+    lower arc (colidx + colour) + 4 B per requeued vertex; in the push variant also
+    20 B per arc pushed by a winner (colidx, the neighbour's rowptr pair, the bitmap
+    word read and written)."""
+    w = [int(x) for x in wsize] + [0]
+    b = sum(20 * w[r] + 8 * int(arcs_cr[r]) + 4 * w[r + 1] for r in range(1, len(wsize)))
+    return b + (20 * pushed_arcs if push else 0)
+
+
+def oracle_stats(g, workload: str):
+    """Per-round statistics of the oracle (stored digests when available)."""
+    import oracle
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}_s1.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            gold = json.load(f)
+        if gold.get("nnz") == g.nnz and gold.get("n") == g.n:
+            return gold["wsize"], gold["arcs_cr"], gold["serial_ff_colors"]
+    res = oracle.sgr(g.n, g.rowptr, g.colidx)
+    return res.wsize.tolist(), res.arcs_cr.tolist(), oracle.serial_ff(g.n, g.rowptr, g.colidx)[1]
 
 
 def cpu_baseline(g, budget_s: float = 20.0):
@@ -68,6 +96,147 @@ def cpu_baseline(g, budget_s: float = 20.0):
                       f"{per:.2f} s each, single thread"}
 
 
+def bench_batched(args, dev) -> int:
+    """Batched workload: G graphs (half ER, half 27-point stencils) coloured in one
+    call on their block-diagonal union; compared with one call per graph."""
+    import torch
+    import numpy as np
+    from paper_1606_06025_amd import api, graphs as gg
+
+    log(f"generating batched set: {args.graphs} graphs (seed {args.seed})")
+    specs = gg.batch_specs(args.graphs, seed=args.seed)
+    parts = gg.build_graphs(specs)
+    b = gg.concat_graphs(parts)
+    log(f"G={b.G} n={b.n} nnz={b.nnz}")
+    voff = torch.from_numpy(b.voff).to(dev)
+    rp = torch.from_numpy(b.rowptr).to(dev)
+    ci = torch.from_numpy(b.colidx).to(dev)
+    out = torch.empty(b.n, dtype=torch.int32, device=dev)
+    tuned = dict(mode=args.mode, lane_assign=args.lane_assign, lane_detect=args.lane_detect,
+                 t_wave=args.t_wave, t_split=args.t_split, blocks_per_cu=args.blocks_per_cu,
+                 sync_every=args.sync_every, firstfit=args.firstfit)
+    if args.autotune:
+        from paper_1606_06025_amd import tune
+        tuned = tune.tune(rp, ci, voff=voff, log=log)
+        log(f"autotuned options: {tuned}")
+    opts = api.make_opts(**tuned) if any(tuned.values()) else None
+    for _ in range(args.warmup):
+        api.color_batched(voff, rp, ci, out=out, opts=opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, ncol = api.color_batched(voff, rp, ci, out=out, opts=opts)
+    torch.cuda.synchronize()
+    ms_batched = (time.perf_counter() - t0) * 1e3 / args.steps
+    colors_b = out.cpu().numpy()
+    ncol = ncol.cpu().numpy()
+    log(f"batched: {ms_batched:.2f} ms/step, {b.nnz / ms_batched / 1e6:.3f} G arcs/s")
+
+    # one graph per launch on the same GPU, same arrays (sub-ranges of the union's
+    # buffers would carry global ids, so each graph is uploaded on its own)
+    dev_parts = [(torch.from_numpy(p.rowptr).to(dev), torch.from_numpy(p.colidx).to(dev),
+                  torch.empty(p.n, dtype=torch.int32, device=dev)) for p in parts]
+    for (prp, pci, pout) in dev_parts[: min(8, len(dev_parts))]:
+        api.color(prp, pci, out=pout, opts=opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (prp, pci, pout) in dev_parts:
+        api.color(prp, pci, out=pout, opts=opts)
+    torch.cuda.synchronize()
+    ms_single = (time.perf_counter() - t0) * 1e3
+    same = all(np.array_equal(colors_b[b.voff[i]:b.voff[i + 1]], dev_parts[i][2].cpu().numpy())
+               and int(ncol[i]) == int(dev_parts[i][2].max().item()) + 1 for i in range(len(parts)))
+    log(f"one graph per launch: {ms_single:.2f} ms for all {len(parts)} graphs; identical colourings: {same}")
+    rec = {
+        "metric": "arcs/s per round-complete coloring (batched)",
+        "value": b.nnz / (ms_batched * 1e-3),
+        "unit": "arcs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_batched,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"batched_{b.G}_graphs", "graphs": b.G, "n": b.n, "nnz": b.nnz,
+                   "one_graph_per_launch_ms": ms_single,
+                   "one_graph_per_launch_arcs_per_s": b.nnz / (ms_single * 1e-3),
+                   "batched_speedup": ms_single / ms_batched,
+                   "identical_colourings": bool(same),
+                   **{k: v for k, v in tuned.items() if v}},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(rec), flush=True)
+    return 0 if same else 1
+
+
+def bench_serve(args, dev) -> int:
+    """Serving workload: a Poisson stream of R-MAT / ER requests through the
+    continuous-batching server.  First all requests at once (saturation throughput
+    and request rate), then the same requests at 50 % and 90 % of that rate."""
+    import numpy as np
+    import torch
+    from paper_1606_06025_amd import api, graphs as gg, serve
+
+    reqs = gg.serve_stream(args.requests, qps=1.0, seed=args.seed,
+                           rmat_scale=(10, args.max_scale), er_n=(1e3, args.max_er_n))
+    log(f"generating {len(reqs)} requests")
+    graphs = gg.build_graphs([r.spec for r in reqs])
+    total_arcs = sum(g.nnz for g in graphs)
+    log(f"requests: {len(graphs)}, total arcs {total_arcs}, largest {max(g.nnz for g in graphs)}")
+    pairs = [(g.rowptr, g.colidx) for g in graphs]
+    budget = int(args.hbm_budget_gb * (1 << 30))
+
+    def run(arrivals):
+        be = serve.HipBackend(nslots=args.slots)
+        with serve.ColoringServer(be, budget, max_batch=args.max_batch) as srv:
+            rr, wall = serve.replay(srv, pairs, arrivals)
+            peak = srv.peak_bytes
+        bad = [r for r in rr if r.error]
+        if bad:
+            raise RuntimeError(f"{len(bad)} requests failed: {bad[0].error}")
+        return rr, wall, peak
+
+    run([0.0] * min(4, len(pairs)))  # warm the workspaces on every slot
+    rr, wall, peak = run([0.0] * len(pairs))
+    sat_arcs = total_arcs / wall
+    sat_qps = len(pairs) / wall
+    log(f"saturation: {wall * 1e3:.1f} ms, {sat_arcs / 1e9:.3f} G arcs/s, {sat_qps:.1f} req/s")
+    unit_arrivals = np.array([r.arrival_s for r in reqs])   # Poisson at 1 req/s
+    loads = {}
+    for frac in (0.5, 0.9):
+        q = frac * sat_qps
+        rr_q, wall_q, _ = run(list(unit_arrivals / q))
+        s = serve.latency_summary(rr_q)
+        loads[f"{int(frac * 100)}pct"] = {"qps": q, "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"],
+                                          "arcs_per_s": total_arcs / wall_q}
+        log(f"load {frac:.0%} ({q:.1f} req/s): p50 {s['p50_ms']:.2f} ms, p99 {s['p99_ms']:.2f} ms")
+    # one graph per launch, back to back on one stream
+    dpairs = [(torch.from_numpy(rp).to(dev), torch.from_numpy(ci).to(dev)) for rp, ci in pairs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for rp, ci in dpairs:
+        api.color(rp, ci)
+    torch.cuda.synchronize()
+    single = time.perf_counter() - t0
+    rec = {
+        "metric": "arcs/s served (continuous batching) with p50/p99 latency",
+        "value": sat_arcs, "unit": "arcs/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"serve_{len(pairs)}_requests", "requests": len(pairs), "total_arcs": total_arcs,
+                   "slots": args.slots, "hbm_budget_gb": args.hbm_budget_gb, "peak_admitted_bytes": peak,
+                   "saturation_qps": sat_qps, "loads": loads,
+                   "one_graph_per_launch_arcs_per_s": total_arcs / single},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,13 +244,23 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="stencil128")
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--graphs", type=int, default=2048, help="batched workload: number of graphs")
+    ap.add_argument("--requests", type=int, default=96, help="serve workload: number of requests")
+    ap.add_argument("--slots", type=int, default=3, help="serve workload: concurrent stream slots")
+    ap.add_argument("--max-batch", type=int, default=16, help="serve workload: requests per batch")
+    ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="serve workload: admission budget")
+    ap.add_argument("--max-scale", type=int, default=20, help="serve workload: largest R-MAT scale")
+    ap.add_argument("--max-er-n", type=float, default=1e6, help="serve workload: largest ER size")
     ap.add_argument("--mode", type=int, default=0, help="csrcolor_mode (0 = library default)")
     ap.add_argument("--lane-assign", type=int, default=0, help="csrcolor_opts.lane_assign (0 = default)")
     ap.add_argument("--lane-detect", type=int, default=0, help="csrcolor_opts.lane_detect (0 = default)")
     ap.add_argument("--t-wave", type=int, default=0)
+    ap.add_argument("--t-split", type=int, default=0)
+    ap.add_argument("--firstfit", type=int, default=0, help="1 = rescan neighbours (as printed), 2 = push bitmaps")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--sync-every", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="pick launch options with paper_1606_06025_amd.tune")
     ap.add_argument("--no-kernel-timing", action="store_true")
     args = ap.parse_args()
 
@@ -100,6 +279,11 @@ def main() -> int:
     _lib.load()
     dev = torch.device("cuda:0")
 
+    if args.workload == "batched":
+        return bench_batched(args, dev)
+    if args.workload == "serve":
+        return bench_serve(args, dev)
+
     log(f"generating {args.workload} (seed {args.seed})")
     g = make_graph(args.workload, args.seed)
     log(f"n={g.n} nnz={g.nnz} maxdeg={g.max_degree()}")
@@ -107,7 +291,12 @@ def main() -> int:
     ci = torch.from_numpy(g.colidx).to(dev)
     out = torch.empty(g.n, dtype=torch.int32, device=dev)
     tuned = dict(mode=args.mode, lane_assign=args.lane_assign, lane_detect=args.lane_detect,
-                 t_wave=args.t_wave, blocks_per_cu=args.blocks_per_cu, sync_every=args.sync_every)
+                 t_wave=args.t_wave, t_split=args.t_split, blocks_per_cu=args.blocks_per_cu,
+                 sync_every=args.sync_every, firstfit=args.firstfit)
+    if args.autotune:
+        from paper_1606_06025_amd import tune
+        tuned = tune.tune(rp, ci, log=log)
+        log(f"autotuned options: {tuned}")
     opts = api.make_opts(**tuned) if any(tuned.values()) else None
 
     # warmup (also allocates the library workspace)
@@ -148,24 +337,37 @@ def main() -> int:
             tot_s += s2.ms_setup
             na += s2.n_assign
             nd += s2.n_detect
-        ab = assign_bytes(st.wsize, st.arcs)
-        launches_per_step = na / args.steps
-        avg_launch_ms = tot_a / na if na else float("nan")
-        bytes_per_launch = ab / launches_per_step if launches_per_step else 0.0
-        achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if na else 0.0
-        roofline = {"bound": "hbm", "kernel": "k_assign (FirstFit)", "achieved": round(achieved, 1),
+        push = args.firstfit != 1
+        ows, ocr, ff_colors = oracle_stats(g, args.workload)
+        if [int(x) for x in ows] != st.wsize:
+            raise SystemExit("worklist sizes differ from the oracle's")
+        # arcs pushed by winners of rounds >= 2 (every vertex pushes its row once; the
+        # round-1 winners' rows are pushed by the round-1 kernel)
+        pushed = int(st.arcs[1]) if len(st.arcs) > 1 else 0
+        kb = {"k_assign": (assign_bytes(st.wsize, st.arcs, push), tot_a, na),
+              "k_detect": (detect_bytes(st.wsize, ocr, pushed, push), tot_d, nd)}
+        dom = max(kb, key=lambda k: kb[k][1])
+        byts, tms, nl = kb[dom]
+        launches_per_step = nl / args.steps
+        avg_launch_ms = tms / nl if nl else float("nan")
+        bytes_per_launch = byts / launches_per_step if launches_per_step else 0.0
+        achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if nl else 0.0
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": None, "bytes_per_launch": round(bytes_per_launch),
                     "avg_launch_us": round(avg_launch_ms * 1e3, 2),
-                    "launches_per_step": launches_per_step}
+                    "launches_per_step": launches_per_step,
+                    "other_kernels_gbs": {k: round(v[0] * args.steps / (v[1] * 1e-3) / 1e9, 1)
+                                          for k, v in kb.items() if k != dom and v[1] > 0}}
         kern = {"ms_assign_per_step": round(tot_a / args.steps, 3),
                 "ms_detect_per_step": round(tot_d / args.steps, 3),
                 "ms_setup_per_step": round(tot_s / args.steps, 3)}
         log(f"kernel time per step: assign {kern['ms_assign_per_step']} ms, detect "
             f"{kern['ms_detect_per_step']} ms, setup {kern['ms_setup_per_step']} ms")
 
-    import oracle
-    ff_colors = oracle.serial_ff(g.n, g.rowptr, g.colidx)[1]
+    if roofline is None:
+        import oracle
+        ff_colors = oracle.serial_ff(g.n, g.rowptr, g.colidx)[1]
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")

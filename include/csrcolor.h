@@ -68,8 +68,15 @@ typedef enum {
     CSRCOLOR_MODE_GRAPH = 3        /* blocks of rounds captured once in a hipGraph and replayed */
 } csrcolor_mode;
 
+/* Which endpoint of a same-colour adjacent pair of worklist vertices is requeued. */
+typedef enum {
+    CSRCOLOR_RULE_ID = 0,      /* the higher vertex id (default) */
+    CSRCOLOR_RULE_DEGREE = 1   /* the smaller degree, the higher id on equal degree: the heuristic
+                                  conflict resolve of Sec. 3.2 (fewer rounds on skewed graphs) */
+} csrcolor_rule;
+
 /* Tuning and checking options.  Zero-initialise and set what you need; every
- * zero field means "library default".  No field changes the colouring. */
+ * zero field means "library default".  Only `rule` changes the colouring. */
 typedef struct {
     int32_t mode;           /* csrcolor_mode */
     int32_t validate;       /* 1: also check symmetry (sorted rows only; costs one search per arc) */
@@ -80,7 +87,11 @@ typedef struct {
     int32_t lane_assign;    /* bit b (b < 4): low-degree bucket b runs FirstFit one lane per vertex;
                                0 = default; -1 = none (all use 2/4/8/16 lanes per vertex) */
     int32_t lane_detect;    /* the same for the conflict test */
-    int32_t reserved[8];
+    int32_t firstfit;       /* 0: default (push); 1: rescan: every FirstFit gathers all neighbour colours
+                               (as printed in the paper); 2: push: a vertex that settles marks its colour in
+                               a per-neighbour bitmap and FirstFit reads that bitmap (same colouring) */
+    int32_t rule;           /* conflict rule, csrcolor_rule; CHANGES the colouring (each rule is exact) */
+    int32_t reserved[6];
 } csrcolor_opts;
 
 /* Optional run statistics (HOST struct).  Set `cap`, `time_kernels` and the array
@@ -141,6 +152,26 @@ int csrcolor_color_batched(int32_t G, int32_t n_total, const int64_t *voff,
                            const int32_t *rowptr, const int32_t *colidx,
                            int32_t *colors_out, int32_t *ncolors_out,
                            const csrcolor_opts *opts, hipStream_t stream);
+
+/* Colour G separate graphs in one run (request batching).  The library copies the
+ * graphs, ids shifted, into one block-diagonal CSR it owns, colours that union as in
+ * csrcolor_color_batched (every graph gets exactly its stand-alone colouring) and
+ * copies each graph's colours to its own output.
+ *   G            number of graphs (>= 0)
+ *   n_host       HOST int32[G]: vertices of graph g
+ *   nnz_host     HOST int64[G]: arcs of graph g (must equal rowptr_g[n_g])
+ *   rowptr_host  HOST array of G DEVICE pointers, graph g's int32[n_g+1] (rowptr_g[0] == 0)
+ *   colidx_host  HOST array of G DEVICE pointers, graph g's int32[nnz_g] with local ids
+ *   colors_host  HOST array of G DEVICE pointers, graph g's int32[n_g] output
+ *   ncolors_out  DEVICE int32[G]
+ *   opts         NULL for defaults
+ * Totals must fit int32 (else CSRCOLOR_EOVERFLOW).  A graph whose rowptr does not start
+ * at 0 or end at nnz_g, or whose ids leave [0, n_g), fails the call with
+ * CSRCOLOR_EBADCSR.  The call synchronises `stream` before returning. */
+int csrcolor_color_multi(int32_t G, const int32_t *n_host, const int64_t *nnz_host,
+                         const int32_t *const *rowptr_host, const int32_t *const *colidx_host,
+                         int32_t *const *colors_host, int32_t *ncolors_out,
+                         const csrcolor_opts *opts, hipStream_t stream);
 
 /* Static description of a status code. */
 const char *csrcolor_strerror(int status);

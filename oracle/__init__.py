@@ -45,6 +45,8 @@ def _load() -> ctypes.CDLL:
         P = ctypes.c_void_p
         lib.oracle_sgr.argtypes = [ctypes.c_int32, P, P, P, P, P, P, P, P, ctypes.c_int32]
         lib.oracle_sgr.restype = ctypes.c_int
+        lib.oracle_sgr_rule.argtypes = [ctypes.c_int32, P, P, P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32]
+        lib.oracle_sgr_rule.restype = ctypes.c_int
         lib.oracle_serial_ff.argtypes = [ctypes.c_int32, P, P, P, P]
         lib.oracle_serial_ff.restype = ctypes.c_int
         lib.oracle_count_conflicts.argtypes = [ctypes.c_int32, P, P, P]
@@ -73,7 +75,11 @@ class SGRResult:
     arcs_cr: np.ndarray      # int64[rounds]: lower arcs examined by the conflict test
 
 
-def sgr(n: int, rowptr, colidx, stats_cap: int = 1 << 16) -> SGRResult:
+RULE_ID = 0        # higher id of a same-colour adjacent pair is requeued
+RULE_DEGREE = 1    # heuristic conflict resolve (Sec. 3.2): smaller degree requeued, ties by id
+
+
+def sgr(n: int, rowptr, colidx, stats_cap: int = 1 << 16, rule: int = RULE_ID) -> SGRResult:
     """Run the serial SGR oracle.  Raises on malformed input."""
     lib = _load()
     rp, ci = _as_i32(rowptr), _as_i32(colidx)
@@ -83,8 +89,8 @@ def sgr(n: int, rowptr, colidx, stats_cap: int = 1 << 16) -> SGRResult:
     ws = np.zeros(stats_cap, dtype=np.int64)
     af = np.zeros(stats_cap, dtype=np.int64)
     ac = np.zeros(stats_cap, dtype=np.int64)
-    rc = lib.oracle_sgr(n, _ptr(rp), _ptr(ci), _ptr(out), _ptr(nc), _ptr(rr),
-                        _ptr(ws), _ptr(af), _ptr(ac), stats_cap)
+    rc = lib.oracle_sgr_rule(n, _ptr(rp), _ptr(ci), _ptr(out), _ptr(nc), _ptr(rr),
+                             _ptr(ws), _ptr(af), _ptr(ac), stats_cap, rule)
     if rc != 0:
         raise ValueError(f"oracle_sgr failed with status {rc}")
     r = int(rr[0])

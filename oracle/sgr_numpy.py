@@ -39,10 +39,12 @@ def _mex_per_vertex(verts: np.ndarray, owner: np.ndarray, col: np.ndarray) -> np
     return out
 
 
-def sgr_numpy(n: int, rowptr, colidx, trace: list | None = None):
+def sgr_numpy(n: int, rowptr, colidx, trace: list | None = None, rule: int = 0):
     """Return (colors 0-based int32[n], ncolors, rounds, wsize list).
 
-    If `trace` is a list, one (W, C[W] 1-based, losers) tuple per round is appended."""
+    If `trace` is a list, one (W, C[W] 1-based, losers) tuple per round is appended.
+    rule 0: the higher id of a same-colour adjacent pair is requeued; rule 1: the
+    smaller degree (row length) is requeued, the higher id on equal degree."""
     rowptr = np.asarray(rowptr, dtype=np.int64)
     colidx = np.asarray(colidx, dtype=np.int64)
     if n == 0:
@@ -51,6 +53,11 @@ def sgr_numpy(n: int, rowptr, colidx, trace: list | None = None):
     dst = colidx
     keep = src != dst
     src, dst = src[keep], dst[keep]
+    rowlen = np.diff(rowptr)
+    if rule == 0:
+        beats = dst < src                       # arc (src, dst): dst requeues src on a tie of colours
+    else:
+        beats = (rowlen[dst] > rowlen[src]) | ((rowlen[dst] == rowlen[src]) & (dst < src))
     S = np.zeros(n, dtype=np.int64)
     C = np.zeros(n, dtype=np.int64)
     inW = np.ones(n, dtype=bool)
@@ -64,7 +71,7 @@ def sgr_numpy(n: int, rowptr, colidx, trace: list | None = None):
         sel = inW[src] & (S[dst] > 0)
         C[W] = _mex_per_vertex(W, src[sel], S[dst[sel]])
         # pairwise conflict test over arcs to lower ids
-        bad = inW[src] & (dst < src) & (C[src] == C[dst])
+        bad = inW[src] & beats & (C[src] == C[dst])
         lose = np.zeros(n, dtype=bool)
         lose[src[bad]] = True
         win = inW & ~lose

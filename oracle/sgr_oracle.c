@@ -42,9 +42,36 @@
  *                is scanned in storage order and the scan stops at the first
  *                conflict (and, for sorted rows, before the first w >= v).
  * Returns 0, or -1 if an allocation failed, -2 if a colidx entry is out of range. */
+/* Conflict rules:
+ *   rule 0 (id):     of two adjacent worklist vertices with equal tentative colour the
+ *                    higher id is requeued;
+ *   rule 1 (degree): the heuristic conflict resolve of Sec. 3.2: the vertex of larger
+ *                    degree keeps its colour and the other is requeued; on equal degree
+ *                    the smaller id keeps it (the higher id is requeued).
+ * Degree = row length.  Under rule 1 every neighbour is examined (a higher-id
+ * neighbour of larger degree can requeue v), so arcs_cr counts all examined arcs. */
+static int beats(const int32_t *rowptr, int32_t w, int32_t v, int rule)
+{
+    if (rule == 0) return w < v;
+    int64_t dw = rowptr[w + 1] - rowptr[w], dv = rowptr[v + 1] - rowptr[v];
+    return dw > dv || (dw == dv && w < v);
+}
+
+int oracle_sgr_rule(int32_t n, const int32_t *rowptr, const int32_t *colidx,
+                    int32_t *colors_out, int32_t *ncolors_out, int32_t *rounds_out,
+                    int64_t *wsize, int64_t *arcs_ff, int64_t *arcs_cr, int32_t stats_cap, int32_t rule);
+
 int oracle_sgr(int32_t n, const int32_t *rowptr, const int32_t *colidx,
                int32_t *colors_out, int32_t *ncolors_out, int32_t *rounds_out,
                int64_t *wsize, int64_t *arcs_ff, int64_t *arcs_cr, int32_t stats_cap)
+{
+    return oracle_sgr_rule(n, rowptr, colidx, colors_out, ncolors_out, rounds_out,
+                           wsize, arcs_ff, arcs_cr, stats_cap, 0);
+}
+
+int oracle_sgr_rule(int32_t n, const int32_t *rowptr, const int32_t *colidx,
+                    int32_t *colors_out, int32_t *ncolors_out, int32_t *rounds_out,
+                    int64_t *wsize, int64_t *arcs_ff, int64_t *arcs_cr, int32_t stats_cap, int32_t rule)
 {
     *ncolors_out = 0;
     *rounds_out = 0;
@@ -85,18 +112,20 @@ int oracle_sgr(int32_t n, const int32_t *rowptr, const int32_t *colidx,
             while (stamp[c] == (int64_t)v + 1) ++c;
             C[v] = c;
         }
-        /* conflict test: a lower-id neighbour holding the same tentative colour */
+        /* conflict test: a neighbour that beats v (rule 0: lower id) holding the same
+           tentative colour */
         for (int64_t i = 0; i < wn; ++i) {
             int32_t v = W[i];
             lose[v] = 0;
             for (int64_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
                 int32_t w = colidx[e];
-                if (w >= v) {
+                if (w == v) continue;
+                if (rule == 0 && w > v) {
                     if (sorted) break;
                     continue;
                 }
                 ++acr;
-                if (C[w] == C[v]) { lose[v] = 1; break; }
+                if (C[w] == C[v] && beats(rowptr, w, v, rule)) { lose[v] = 1; break; }
             }
         }
         /* winners keep their colour, losers are cleared and requeued */

@@ -22,12 +22,15 @@ EOVERFLOW = -5
 ENOTSYM = -6
 ELIMIT = -7
 
+RULE_ID = 0
+RULE_DEGREE = 1
+
 MODE_AUTO = 0
 MODE_LOOP = 1
 MODE_PERSISTENT = 2
 MODE_GRAPH = 3
 
-EXPORTS = ["csrcolor_color", "csrcolor_color_ex", "csrcolor_color_batched",
+EXPORTS = ["csrcolor_color", "csrcolor_color_ex", "csrcolor_color_batched", "csrcolor_color_multi",
            "csrcolor_strerror", "csrcolor_release_workspace", "csrcolor_version"]
 
 
@@ -35,7 +38,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("validate", ctypes.c_int32), ("t_wave", ctypes.c_int32),
                 ("t_split", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("sync_every", ctypes.c_int32), ("lane_assign", ctypes.c_int32),
-                ("lane_detect", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+                ("lane_detect", ctypes.c_int32), ("firstfit", ctypes.c_int32),
+                ("rule", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class Stats(ctypes.Structure):
@@ -73,6 +77,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.csrcolor_color_ex.restype = ctypes.c_int
     lib.csrcolor_color_batched.argtypes = [I32, I32, P, P, P, P, P, ctypes.POINTER(Opts), P]
     lib.csrcolor_color_batched.restype = ctypes.c_int
+    lib.csrcolor_color_multi.argtypes = [I32, P, P, P, P, P, P, ctypes.POINTER(Opts), P]
+    lib.csrcolor_color_multi.restype = ctypes.c_int
     lib.csrcolor_strerror.argtypes = [ctypes.c_int]
     lib.csrcolor_strerror.restype = ctypes.c_char_p
     lib.csrcolor_release_workspace.argtypes = []

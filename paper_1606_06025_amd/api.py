@@ -3,7 +3,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
-from typing import List, Optional, Tuple
+from typing import List, Optional, Sequence, Tuple
 
 import torch
 
@@ -28,11 +28,11 @@ class ColorStats:
 
 def make_opts(mode: int = 0, validate: int = 0, t_wave: int = 0, t_split: int = 0,
               blocks_per_cu: int = 0, sync_every: int = 0, lane_assign: int = 0,
-              lane_detect: int = 0) -> L.Opts:
+              lane_detect: int = 0, firstfit: int = 0, rule: int = 0) -> L.Opts:
     o = L.Opts()
     o.mode, o.validate, o.t_wave, o.t_split = mode, validate, t_wave, t_split
     o.blocks_per_cu, o.sync_every = blocks_per_cu, sync_every
-    o.lane_assign, o.lane_detect = lane_assign, lane_detect
+    o.lane_assign, o.lane_detect, o.firstfit, o.rule = lane_assign, lane_detect, firstfit, rule
     return o
 
 
@@ -114,6 +114,37 @@ def color_batched(voff: torch.Tensor, rowptr: torch.Tensor, colidx: torch.Tensor
                                     ctypes.byref(opts) if opts is not None else None, _stream_ptr(stream))
     L.check(rc)
     return out[:n], ncol[:G]
+
+
+def color_multi(graphs: Sequence[Tuple[torch.Tensor, torch.Tensor]], outs: Optional[Sequence[torch.Tensor]] = None,
+                nnz: Optional[Sequence[int]] = None, opts: Optional[L.Opts] = None,
+                stream: Optional[torch.cuda.Stream] = None) -> Tuple[List[torch.Tensor], torch.Tensor]:
+    """Colour several separate graphs (device (rowptr, colidx) pairs) in one library
+    call.  Returns (per-graph colour tensors, ncolors int32[G] on the device).  `nnz`
+    gives each graph's arc count (default: colidx.numel())."""
+    lib = L.load()
+    G = len(graphs)
+    ns = (ctypes.c_int32 * max(G, 1))()
+    es = (ctypes.c_int64 * max(G, 1))()
+    rps = (ctypes.c_void_p * max(G, 1))()
+    cis = (ctypes.c_void_p * max(G, 1))()
+    cos = (ctypes.c_void_p * max(G, 1))()
+    if outs is None:
+        outs = [torch.empty(max(rp.numel() - 1, 0), dtype=torch.int32, device=rp.device) for rp, _ in graphs]
+    for g, (rp, ci) in enumerate(graphs):
+        n = _check_csr(rp, ci) if ci.numel() else rp.numel() - 1
+        ns[g] = n
+        es[g] = int(nnz[g]) if nnz is not None else ci.numel()
+        rps[g] = rp.data_ptr()
+        cis[g] = ci.data_ptr() if ci.numel() else None
+        cos[g] = outs[g].data_ptr() if n else None
+    dev = graphs[0][0].device if G else torch.device("cuda")
+    ncol = torch.empty(max(G, 1), dtype=torch.int32, device=dev)
+    rc = lib.csrcolor_color_multi(G, ctypes.addressof(ns), ctypes.addressof(es), ctypes.addressof(rps),
+                                  ctypes.addressof(cis), ctypes.addressof(cos), ncol.data_ptr(),
+                                  ctypes.byref(opts) if opts is not None else None, _stream_ptr(stream))
+    L.check(rc)
+    return [o[:ns[g]] for g, o in enumerate(outs)], ncol[:G]
 
 
 def release_workspace() -> None:

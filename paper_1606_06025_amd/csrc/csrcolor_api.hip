@@ -39,6 +39,17 @@ struct Workspace {
     // split-row bucket scratch: cstart[2] and hub flags sized by hub count, owner[2] by chunk count
     int* split = nullptr;
     size_t split_cap = 0;        // ints
+    unsigned* F = nullptr;       // push-mode forbidden-colour bitmaps
+    size_t F_cap = 0;            // words
+    // multi-graph calls: union CSR, its colours, vertex offsets and the graph table
+    int* u_rowptr = nullptr;
+    int* u_colidx = nullptr;
+    int* u_colors = nullptr;
+    long long* u_voff = nullptr;
+    MultiDesc* u_desc = nullptr;
+    MultiDesc* u_desc_h = nullptr;   // pinned staging for the table
+    long long* u_voff_h = nullptr;   // pinned staging for the offsets
+    size_t u_n_cap = 0, u_e_cap = 0, u_g_cap = 0;
     std::vector<hipEvent_t> evs; // event pool for per-kernel timing
     // graph mode: private capture stream, the instantiated two-round graph and the
     // arguments it was captured with
@@ -118,15 +129,63 @@ Workspace* get_ws(int dev, hipStream_t stream) {
     return w;
 }
 
-void free_ws_arrays(Workspace* w) {
-    if (w->split) (void)hipFree(w->split);
-    w->split = nullptr;
-    w->split_cap = 0;
+void free_union(Workspace* w) {
+    if (w->u_rowptr) (void)hipFree(w->u_rowptr);
+    if (w->u_colidx) (void)hipFree(w->u_colidx);
+    if (w->u_colors) (void)hipFree(w->u_colors);
+    if (w->u_voff) (void)hipFree(w->u_voff);
+    if (w->u_desc) (void)hipFree(w->u_desc);
+    if (w->u_desc_h) (void)hipHostFree(w->u_desc_h);
+    if (w->u_voff_h) (void)hipHostFree(w->u_voff_h);
+    w->u_rowptr = w->u_colidx = w->u_colors = nullptr;
+    w->u_voff = nullptr;
+    w->u_desc = w->u_desc_h = nullptr;
+    w->u_voff_h = nullptr;
+    w->u_n_cap = w->u_e_cap = w->u_g_cap = 0;
+}
+
+int ensure_union(Workspace* w, size_t N, size_t E, size_t G) {
+    if (N <= w->u_n_cap && E <= w->u_e_cap && G <= w->u_g_cap) return CSRCOLOR_OK;
+    (void)hipStreamSynchronize(w->stream);
+    const size_t n2 = std::max(N, w->u_n_cap), e2 = std::max(E, w->u_e_cap), g2 = std::max(G, w->u_g_cap);
+    free_union(w);
+    if (hipMalloc(&w->u_rowptr, (n2 + 1) * sizeof(int)) != hipSuccess ||
+        hipMalloc(&w->u_colidx, std::max(e2, (size_t)1) * sizeof(int)) != hipSuccess ||
+        hipMalloc(&w->u_colors, std::max(n2, (size_t)1) * sizeof(int)) != hipSuccess ||
+        hipMalloc(&w->u_voff, (g2 + 1) * sizeof(long long)) != hipSuccess ||
+        hipMalloc(&w->u_desc, g2 * sizeof(MultiDesc)) != hipSuccess ||
+        hipHostMalloc(&w->u_desc_h, g2 * sizeof(MultiDesc), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&w->u_voff_h, (g2 + 1) * sizeof(long long), hipHostMallocDefault) != hipSuccess) {
+        free_union(w);
+        return CSRCOLOR_ENOMEM;
+    }
+    w->u_n_cap = n2;
+    w->u_e_cap = e2;
+    w->u_g_cap = g2;
+    return CSRCOLOR_OK;
+}
+
+// Frees only the per-vertex arrays (colour state and worklists).  Every other
+// buffer of the workspace has its own ensure_* / free pair, so growing one never
+// invalidates another that the caller has already filled.
+void free_vertex_arrays(Workspace* w) {
     if (w->X) (void)hipFree(w->X);
     if (w->wl[0]) (void)hipFree(w->wl[0]);
     if (w->wl[1]) (void)hipFree(w->wl[1]);
     w->X = w->wl[0] = w->wl[1] = nullptr;
     w->cap_n = 0;
+}
+
+// Frees every device array of the workspace (release_workspace).
+void free_ws_arrays(Workspace* w) {
+    free_union(w);
+    if (w->F) (void)hipFree(w->F);
+    w->F = nullptr;
+    w->F_cap = 0;
+    if (w->split) (void)hipFree(w->split);
+    w->split = nullptr;
+    w->split_cap = 0;
+    free_vertex_arrays(w);
 }
 
 int ensure_capacity(Workspace* w, size_t n, int st_cap) {
@@ -136,12 +195,12 @@ int ensure_capacity(Workspace* w, size_t n, int st_cap) {
     }
     if (n > w->cap_n) {
         (void)hipStreamSynchronize(w->stream);
-        free_ws_arrays(w);
+        free_vertex_arrays(w);
         size_t want = std::max(n, (size_t)1024);
         if (hipMalloc(&w->X, want * sizeof(int)) != hipSuccess ||
             hipMalloc(&w->wl[0], want * sizeof(int)) != hipSuccess ||
             hipMalloc(&w->wl[1], want * sizeof(int)) != hipSuccess) {
-            free_ws_arrays(w);
+            free_vertex_arrays(w);
             return CSRCOLOR_ENOMEM;
         }
         w->cap_n = want;
@@ -172,6 +231,18 @@ int ensure_split(Workspace* w, size_t ints) {
     return CSRCOLOR_OK;
 }
 
+int ensure_F(Workspace* w, size_t words) {
+    if (words <= w->F_cap) return CSRCOLOR_OK;
+    (void)hipStreamSynchronize(w->stream);
+    if (w->F) (void)hipFree(w->F);
+    w->F = nullptr;
+    w->F_cap = 0;
+    const size_t want = std::max(words, (size_t)4096);
+    if (hipMalloc(&w->F, want * sizeof(unsigned)) != hipSuccess) return CSRCOLOR_ENOMEM;
+    w->F_cap = want;
+    return CSRCOLOR_OK;
+}
+
 int read_ctl(Workspace* w) {
     HIP_TRY(hipMemcpyAsync(w->ctl_h, w->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, w->stream));
     HIP_TRY(hipStreamSynchronize(w->stream));
@@ -187,6 +258,8 @@ struct Options {
     int tsplit = 2048;
     int lane_assign = 0;      // tile buckets run with 2/4/8/16 lanes per vertex
     int lane_detect = 0xF;    // lane-per-vertex conflict test (early exit) in every tile bucket
+    int pushff = 1;           // push-mode FirstFit
+    int rule = 0;             // conflict rule (csrcolor_rule)
 };
 
 Options parse_opts(const csrcolor_opts* o) {
@@ -201,6 +274,8 @@ Options parse_opts(const csrcolor_opts* o) {
     r.tsplit = std::max(r.tsplit, r.twave);
     if (o->lane_assign) r.lane_assign = o->lane_assign < 0 ? 0 : (o->lane_assign & 0xF);
     if (o->lane_detect) r.lane_detect = o->lane_detect < 0 ? 0 : (o->lane_detect & 0xF);
+    if (o->firstfit) r.pushff = o->firstfit != 1;
+    r.rule = o->rule;
     return r;
 }
 
@@ -261,6 +336,10 @@ int drive_loop(Workspace* w, Job& J, RoundArgs& a, int ub[NB], int budget, KTime
             a.wl_out = w->wl[par ^ 1];
             T.run(1, [&] { k_assign<<<grid, WG, 0, st>>>(a); });
             T.run(2, [&] { k_detect<<<grid, WG, 0, st>>>(a); });
+            if (a.pushff && ub[BSPLIT] > 0) {
+                const int pg = std::min(ub[BSPLIT], budget);
+                T.run(2, [&] { k_push<<<pg, WG, 0, st>>>(a); });
+            }
             par ^= 1;
             ++launched;
         }
@@ -285,13 +364,19 @@ int drive_persistent(Workspace* w, Job& J, RoundArgs& a, int budget, KTimer& T) 
     const int cus = num_cus(w->device);
     const int grid = std::min(std::max(per_cu, 1) * cus, budget);
     a.dev_plan = 1;
-    a.par_in = 1;
-    a.par_out = 0;
-    a.wl_in = w->wl[1];
-    a.wl_out = w->wl[0];
-    a.round = 1;
+    // round index 1 (the second round) reads parity 1; odd rounds 1 -> 0, even rounds 0 -> 1
+    RoundArgs a_odd = a, a_even = a;
+    a_odd.par_in = 1;
+    a_odd.par_out = 0;
+    a_odd.wl_in = w->wl[1];
+    a_odd.wl_out = w->wl[0];
+    a_even.par_in = 0;
+    a_even.par_out = 1;
+    a_even.wl_in = w->wl[0];
+    a_even.wl_out = w->wl[1];
+    int first = 1;
     int maxr = J.n + 2;
-    void* args[] = {&a, &maxr};
+    void* args[] = {&a_odd, &a_even, &first, &maxr};
     hipError_t e = hipSuccess;
     T.run(1, [&] {
         e = hipLaunchCooperativeKernel((const void*)k_persistent, dim3(grid), dim3(WG), args, 0, w->stream);
@@ -328,6 +413,7 @@ int drive_graph(Workspace* w, Job& J, RoundArgs& a, int budget) {
             r.wl_out = w->wl[par ^ 1];
             k_assign<<<budget, WG, 0, w->gstream>>>(r);
             k_detect<<<budget, WG, 0, w->gstream>>>(r);
+            if (r.pushff && r.cstart[1] != r.cstart[0]) k_push<<<budget, WG, 0, w->gstream>>>(r);  // split hubs exist
         }
         hipError_t ce = hipStreamEndCapture(w->gstream, &g);
         if (ce != hipSuccess) return CSRCOLOR_EHIP;
@@ -415,10 +501,23 @@ int run_job(Workspace* w, Job& J, const long long* voff, int G) {
         k_fill<<<std::min((cnt + WG - 1) / WG, cus * 4), WG, 0, st>>>(hubflags, cnt, 0);
     }
 
+    // push mode: deg(v)+1 bits per vertex, zeroed
+    unsigned* F = nullptr;
+    if (J.opt.pushff) {
+        const size_t words = ((size_t)w->ctl_h->nnz + (size_t)n) / 32 + 2;
+        if ((rc = ensure_F(w, words))) return rc;
+        F = w->F;
+        T.run(0, [&] {
+            k_fill<<<(int)std::min<size_t>((words + WG - 1) / WG, (size_t)cus * 8), WG, 0, st>>>(
+                reinterpret_cast<int*>(F), (int)words, 0);
+        });
+    }
+
     const int r1blocks = (int)(((long long)n + 4 * WG - 1) / (4 * WG));
     T.run(0, [&] {
         k_round1<<<r1blocks, WG, 0, st>>>(n, J.rowptr, J.colidx, w->X, J.colors_out, w->wl[1], w->ctl,
-                                          J.sorted, twave, J.opt.tsplit, seg, cstart1, owner1);
+                                          J.sorted, twave, J.opt.tsplit, seg, cstart1, owner1, F,
+                                          w->ctl_h->nnz, J.opt.rule);
     });
     HIP_TRY(hipGetLastError());
 
@@ -443,6 +542,9 @@ int run_job(Workspace* w, Job& J, const long long* voff, int G) {
     a.hubbm = reinterpret_cast<unsigned*>(hubflags);
     a.hubdone = hubflags + (size_t)nhub * HW;
     a.hublost = a.hubdone + nhub;
+    a.pushff = J.opt.pushff;
+    a.F = F;
+    a.rule = J.opt.rule;
     a.st_cap = st_cap;
     a.st_wsize = st_cap ? w->st_wsize : nullptr;
     a.st_arcs = st_cap ? w->st_arcs : nullptr;
@@ -515,7 +617,8 @@ int csrcolor_color_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx, i
                       int32_t* ncolors_host, const csrcolor_opts* opts, csrcolor_stats* stats,
                       hipStream_t stream) {
     if (n < 0) return CSRCOLOR_EINVAL;
-    if (opts && (opts->mode < 0 || opts->mode > CSRCOLOR_MODE_GRAPH || opts->validate < 0))
+    if (opts && (opts->mode < 0 || opts->mode > CSRCOLOR_MODE_GRAPH || opts->validate < 0 ||
+                 opts->firstfit < 0 || opts->firstfit > 2 || opts->rule < 0 || opts->rule > 1))
         return CSRCOLOR_EINVAL;
     if (stats && stats->cap > 0 && stats->cap > (1 << 24)) return CSRCOLOR_EINVAL;
     if (n == 0) {
@@ -586,6 +689,86 @@ int csrcolor_color_batched(int32_t G, int32_t n_total, const int64_t* voff, cons
     if (hipGetLastError() != hipSuccess) return CSRCOLOR_EHIP;
     if (hipStreamSynchronize(stream) != hipSuccess) return CSRCOLOR_EHIP;
     return CSRCOLOR_OK;
+}
+
+int csrcolor_color_multi(int32_t G, const int32_t* n_host, const int64_t* nnz_host,
+                         const int32_t* const* rowptr_host, const int32_t* const* colidx_host,
+                         int32_t* const* colors_host, int32_t* ncolors_out, const csrcolor_opts* opts,
+                         hipStream_t stream) {
+    if (G < 0) return CSRCOLOR_EINVAL;
+    if (G == 0) return CSRCOLOR_OK;
+    if (!n_host || !nnz_host || !rowptr_host || !colidx_host || !colors_host || !ncolors_out)
+        return CSRCOLOR_EINVAL;
+    if (opts && (opts->mode < 0 || opts->mode > CSRCOLOR_MODE_GRAPH || opts->validate < 0 ||
+                 opts->firstfit < 0 || opts->firstfit > 2 || opts->rule < 0 || opts->rule > 1))
+        return CSRCOLOR_EINVAL;
+    long long N = 0, E = 0;
+    for (int g = 0; g < G; ++g) {
+        if (n_host[g] < 0 || nnz_host[g] < 0) return CSRCOLOR_EINVAL;
+        if (!rowptr_host[g] || (n_host[g] > 0 && !colors_host[g]) || (nnz_host[g] > 0 && !colidx_host[g]))
+            return CSRCOLOR_EINVAL;
+        N += n_host[g];
+        E += nnz_host[g];
+    }
+    if (N >= (1ll << 31) - 1 || E >= (1ll << 31) - 1) return CSRCOLOR_EOVERFLOW;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return CSRCOLOR_EHIP;
+    Workspace* w = get_ws(dev, stream);
+    std::lock_guard<std::mutex> lk(w->mu);
+    // size every buffer first: nothing below may reallocate what the union copy filled
+    int rc = ensure_capacity(w, (size_t)std::max<long long>(N, 1), 0);
+    if (rc) return rc;
+    rc = ensure_union(w, (size_t)N, (size_t)E, (size_t)G);
+    if (rc) return rc;
+    // the staging buffers may still feed an earlier call's copies: wait for the stream
+    HIP_TRY(hipStreamSynchronize(stream));
+    long long vo = 0, eo = 0;
+    int maxn = 0;
+    long long maxe = 0;
+    for (int g = 0; g < G; ++g) {
+        MultiDesc& m = w->u_desc_h[g];
+        m.rowptr = rowptr_host[g];
+        m.colidx = colidx_host[g];
+        m.colors = colors_host[g];
+        m.voff = vo;
+        m.eoff = eo;
+        m.n = n_host[g];
+        m.pad = 0;
+        m.nnz = nnz_host[g];
+        w->u_voff_h[g] = vo;
+        vo += n_host[g];
+        eo += nnz_host[g];
+        maxn = std::max(maxn, n_host[g]);
+        maxe = std::max(maxe, (long long)nnz_host[g]);
+    }
+    w->u_voff_h[G] = vo;
+    HIP_TRY(hipMemcpyAsync(w->u_desc, w->u_desc_h, G * sizeof(MultiDesc), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(w->u_voff, w->u_voff_h, (G + 1) * sizeof(long long), hipMemcpyHostToDevice, stream));
+    k_init<<<1, WG, 0, stream>>>(w->ctl);
+    const long long per = std::max<long long>(maxn, maxe);
+    const int gx = (int)std::min<long long>(std::max<long long>((per + WG * 4 - 1) / (WG * 4), 1), 64);
+    k_concat<<<dim3(gx, G), WG, 0, stream>>>(w->u_desc, G, w->u_rowptr, w->u_colidx, N, E, w->ctl);
+    HIP_TRY(hipGetLastError());
+    if ((rc = read_ctl(w))) return rc;
+    if (w->ctl_h->err) return CSRCOLOR_EBADCSR;
+    if (N > 0) {
+        Job J;
+        J.n = (int)N;
+        J.rowptr = w->u_rowptr;
+        J.colidx = E > 0 ? w->u_colidx : nullptr;
+        J.colors_out = w->u_colors;
+        J.opt = parse_opts(opts);
+        J.stats = nullptr;
+        rc = run_job(w, J, w->u_voff, G);
+        if (rc) return rc;
+        const int gxs = (int)std::min<long long>(std::max<long long>((maxn + WG * 4 - 1) / (WG * 4), 1), 64);
+        k_scatter<<<dim3(gxs, G), WG, 0, stream>>>(w->u_desc, w->u_colors);
+        k_segmented_max<<<std::min(G, num_cus(dev) * 8), WG, 0, stream>>>(G, w->u_voff, w->u_colors, ncolors_out);
+    } else {
+        k_fill<<<(G + WG - 1) / WG, WG, 0, stream>>>(ncolors_out, G, 0);
+    }
+    if (hipGetLastError() != hipSuccess) return CSRCOLOR_EHIP;
+    return hipStreamSynchronize(stream) == hipSuccess ? CSRCOLOR_OK : CSRCOLOR_EHIP;
 }
 
 const char* csrcolor_strerror(int status) {

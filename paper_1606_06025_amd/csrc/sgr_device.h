@@ -46,6 +46,33 @@ __host__ __device__ inline int bucket_of(int deg, int twave, int tsplit) {
 }
 __host__ __device__ inline int split_chunks(int deg) { return (deg + SPLIT_CH - 1) / SPLIT_CH; }
 
+// Does neighbour w (same tentative colour) requeue v?  dv = deg(v).
+__device__ __forceinline__ bool beats(int rule, const int* __restrict__ rowptr, int w, int v, int dv) {
+    if (rule == 0) return w < v;
+    const int dw = rowptr[w + 1] - rowptr[w];
+    return dw > dv || (dw == dv && w < v);
+}
+
+// Conflict of v (tentative colour cv, degree dv) with row entry w (-1 = none).
+// Under the id rule only lower ids are gathered.
+__device__ __forceinline__ bool conflict(int rule, const int* __restrict__ rowptr, const int* X, int w, int v,
+                                         int cv, int dv) {
+    if (w < 0 || w == v) return false;
+    if (rule == 0) return w < v && (X[w] & 0x7fffffff) == cv;
+    return (X[w] & 0x7fffffff) == cv && beats(1, rowptr, w, v, dv);
+}
+
+// Marks colour c in the forbidden bitmap of neighbour u (push-mode FirstFit).  Only
+// colours <= deg(u)+1 can change u's smallest free colour, and only they have a bit.
+__device__ __forceinline__ void push_colour(unsigned* F, const int* __restrict__ rowptr, int u, int c) {
+    const int ub = rowptr[u];
+    const int du = rowptr[u + 1] - ub;
+    if (c - 1 <= du) {
+        const long long bit = (long long)ub + u + c - 1;
+        atomicOr(&F[bit >> 5], 1u << (bit & 31));
+    }
+}
+
 // Device-resident control block.
 struct Ctl {
     int cnt[2][8];      // worklist length per bucket, double-buffered by round parity
@@ -91,6 +118,13 @@ struct RoundArgs {
     int lane_mode_detect;  // bit b: tile bucket b runs the conflict test lane-per-vertex
     int tsplit;            // largest degree handled without splitting the row
     int dev_plan;          // 1: every block derives the bucket partition from the device queue sizes
+    // push mode: F holds, for every vertex v, deg(v)+1 bits starting at bit rowptr[v]+v;
+    // bit c-1 set <=> a neighbour settled with colour c in an earlier round
+    int pushff;
+    unsigned* F;
+    // conflict rule: 0 = the higher id is requeued; 1 = the smaller degree (row
+    // length) is requeued, the higher id on equal degree (heuristic of Sec. 3.2)
+    int rule;
     // split bucket: per queued hub its first chunk; per chunk the hub's queue entry;
     // per queue entry a colour bitmap, a finished-chunk counter and a lost flag
     int* cstart[2];

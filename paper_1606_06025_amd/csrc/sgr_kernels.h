@@ -3,6 +3,7 @@
 #pragma once
 
 #include "sgr_device.h"
+#include "sgr_round.h"
 
 namespace csrcolor {
 
@@ -111,7 +112,8 @@ __global__ __launch_bounds__(WG) void k_check_symmetric(int n, const int* __rest
 __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ rowptr,
                                                const int* __restrict__ colidx, int* X, int* out,
                                                int* wl1, Ctl* ctl, int sorted, int twave, int tsplit,
-                                               Seg seg, int* cstart1, int* owner1) {
+                                               Seg seg, int* cstart1, int* owner1, unsigned* F, int nnz,
+                                               int rule) {
     constexpr int ITER = 4;
     __shared__ int buf[WAVES][NB][ITER * 64];
     __shared__ int wcnt[WAVES][NB];
@@ -126,16 +128,21 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
         // so concatenating the per-wavefront buffers keeps ascending vertex order
         const long long vv = chunk0 + (long long)wv * (64 * ITER) + it * 64 + lane;
         bool lose = false;
+        bool winpush = false;   // push mode: a round-1 winner with neighbours
         int bkt = -1;
+        int wbeg = 0, wend = 0;
         if (vv < n) {
             const int v = (int)vv;
             const int beg = rowptr[v], end = rowptr[v + 1];
             if (end > beg) {
-                if (sorted) {
+                if (rule == 0 && sorted) {
                     lose = colidx[beg] < v;
                 } else {
-                    for (int e = beg; e < end; ++e)
-                        if (colidx[e] < v) { lose = true; break; }
+                    // all tentative colours are 1: requeued iff some neighbour beats v
+                    for (int e = beg; e < end; ++e) {
+                        const int w = colidx[e];
+                        if (w != v && beats(rule, rowptr, w, v, end - beg)) { lose = true; break; }
+                    }
                 }
             }
             if (lose) {
@@ -154,6 +161,22 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
             } else {
                 X[v] = 1;
                 out[v] = 0;
+                winpush = F != nullptr && end > beg;
+                wbeg = beg;
+                wend = end;
+            }
+        }
+        if (F != nullptr) {
+            // round-1 winners push colour 1: short rows by their own lane, long rows by
+            // the whole wavefront
+            const bool longrow = winpush && wend - wbeg > 64;
+            if (winpush && !longrow) push_row_lane(F, rowptr, colidx, nnz, (int)vv, 1, wbeg, wend);
+            unsigned long long lr = __ballot(longrow);
+            while (lr) {
+                const int j = __ffsll((long long)lr) - 1;
+                lr &= lr - 1;
+                push_row_coop(F, rowptr, colidx, nnz, (int)__builtin_amdgcn_readlane((int)vv, j), 1,
+                              __builtin_amdgcn_readlane(wbeg, j), __builtin_amdgcn_readlane(wend, j), lane, 64);
             }
         }
 #pragma unroll
@@ -183,11 +206,6 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
     }
 }
 
-}  // namespace csrcolor
-
-#include "sgr_round.h"
-
-namespace csrcolor {
 
 // Per-graph colour count of a batched run: ncolors[g] = 1 + max colour in graph g.
 __global__ __launch_bounds__(WG) void k_segmented_max(int G, const long long* __restrict__ voff,
@@ -204,6 +222,39 @@ __global__ __launch_bounds__(WG) void k_segmented_max(int G, const long long* __
 
 __global__ void k_fill(int* p, int count, int value) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = value;
+}
+
+// One graph of a multi-graph call: device pointers, its place in the union and sizes.
+struct MultiDesc {
+    const int* rowptr;
+    const int* colidx;
+    int* colors;
+    long long voff;
+    long long eoff;
+    int n;
+    int pad;
+    long long nnz;
+};
+
+// Copies graph blockIdx.y into the union CSR with ids shifted by its vertex offset and
+// row offsets shifted by its arc offset; the last graph also writes rowptr[N].
+__global__ __launch_bounds__(WG) void k_concat(const MultiDesc* __restrict__ d, int G, int* urowptr, int* ucolidx,
+                                               long long N, long long E, Ctl* ctl) {
+    const int g = blockIdx.y;
+    const MultiDesc m = d[g];
+    const long long stride = (long long)gridDim.x * WG;
+    const long long t0 = (long long)blockIdx.x * WG + threadIdx.x;
+    if (t0 == 0 && (m.rowptr[0] != 0 || m.rowptr[m.n] != m.nnz)) atomicOr(&ctl->err, 32);
+    for (long long i = t0; i < m.n; i += stride) urowptr[m.voff + i] = m.rowptr[i] + (int)m.eoff;
+    for (long long j = t0; j < m.nnz; j += stride) ucolidx[m.eoff + j] = m.colidx[j] + (int)m.voff;
+    if (g == G - 1 && t0 == 0) urowptr[N] = (int)E;
+}
+
+// Copies each graph's colours from the union output to its own buffer.
+__global__ __launch_bounds__(WG) void k_scatter(const MultiDesc* __restrict__ d, const int* __restrict__ ucolors) {
+    const MultiDesc m = d[blockIdx.y];
+    for (long long i = (long long)blockIdx.x * WG + threadIdx.x; i < m.n; i += (long long)gridDim.x * WG)
+        m.colors[i] = ucolors[m.voff + i];
 }
 
 // Batched validation: voff[0] == 0, non-decreasing, voff[G] == n_total, and every

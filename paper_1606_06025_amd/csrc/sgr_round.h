@@ -128,6 +128,73 @@ __device__ __forceinline__ void wave_slice(int lo, int hi, int& wlo, int& whi) {
 }
 
 // ---------------------------------------------------------------------------
+// Push mode: a vertex that settles with colour c sets bit c-1 in the forbidden
+// bitmap F of each neighbour (once in its life); FirstFit then reads the vertex's
+// own bitmap instead of gathering every neighbour's colour every round.  The bitmap
+// of v at round r holds exactly the colours of neighbours settled before round r,
+// which is the snapshot FirstFit of Sec. 3 reads, so the colouring is unchanged.
+// ---------------------------------------------------------------------------
+
+// One lane pushes colour c of vertex v to every neighbour in row [beg, end).
+__device__ __forceinline__ void push_row_lane(unsigned* F, const int* __restrict__ rowptr,
+                                              const int* __restrict__ colidx, int nnz, int v, int c, int beg,
+                                              int end) {
+    const int mis = (int)((reinterpret_cast<uintptr_t>(colidx) >> 2) & 3);
+    const int nq = end > beg ? (((end - 1 + mis) >> 2) - ((beg + mis) >> 2) + 1) : 0;
+    for (int q = 0; q < nq; ++q) {
+        int w[4];
+        load_quad(colidx, nnz, beg, end, q, w);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (w[k] >= 0 && w[k] != v) push_colour(F, rowptr, w[k], c);
+    }
+}
+__device__ __forceinline__ void push_row_lane(const RoundArgs& a, int v, int c, int beg, int end) {
+    push_row_lane(a.F, a.rowptr, a.colidx, a.nnz, v, c, beg, end);
+}
+
+// `nthr` threads (thread index t) push colour c of v over row [beg, end) together.
+__device__ __forceinline__ void push_row_coop(unsigned* F, const int* __restrict__ rowptr,
+                                              const int* __restrict__ colidx, int nnz, int v, int c, int beg,
+                                              int end, int t, int nthr) {
+    const int nq = ((end - beg) + 3 + 3) / 4 + 1;
+    for (int q0 = 0; q0 < nq; q0 += nthr) {
+        int w[4];
+        load_quad(colidx, nnz, beg, end, q0 + t, w);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (w[k] >= 0 && w[k] != v) push_colour(F, rowptr, w[k], c);
+    }
+}
+__device__ __forceinline__ void push_row_coop(const RoundArgs& a, int v, int c, int beg, int end, int t,
+                                              int nthr) {
+    push_row_coop(a.F, a.rowptr, a.colidx, a.nnz, v, c, beg, end, t, nthr);
+}
+
+// Push-mode FirstFit for any bucket: one lane per vertex finds the first clear bit
+// of the vertex's bitmap (bits below its start count as set); the scan stops at the
+// first clear bit, which exists within deg(v)+1 bits.
+__device__ __forceinline__ void assign_push(const RoundArgs& a, const int* list, int lo, int hi, long long& arcs) {
+    const int lane = __lane_id();
+    int wlo, whi;
+    wave_slice(lo, hi, wlo, whi);
+    for (int t0 = wlo; t0 < whi; t0 += 64) {
+        const int nv = min(64, whi - t0);
+        if (lane < nv) {
+            const int v = list[t0 + lane];
+            const int beg = a.rowptr[v];
+            const long long bit = (long long)beg + v;
+            long long wi = bit >> 5;
+            unsigned wd = a.F[wi] | ((1u << (bit & 31)) - 1u);
+            while (wd == 0xffffffffu) wd = a.F[++wi];
+            const long long pos = wi * 32 + __ffs(~wd) - 1;
+            a.X[v] = FLAG | (int)(pos - bit + 1);
+            arcs += a.rowptr[v + 1] - beg;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // FirstFit (Sec. 3, FirstFit routine, with the bitset of Sec. 3.2): colour =
 // smallest c > 0 whose bit c-1 is clear in the OR of the neighbours' settled
 // colours (X > 0).  Written as FLAG | c.
@@ -346,12 +413,31 @@ __device__ __forceinline__ void assign_wg(const RoundArgs& a, const int* list, i
     }
 }
 
+// Device-scope atomic access to the split-row merge state.  These are performed at
+// the device coherence point, so no L2 writeback / invalidate fence is needed; the
+// order "my contributions, then my done-count" is kept by waiting for the returned
+// values of the contributions (wait_on) before issuing the count.
 __device__ __forceinline__ unsigned ld_agent(const unsigned* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ int ld_agent(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void st_agent(unsigned* p, unsigned v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned or_agent(unsigned* p, unsigned v) {
+    return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int add_agent(int* p, int v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Makes the wavefront wait until `v` (the result of an atomic) has arrived, and keeps
+// later memory operations after that point.
+__device__ __forceinline__ void wait_on(unsigned v) { asm volatile("" ::"v"(v) : "memory"); }
 
 // Split bucket (> t_split): the row of a queued hub is cut into SPLIT_CH-arc chunks,
 // one workgroup per chunk (chunk t belongs to queue entry owner[t]).  Each chunk ORs
@@ -386,23 +472,27 @@ __device__ __forceinline__ void assign_split(const RoundArgs& a, const int* list
             }
         }
         __syncthreads();
-        if (tid < HW) {
-            const unsigned wd = s.bm[tid];
-            if (wd) atomicOr(&a.hubbm[p * HW + tid], wd);
+        if (tid < 64) {
+            // wavefront 0 publishes the chunk's colours, waits for the atomics to be
+            // performed, then counts the chunk done
+            unsigned old = 0;
+            if (tid < HW) {
+                const unsigned wd = s.bm[tid];
+                if (wd) old = or_agent(&a.hubbm[p * HW + tid], wd);
+            }
+            wait_on(old);
+            __builtin_amdgcn_wave_barrier();
+            if (tid == 0) s.sh[1] = add_agent(&a.hubdone[p], 1) == nch - 1;
         }
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) s.sh[1] = atomicAdd(&a.hubdone[p], 1) == nch - 1;
         __syncthreads();
         if (s.sh[1]) {
-            __threadfence();
             const unsigned wd = tid < HW ? ld_agent(&a.hubbm[p * HW + tid]) : 0xffffffffu;
             int best = wd != 0xffffffffu ? tid * 32 + __ffs(~wd) - 1 : 0x7fffffff;
             best = block_min(best, s.red);
             const int c = best != 0x7fffffff ? best + 1 : wg_mex_window(a, rb, re, HW * 32, s);
-            if (tid < HW) a.hubbm[p * HW + tid] = 0;
+            if (tid < HW) st_agent(&a.hubbm[p * HW + tid], 0u);
             if (tid == 0) {
-                a.hubdone[p] = 0;
+                st_agent(&a.hubdone[p], 0);
                 a.X[v] = FLAG | c;
                 arcs += re - rb;
             }
@@ -429,7 +519,10 @@ __device__ __forceinline__ void assign_phase(const RoundArgs& a, RoundLds& s, in
     const int hi = (int)((long long)(j + 1) * cnt / nbk);
     int* res = s.res + (threadIdx.x >> 6) * 64;
     long long arcs = 0;
-    if (b < NTILE && (a.lane_mode_assign >> b & 1)) {
+    if (a.pushff) {
+        // every bucket, split hubs included, is one lane per vertex in push mode
+        assign_push(a, list, lo, hi, arcs);
+    } else if (b < NTILE && (a.lane_mode_assign >> b & 1)) {
         assign_lanes(a, list, lo, hi, arcs);
     } else {
         switch (b) {
@@ -557,14 +650,17 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
                 load_quad(a.colidx, a.nnz, beg, end, q, w);
                 bool hit = false;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) hit |= w[k] >= 0 && w[k] < v && (a.X[w[k]] & CMASK) == cv;
+                for (int k = 0; k < 4; ++k) hit |= conflict(a.rule, a.rowptr, a.X, w[k], v, cv, end - beg);
                 const bool lost = ((__ballot(hit) >> gshift) & gmask) != 0;
                 if (q == 0) res[j] = lost;
             }
             __builtin_amdgcn_wave_barrier();
             const bool lost_l = res[lane] != 0;
             __builtin_amdgcn_wave_barrier();
-            if (v_l >= 0 && !lost_l) settle(a, v_l, cv_l, cmax);
+            if (v_l >= 0 && !lost_l) {
+                settle(a, v_l, cv_l, cmax);
+                if (a.pushff) push_row_lane(a, v_l, cv_l, beg_l, end_l);
+            }
             push_losers(v_l, lost_l, mybuf, wc);
         }
         flush_losers(s, wc, outl, cnt_out);
@@ -603,16 +699,19 @@ __device__ __forceinline__ void detect_lanes(const RoundArgs& a, const int* list
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     if (w[k] >= 0) {
-                        if (w[k] < v_l) {
-                            if ((a.X[w[k]] & CMASK) == cv) lost = true;
-                        } else if (a.sorted) {
-                            stop = true;
+                        if (a.rule == 0 && w[k] >= v_l) {
+                            stop |= a.sorted != 0;
+                        } else if (conflict(a.rule, a.rowptr, a.X, w[k], v_l, cv, end - beg)) {
+                            lost = true;
                         }
                     }
                 }
                 if (lost || stop) break;
             }
-            if (v_l >= 0 && !lost) settle(a, v_l, cv, cmax);
+            if (v_l >= 0 && !lost) {
+                settle(a, v_l, cv, cmax);
+                if (a.pushff) push_row_lane(a, v_l, cv, beg, end);
+            }
             push_losers(v_l, lost, mybuf, wc);
         }
         flush_losers(s, wc, outl, cnt_out);
@@ -655,8 +754,8 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
                     bool hit = false, stop = false;
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        hit |= w[k] >= 0 && w[k] < v && (a.X[w[k]] & CMASK) == cv;
-                        stop |= a.sorted && w[k] >= v;
+                        hit |= conflict(a.rule, a.rowptr, a.X, w[k], v, cv, end - beg);
+                        stop |= a.sorted && a.rule == 0 && w[k] >= v;
                     }
                     if (__ballot(hit)) {
                         lost = true;
@@ -667,6 +766,16 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
                 if (lane == j) lost_l = lost;
             }
             if (v_l >= 0 && !lost_l) settle(a, v_l, cv_l, cmax);
+            if (a.pushff) {
+                unsigned long long win = __ballot(v_l >= 0 && !lost_l);
+                while (win) {
+                    const int j = __ffsll((long long)win) - 1;
+                    win &= win - 1;
+                    push_row_coop(a, __builtin_amdgcn_readlane(v_l, j), __builtin_amdgcn_readlane(cv_l, j),
+                                  __builtin_amdgcn_readlane(beg_l, j), __builtin_amdgcn_readlane(end_l, j),
+                                  lane, 64);
+                }
+            }
             push_losers(v_l, lost_l, mybuf, wc);
         }
         flush_losers(s, wc, outl, cnt_out);
@@ -692,8 +801,8 @@ __device__ __forceinline__ void detect_wg(const RoundArgs& a, const int* list, i
             bool hit = false, stop = false;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                hit |= w[k] >= 0 && w[k] < v && (a.X[w[k]] & CMASK) == cv;
-                stop |= a.sorted && w[k] >= v;
+                hit |= conflict(a.rule, a.rowptr, a.X, w[k], v, cv, end - beg);
+                stop |= a.sorted && a.rule == 0 && w[k] >= v;
             }
             const int anyhit = __syncthreads_or(hit);
             const int anystop = __syncthreads_or(stop);
@@ -711,6 +820,7 @@ __device__ __forceinline__ void detect_wg(const RoundArgs& a, const int* list, i
                 settle(a, v, cv, cmax);
             }
         }
+        if (a.pushff && !lost) push_row_coop(a, v, cv, beg, end, threadIdx.x, WG);
     }
 }
 
@@ -734,28 +844,29 @@ __device__ __forceinline__ void detect_split(const RoundArgs& a, const int* list
         const int beg = rb + k * SPLIT_CH, end = min(beg + SPLIT_CH, re);
         const int cv = a.X[v] & CMASK;
         bool hit = false;
-        const bool skip = ld_agent(&a.hublost[p]) != 0 || (a.sorted && a.colidx[beg] >= v);
+        const bool skip = ld_agent(&a.hublost[p]) != 0 || (a.rule == 0 && a.sorted && a.colidx[beg] >= v);
         if (!skip) {
             const int nq = ((end - beg) + 3 + 3) / 4 + 1;
             for (int q0 = 0; q0 < nq; q0 += WG) {
                 int w[4];
                 load_quad(a.colidx, a.nnz, beg, end, q0 + tid, w);
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk) hit |= w[kk] >= 0 && w[kk] < v && (a.X[w[kk]] & CMASK) == cv;
+                for (int kk = 0; kk < 4; ++kk) hit |= conflict(a.rule, a.rowptr, a.X, w[kk], v, cv, re - rb);
             }
         }
         const int anyhit = __syncthreads_or(hit);
-        if (tid == 0 && anyhit) atomicOr(&a.hublost[p], 1);
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) s.sh[1] = atomicAdd(&a.hubdone[p], 1) == nch - 1;
+        if (tid == 0) {
+            unsigned old = 0;
+            if (anyhit) old = or_agent(reinterpret_cast<unsigned*>(&a.hublost[p]), 1u);
+            wait_on(old);
+            s.sh[1] = add_agent(&a.hubdone[p], 1) == nch - 1;
+        }
         __syncthreads();
         if (s.sh[1]) {
             if (tid == 0) {
-                __threadfence();
                 const bool lost = ld_agent(&a.hublost[p]) != 0;
-                a.hublost[p] = 0;
-                a.hubdone[p] = 0;
+                st_agent(&a.hublost[p], 0);
+                st_agent(&a.hubdone[p], 0);
                 s.sh[2] = -1;
                 if (lost) {
                     const int qn = atomicAdd(cnt_out, 1);
@@ -833,6 +944,27 @@ __global__ __launch_bounds__(WG) void k_detect(RoundArgs a) {
     if (threadIdx.x == 0 && cmax > 0) atomicMax(&a.ctl->maxcolor, cmax);
 }
 
+// Push phase for the split bucket (push mode): every chunk of a hub that settled this
+// round pushes the hub's colour over the chunk's part of the row.
+__device__ __forceinline__ void push_split_phase(const RoundArgs& a, int j, int nbk) {
+    const int nchunks = a.ctl->ccnt[a.par_in];
+    const int* list = a.wl_in + a.seg[BSPLIT];
+    const int* cstart = a.cstart[a.par_in];
+    const int* owner = a.owner[a.par_in];
+    for (int t = j; t < nchunks; t += nbk) {
+        const int p = owner[t];
+        const int v = list[p];
+        const int x = a.X[v];
+        if (x <= 0) continue;                  // requeued: nothing to push
+        const int k = t - cstart[p];
+        const int rb = a.rowptr[v], re = a.rowptr[v + 1];
+        const int beg = rb + k * SPLIT_CH, end = min(beg + SPLIT_CH, re);
+        push_row_coop(a, v, x, beg, end, threadIdx.x, WG);
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_push(RoundArgs a) { push_split_phase(a, blockIdx.x, gridDim.x); }
+
 // ---------------------------------------------------------------------------
 // Persistent mode (the kernel fusion of Sec. 3.3): every round of a colouring in
 // one cooperative launch, FirstFit and the conflict test separated by device-wide
@@ -858,48 +990,63 @@ __device__ __forceinline__ void grid_sync(Ctl* ctl, int& gen) {
             if (t == ngrp * target - 1) __hip_atomic_store(&ctl->bar_gen[0], target, __ATOMIC_RELEASE,
                                                          __HIP_MEMORY_SCOPE_AGENT);
         }
-        while (__hip_atomic_load(&ctl->bar_gen[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target)
-            __builtin_amdgcn_s_sleep(1);
+        // spin with relaxed loads (an acquire load would invalidate the L2 on every poll),
+        // then one acquire fence
+        while (__hip_atomic_load(&ctl->bar_gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
+            __builtin_amdgcn_s_sleep(2);
         __threadfence();
     }
     gen += 1;
     __syncthreads();
 }
 
-__global__ __launch_bounds__(WG) void k_persistent(RoundArgs a, int max_rounds) {
+// One round of the persistent kernel: FirstFit, barrier, conflict test, barrier, and
+// in push mode the split-hub push phase with its barrier.  Returns false when every
+// queue was empty (the colouring is complete).
+__device__ __forceinline__ bool persistent_round(const RoundArgs& a, RoundLds& s, int* boff, int& total,
+                                                 int& gen, int& cmax) {
+    if (threadIdx.x == 0) {
+        int cnt[NB];
+        for (int b = 0; b < NB; ++b) cnt[b] = ld_agent(&a.ctl->cnt[a.par_in][b]);
+        cnt[BSPLIT] = ld_agent(&a.ctl->ccnt[a.par_in]);
+        int t = 0;
+        for (int b = 0; b < NB; ++b) t += cnt[b];
+        total = t;
+        device_plan(cnt, gridDim.x, boff);
+    }
+    __syncthreads();
+    if (total == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->pdone = 1;
+        return false;
+    }
+    assign_phase(a, s, blockIdx.x, boff);
+    grid_sync(a.ctl, gen);
+    detect_phase(a, s, blockIdx.x, boff, cmax);
+    grid_sync(a.ctl, gen);
+    if (a.pushff && boff[BSPLIT + 1] > boff[BSPLIT]) {
+        push_split_phase(a, blockIdx.x, gridDim.x);
+        grid_sync(a.ctl, gen);
+    }
+    return true;
+}
+
+// a_odd / a_even: the same arguments with the worklist parities of odd / even round
+// indices, kept as two constant kernel arguments and used from separate branches
+// (selecting one into a private copy would spill its indexed arrays to scratch).
+__global__ __launch_bounds__(WG) void k_persistent(RoundArgs a_odd, RoundArgs a_even, int first_round,
+                                                   int max_rounds) {
     __shared__ RoundLds s;
     __shared__ int boff[NB + 1];
     __shared__ int total;
     int gen = 0;
     int cmax = 0;
-    for (int r = a.round; r < max_rounds; ++r) {
-        if (threadIdx.x == 0) {
-            int cnt[NB];
-            for (int b = 0; b < NB; ++b) cnt[b] = ld_agent(&a.ctl->cnt[a.par_in][b]);
-            cnt[BSPLIT] = ld_agent(&a.ctl->ccnt[a.par_in]);
-            int t = 0;
-            for (int b = 0; b < NB; ++b) t += cnt[b];
-            total = t;
-            device_plan(cnt, gridDim.x, boff);
-        }
-        __syncthreads();
-        if (total == 0) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->pdone = 1;
-            break;
-        }
-        assign_phase(a, s, blockIdx.x, boff);
-        grid_sync(a.ctl, gen);
-        detect_phase(a, s, blockIdx.x, boff, cmax);
-        grid_sync(a.ctl, gen);
-        const int t = a.par_in;
-        a.par_in = a.par_out;
-        a.par_out = t;
-        const int* tl = a.wl_in;
-        a.wl_in = a.wl_out;
-        a.wl_out = const_cast<int*>(tl);
+    for (int r = first_round; r < max_rounds; ++r) {
+        const bool more = (r & 1) ? persistent_round(a_odd, s, boff, total, gen, cmax)
+                                  : persistent_round(a_even, s, boff, total, gen, cmax);
+        if (!more) break;
     }
     cmax = block_max(cmax, s.red);
-    if (threadIdx.x == 0 && cmax > 0) atomicMax(&a.ctl->maxcolor, cmax);
+    if (threadIdx.x == 0 && cmax > 0) atomicMax(&a_odd.ctl->maxcolor, cmax);
 }
 
 }  // namespace csrcolor

@@ -381,8 +381,20 @@ def concat_graphs(graphs: Sequence[CSR], keep_parts: bool = False) -> BatchedCSR
     return BatchedCSR(G, voff, rowptr, colidx, list(graphs) if keep_parts else None)
 
 
-def batch_graphs(specs: Sequence[GraphSpec], keep_parts: bool = False) -> BatchedCSR:
-    return concat_graphs([s.build() for s in specs], keep_parts=keep_parts)
+def build_graphs(specs: Sequence[GraphSpec], threads: Optional[int] = None) -> List[CSR]:
+    """Build every spec, on a thread pool (each graph is a pure function of its spec)."""
+    import concurrent.futures
+    import os
+    nthr = threads or min(16, os.cpu_count() or 1)
+    if nthr <= 1 or len(specs) <= 1:
+        return [s.build() for s in specs]
+    with concurrent.futures.ThreadPoolExecutor(nthr) as ex:
+        return list(ex.map(lambda sp: sp.build(), specs))
+
+
+def batch_graphs(specs: Sequence[GraphSpec], keep_parts: bool = False,
+                 threads: Optional[int] = None) -> BatchedCSR:
+    return concat_graphs(build_graphs(specs, threads), keep_parts=keep_parts)
 
 
 # ----------------------------------------------------------------------------

@@ -261,3 +261,46 @@ def test_stats_shapes(oracle_mod):
 def test_malformed_input_rejected(oracle_mod):
     with pytest.raises(ValueError):
         oracle_mod.sgr(3, np.array([0, 1, 2, 2]), np.array([1, 5]))
+
+
+def test_degree_rule_golden(oracle_mod):
+    with open(os.path.join(GOLDEN, "sgr_degree_rule.txt")) as f:
+        rows = [l for l in f if l.strip() and not l.startswith("#")]
+    assert len(rows) >= 4
+    for line in rows:
+        name, n, edges, final, rounds = [x.strip() for x in line.split("|")]
+        e = [tuple(int(x) for x in t.split("-")) for t in edges.split()]
+        g = gg.from_edges(int(n), e)
+        res = oracle_mod.sgr(g.n, g.rowptr, g.colidx, rule=oracle_mod.RULE_DEGREE)
+        assert (res.colors + 1).tolist() == [int(x) for x in final.split()], name
+        assert res.rounds == int(rounds), name
+        c2, _, r2, _ = oracle_mod.sgr_numpy(g.n, g.rowptr, g.colidx, rule=1)
+        assert (c2 + 1).tolist() == [int(x) for x in final.split()] and r2 == int(rounds), name
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_degree_rule_cross_check_and_invariants(oracle_mod, seed):
+    n = [9, 40, 150, 600][seed % 4]
+    p = [0.4, 0.15, 0.05, 0.01][seed % 4]
+    g = gg.random_small(n, p, 300 + seed)
+    res = oracle_mod.sgr(g.n, g.rowptr, g.colidx, rule=oracle_mod.RULE_DEGREE)
+    c, nc, r, ws = oracle_mod.sgr_numpy(g.n, g.rowptr, g.colidx, rule=1)
+    assert (c == res.colors).all() and r == res.rounds and list(ws) == res.wsize.tolist()
+    _invariants(oracle_mod, g, res)
+
+
+def test_degree_rule_regular_graph_equals_id_rule(oracle_mod):
+    """On a regular graph every degree ties, so the rule falls back to the id rule."""
+    for g in [gg.cycle(31), gg.complete(12), gg.stencil27(3, 3, 3)]:
+        if len(set(g.degrees().tolist())) == 1:
+            a = oracle_mod.sgr(g.n, g.rowptr, g.colidx, rule=0)
+            b = oracle_mod.sgr(g.n, g.rowptr, g.colidx, rule=1)
+            assert (a.colors == b.colors).all() and a.rounds == b.rounds
+
+
+def test_degree_rule_workloads(oracle_mod):
+    for g in [gg.rmat(12, 16, 2), gg.erdos_renyi(3000, 20000, 2)]:
+        a = oracle_mod.sgr(g.n, g.rowptr, g.colidx, rule=1)
+        c, nc, r, ws = oracle_mod.sgr_numpy(g.n, g.rowptr, g.colidx, rule=1)
+        assert (c == a.colors).all() and r == a.rounds
+        _invariants(oracle_mod, g, a)

@@ -37,7 +37,7 @@ def _run(g, dev, **kw):
 def _assert_parity(g, dev, ref=None, **kw):
     import oracle
     if ref is None:
-        ref = oracle.sgr(g.n, g.rowptr, g.colidx)
+        ref = oracle.sgr(g.n, g.rowptr, g.colidx, rule=kw.get("rule", 0))
     got, nc, st = _run(g, dev, **kw)
     assert got.shape == ref.colors.shape
     bad = np.flatnonzero(got != ref.colors)
@@ -332,3 +332,43 @@ def test_drive_modes_repeat_and_shrink(dev, mode):
     for g in [gg.erdos_renyi(30000, 300000, 8), gg.erdos_renyi(30000, 300000, 8), gg.erdos_renyi(5000, 30000, 9),
               gg.rmat(12, 8, 3)]:
         _assert_parity(g, dev, mode=mode)
+
+
+@pytest.mark.parametrize("firstfit", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_firstfit_variants_match_oracle(dev, firstfit, mode):
+    """FirstFit by rescanning neighbour colours every round (1) and by per-vertex
+    forbidden bitmaps filled when neighbours settle (2) give the oracle's colouring
+    in every drive mode, including hubs that win round 1 (star centred at 0)."""
+    graphs = [gg.erdos_renyi(20000, 160000, 4), gg.rmat(14, 16, 6), gg.stencil27(21, 13, 11),
+              gg.complete(90), gg.star(0, list(range(1, 40001))),
+              _degree_ladder([5, 13, 29, 61, 300, 1500, 2500, 9000], 2), gg.cycle(77)]
+    for g in graphs:
+        _assert_parity(g, dev, mode=mode, firstfit=firstfit)
+
+
+@pytest.mark.parametrize("firstfit", [1, 2])
+def test_firstfit_variants_split_heavy(dev, firstfit):
+    g = gg.rmat(16, 16, 11)
+    _assert_parity(g, dev, firstfit=firstfit, t_split=1024, t_wave=61)
+    got, ref = _assert_parity(gg.complete(1300), dev, firstfit=firstfit, t_split=1024)
+    assert got.tolist() == list(range(1300))
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_degree_rule_matches_oracle(dev, mode):
+    """Heuristic conflict resolve (Sec. 3.2): the smaller degree is requeued, the
+    higher id on equal degree; bit-exact against the oracle's rule 1."""
+    for g in [gg.from_edges(6, [(5, k) for k in range(5)]), gg.path(4),
+              gg.from_edges(4, [(0, 1), (1, 2), (2, 0), (2, 3)]),
+              gg.erdos_renyi(20000, 160000, 5), gg.rmat(14, 16, 7), gg.stencil27(12, 9, 7),
+              _degree_ladder([5, 13, 29, 61, 300, 1500, 2500, 9000], 3),
+              gg.shuffle_rows(gg.rmat(12, 16, 8), 2)]:
+        for ff in (1, 2):
+            _assert_parity(g, dev, rule=1, mode=mode, firstfit=ff)
+
+
+def test_degree_rule_split_and_unsorted(dev):
+    g = gg.rmat(16, 16, 13)
+    _assert_parity(g, dev, rule=1, t_split=1024, t_wave=61)
+    _assert_parity(gg.shuffle_rows(g, 5), dev, rule=1)

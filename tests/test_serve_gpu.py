@@ -1,0 +1,72 @@
+"""Serving on the GPU: continuous batching over several stream slots gives every
+request exactly the colouring it gets alone (tolerance 0), and csrcolor_color_multi
+matches per-graph calls."""
+import numpy as np
+import pytest
+
+from paper_1606_06025_amd import graphs as gg
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1606_06025_amd import _lib
+    _lib.load()
+    return torch.device("cuda:0")
+
+
+def _mix(k, seed):
+    out = []
+    for i in range(k):
+        if i % 2:
+            out.append(gg.rmat(10 + i % 5, 8 + 4 * (i % 4), seed, sub=i))
+        else:
+            out.append(gg.erdos_renyi(1000 + 997 * i, (1000 + 997 * i) * (4 + i % 12), seed, i))
+    return out
+
+
+def test_color_multi_equals_single(dev):
+    import oracle
+    from paper_1606_06025_amd import api
+    gs = _mix(12, 1) + [gg.edgeless(5), gg.complete(40), gg.star(2, [0, 1, 3, 4])]
+    dgs = [(torch.from_numpy(g.rowptr).to(dev), torch.from_numpy(g.colidx).to(dev)) for g in gs]
+    outs, ncol = api.color_multi(dgs)
+    ncol = ncol.cpu().numpy()
+    for i, g in enumerate(gs):
+        ref = oracle.sgr(g.n, g.rowptr, g.colidx)
+        assert (outs[i].cpu().numpy() == ref.colors).all()
+        assert ncol[i] == ref.ncolors
+
+
+def test_color_multi_rejects_bad_graph(dev):
+    from paper_1606_06025_amd import _lib as L, api
+    good = gg.cycle(9)
+    rp = torch.tensor([0, 1, 2], dtype=torch.int32, device=dev)
+    ci = torch.tensor([5, 0], dtype=torch.int32, device=dev)     # id 5 outside its 2-vertex graph
+    with pytest.raises(L.CsrColorError) as e:
+        api.color_multi([(torch.from_numpy(good.rowptr).to(dev), torch.from_numpy(good.colidx).to(dev)), (rp, ci)])
+    assert e.value.status == L.EBADCSR
+
+
+def test_server_alone_vs_mix(dev):
+    """Also the regression case of the first multi-graph call on fresh streams (each
+    slot's workspace starts empty and grows while the union is being built)."""
+    from paper_1606_06025_amd import api, serve
+    gs = _mix(24, 7)
+    # alone: one library call per graph
+    alone = []
+    for g in gs:
+        c, nc, _ = api.color(torch.from_numpy(g.rowptr).to(dev), torch.from_numpy(g.colidx).to(dev))
+        alone.append((c.cpu().numpy(), nc))
+    budget = 6 * max(serve.footprint_bytes(g.n, g.nnz) for g in gs)
+    with serve.ColoringServer(serve.HipBackend(nslots=3), budget, max_batch=8) as srv:
+        reqs, wall = serve.replay(srv, [(g.rowptr, g.colidx) for g in gs], [0.002 * i for i in range(len(gs))])
+        assert srv.peak_bytes <= budget
+    assert max(r.batch_size for r in reqs) > 1
+    for (c, nc), r in zip(alone, reqs):
+        assert r.error is None
+        assert np.array_equal(r.colors, c) and r.ncolors == nc

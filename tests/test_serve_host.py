@@ -1,0 +1,111 @@
+"""Serving scheduler on the host: the CPU oracle stands in for the device.
+
+Checks that admission never lets the admitted HBM footprint exceed the budget, that
+every request gets the colouring it gets alone, that requests arriving while others
+run are still batched and served, that an oversize request is rejected without
+affecting the others, and that a failing request fails alone."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_1606_06025_amd import graphs as gg
+from paper_1606_06025_amd import serve
+
+
+class OracleBackend(serve.Backend):
+    def __init__(self, nslots=2, delay=0.002, fail_on=None):
+        import oracle
+        self.oracle = oracle
+        self.nslots = nslots
+        self.delay = delay
+        self.fail_on = fail_on or set()
+        self.live = 0
+        self.lock = threading.Lock()
+        self.batches = []
+
+    def upload(self, rowptr, colidx):
+        if len(rowptr) - 1 in self.fail_on:
+            raise ValueError("bad graph")
+        with self.lock:
+            self.live += 1
+        return (np.asarray(rowptr), np.asarray(colidx))
+
+    def release(self, handle):
+        if handle is not None:
+            with self.lock:
+                self.live -= 1
+
+    def run_batch(self, slot, handles):
+        self.batches.append(len(handles))
+        time.sleep(self.delay)
+        out = []
+        for rp, ci in handles:
+            r = self.oracle.sgr(len(rp) - 1, rp, ci)
+            out.append((r.colors, r.ncolors))
+        return out
+
+
+def _graphs(k, seed=0):
+    res = []
+    for i in range(k):
+        if i % 3 == 0:
+            g = gg.rmat(8 + i % 4, 8, seed + i)
+        elif i % 3 == 1:
+            g = gg.erdos_renyi(500 + 37 * i, 2500 + 100 * i, seed, i)
+        else:
+            g = gg.stencil27(5 + i % 4, 6, 4)
+        res.append(g)
+    return res
+
+
+def test_results_equal_alone_and_budget_respected(oracle_mod):
+    gs = _graphs(30)
+    fps = [serve.footprint_bytes(g.n, g.nnz) for g in gs]
+    budget = 3 * max(fps)           # forces queueing: at most a few graphs admitted at once
+    be = OracleBackend(nslots=2, delay=0.003)
+    with serve.ColoringServer(be, budget, max_batch=4) as srv:
+        reqs, wall = serve.replay(srv, [(g.rowptr, g.colidx) for g in gs], [0.0005 * i for i in range(len(gs))])
+        assert srv.peak_bytes <= budget
+    assert be.live == 0
+    for g, r in zip(gs, reqs):
+        assert r.error is None
+        ref = oracle_mod.sgr(g.n, g.rowptr, g.colidx)
+        assert (r.colors == ref.colors).all() and r.ncolors == ref.ncolors
+        assert r.latency >= 0 and r.done_time >= r.started >= r.admitted >= r.arrival - 1e-9
+    assert max(be.batches) > 1       # continuous batching actually grouped requests
+    s = serve.latency_summary(reqs)
+    assert s["count"] == len(gs) and s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_oversize_request_rejected_others_served():
+    gs = _graphs(6, seed=3)
+    big = gg.erdos_renyi(20000, 200000, 5)
+    budget = serve.footprint_bytes(big.n, big.nnz) - 1
+    be = OracleBackend(nslots=1)
+    with serve.ColoringServer(be, budget) as srv:
+        rb = srv.submit(big.rowptr, big.colidx)
+        rs = [srv.submit(g.rowptr, g.colidx) for g in gs]
+        for r in rs + [rb]:
+            assert r.wait(30)
+    assert rb.error and all(r.error is None for r in rs)
+
+
+def test_failing_request_fails_alone():
+    gs = _graphs(5, seed=7)
+    bad = gg.cycle(13)
+    be = OracleBackend(nslots=2, fail_on={13})
+    with serve.ColoringServer(be, 1 << 40) as srv:
+        rs = [srv.submit(g.rowptr, g.colidx) for g in gs[:2]]
+        rb = srv.submit(bad.rowptr, bad.colidx)
+        rs += [srv.submit(g.rowptr, g.colidx) for g in gs[2:]]
+        for r in rs + [rb]:
+            assert r.wait(30)
+    assert rb.error and "bad graph" in rb.error
+    assert all(r.error is None for r in rs)
+    assert be.live == 0
+
+
+def test_footprint_model_monotone():
+    assert serve.footprint_bytes(10, 20) < serve.footprint_bytes(11, 20) < serve.footprint_bytes(11, 21)
