@@ -96,6 +96,45 @@ def cpu_baseline(g, budget_s: float = 20.0):
                       f"{per:.2f} s each, single thread"}
 
 
+def copy_probe(mib: int, reps: int = 5) -> int:
+    """A plain device-to-device copy of `mib` MiB, `reps` times: the reference kernel
+    whose FETCH_SIZE / WRITE_SIZE counters calibrate the counter-to-byte factor."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.arange(n, dtype=torch.int32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ok = bool(torch.equal(dst, src))
+    print(json.dumps({"copy_probe_bytes": n * 4, "reps": reps, "ok": ok}), flush=True)
+    return 0 if ok else 1
+
+
+def digest_pmc(path: str) -> int:
+    """Per-kernel sums of the counters in every rocprofv3 counter_collection.csv under
+    `path`: prints one JSON object {kernel: {counter: {"sum", "dispatches", "per_dispatch"}}}."""
+    import csv
+    import glob
+    tab = {}
+    files = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+    for fn in files:
+        with open(fn) as f:
+            for row in csv.DictReader(f):
+                k = row["Kernel_Name"].split("(")[0].split("<")[0].strip()
+                k = k.replace("void ", "").split("::")[-1]
+                c = row["Counter_Name"]
+                e = tab.setdefault(k, {}).setdefault(c, {"sum": 0.0, "dispatches": set()})
+                e["sum"] += float(row["Counter_Value"])
+                e["dispatches"].add(row.get("Dispatch_Id") or row.get("Correlation_Id"))
+    out = {k: {c: {"sum": e["sum"], "dispatches": len(e["dispatches"]),
+                   "per_dispatch": e["sum"] / max(len(e["dispatches"]), 1)} for c, e in v.items()}
+           for k, v in tab.items()}
+    print(json.dumps({"files": len(files), "kernels": out}, indent=1, sort_keys=True), flush=True)
+    return 0 if files else 1
+
+
 def bench_batched(args, dev) -> int:
     """Batched workload: G graphs (half ER, half 27-point stencils) coloured in one
     call on their block-diagonal union; compared with one call per graph."""
@@ -262,7 +301,19 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="pick launch options with paper_1606_06025_amd.tune")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--algo", default="sgr", choices=["sgr", "topo", "jp"],
+                    help="sgr: data-driven worklists (default); topo: topology-driven ablation; "
+                         "jp: Jones-Plassmann independent sets")
+    ap.add_argument("--rule", type=int, default=0, help="conflict rule: 0 = higher id, 1 = smaller degree requeued")
+    ap.add_argument("--jp-seed", type=int, default=1)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--digest-pmc", default="", metavar="DIR",
+                    help="only summarise rocprofv3 counter CSV files under DIR per kernel")
     args = ap.parse_args()
+
+    if args.digest_pmc:
+        return digest_pmc(args.digest_pmc)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build colours one graph on one GPU; runs on more than one GPU "
@@ -276,6 +327,8 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
+    if args.copy_probe:
+        return copy_probe(args.copy_probe)
     _lib.load()
     dev = torch.device("cuda:0")
 
@@ -292,11 +345,15 @@ def main() -> int:
     out = torch.empty(g.n, dtype=torch.int32, device=dev)
     tuned = dict(mode=args.mode, lane_assign=args.lane_assign, lane_detect=args.lane_detect,
                  t_wave=args.t_wave, t_split=args.t_split, blocks_per_cu=args.blocks_per_cu,
-                 sync_every=args.sync_every, firstfit=args.firstfit)
-    if args.autotune:
+                 sync_every=args.sync_every, firstfit=args.firstfit, rule=args.rule)
+    algo = {"sgr": 0, "topo": 1, "jp": 2}[args.algo]
+    if args.autotune and algo == 0:
         from paper_1606_06025_amd import tune
         tuned = tune.tune(rp, ci, log=log)
+        tuned["rule"] = args.rule
         log(f"autotuned options: {tuned}")
+    if algo:
+        tuned.update(algorithm=algo, seed=args.jp_seed if algo == 2 else 0)
     opts = api.make_opts(**tuned) if any(tuned.values()) else None
 
     # warmup (also allocates the library workspace)
@@ -326,7 +383,18 @@ def main() -> int:
     _, _, st = api.color(rp, ci, out=out, opts=opts, stats=True, stats_cap=1 << 16)
     roofline = None
     kern = {}
-    if not args.no_kernel_timing:
+    if algo != 0 or args.rule != 0:
+        # the ablations are reported by throughput and colour count only; the bytes
+        # model below is the one of the default method
+        import oracle
+        if algo == 2:
+            ref = oracle.jp(g.n, g.rowptr, g.colidx, seed=args.jp_seed)
+        else:
+            ref = oracle.sgr(g.n, g.rowptr, g.colidx, rule=args.rule)
+        same = bool((out.cpu().numpy() == ref.colors).all()) and ref.ncolors == ncolors
+        log(f"{args.algo} rule {args.rule}: {ncolors} colours, {st.rounds} rounds, equals oracle: {same}")
+        kern = {"algorithm": args.algo, "equals_oracle": same}
+    elif not args.no_kernel_timing:
         tot_a = tot_d = tot_s = 0.0
         na = nd = 0
         for _ in range(args.steps):

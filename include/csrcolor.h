@@ -75,8 +75,27 @@ typedef enum {
                                   conflict resolve of Sec. 3.2 (fewer rounds on skewed graphs) */
 } csrcolor_rule;
 
+/* Which colouring method runs. */
+typedef enum {
+    CSRCOLOR_ALGO_SGR = 0,       /* data-driven speculative greedy with worklists (Sec. 3.1, Algorithm
+                                    Data-GC; default) */
+    CSRCOLOR_ALGO_SGR_TOPO = 1,  /* topology-driven speculative greedy (Sec. 3.1, Algorithm Topo-GC): every
+                                    round visits all n vertices, one lane per vertex.  Same colouring as
+                                    CSRCOLOR_ALGO_SGR; kept to measure what the worklists save.  LOOP only */
+    CSRCOLOR_ALGO_JP = 2         /* Jones-Plassmann independent sets (Sec. 2.2, Algorithm 3): in round c a
+                                    vertex takes colour c iff its priority beats every neighbour still
+                                    uncoloured.  The priority of v in round c is output number
+                                    c * 2^32 + v of SplitMix64 seeded with seed_hi:seed_lo, compared
+                                    unsigned (the map is a bijection, so priorities never tie).  `rule` and `firstfit` are ignored.
+                                    LOOP only; not for the batched and multi entry points, because the
+                                    priorities depend on vertex ids */
+} csrcolor_algorithm;
+
 /* Tuning and checking options.  Zero-initialise and set what you need; every
- * zero field means "library default".  Only `rule` changes the colouring. */
+ * zero field means "library default".  Only `rule`, `algorithm` and (for JP) the
+ * seed change the colouring.  A field out of its range, or an algorithm other than
+ * CSRCOLOR_ALGO_SGR with mode PERSISTENT or GRAPH (or JP given to the batched or
+ * multi entry points), fails the call with CSRCOLOR_EINVAL. */
 typedef struct {
     int32_t mode;           /* csrcolor_mode */
     int32_t validate;       /* 1: also check symmetry (sorted rows only; costs one search per arc) */
@@ -91,7 +110,10 @@ typedef struct {
                                (as printed in the paper); 2: push: a vertex that settles marks its colour in
                                a per-neighbour bitmap and FirstFit reads that bitmap (same colouring) */
     int32_t rule;           /* conflict rule, csrcolor_rule; CHANGES the colouring (each rule is exact) */
-    int32_t reserved[6];
+    int32_t algorithm;      /* csrcolor_algorithm (default CSRCOLOR_ALGO_SGR) */
+    uint32_t seed_lo;       /* JP: low and high 32 bits of the 64-bit priority seed */
+    uint32_t seed_hi;
+    int32_t reserved[3];
 } csrcolor_opts;
 
 /* Optional run statistics (HOST struct).  Set `cap`, `time_kernels` and the array
@@ -106,7 +128,9 @@ typedef struct {
     int32_t cap;            /* in: capacity of the per-round arrays */
     int32_t time_kernels;   /* in: 1 = bracket every kernel launch with HIP events on `stream` */
     int64_t *wsize;         /* out: |W_r| for r = 0 .. min(rounds, cap)-1 */
-    int64_t *arcs;          /* out: sum of row lengths over W_r (arcs scanned by FirstFit) */
+    int64_t *arcs;          /* out: sum of row lengths over W_r (arcs scanned by FirstFit); for
+                               CSRCOLOR_ALGO_SGR_TOPO and CSRCOLOR_ALGO_JP only arcs[0] (= rowptr[n]) is
+                               filled, later entries are 0 */
     double ms_setup;        /* out (time_kernels): validation and round-1 kernels */
     double ms_assign;       /* out (time_kernels): all FirstFit kernel launches */
     double ms_detect;       /* out (time_kernels): all conflict-test kernel launches */

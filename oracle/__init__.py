@@ -6,10 +6,14 @@ path.  It offers:
 
   * ``sgr``        -- serial speculative-greedy rounds (Sec. 3.1, Algorithm Data-GC with
                       FirstFit and ConflictResolve of Sec. 3), plain C (sgr_oracle.c);
+  * ``sgr_topo``   -- the topology-driven variant (Sec. 3.1, Algorithm Topo-GC), plain C;
+  * ``jp``         -- Jones-Plassmann independent-set colouring (Sec. 2.2, Algorithm 3)
+                      with counter-based SplitMix64 priorities, plain C (jp_oracle.c);
   * ``serial_ff``  -- natural-order sequential greedy (Sec. 2.1, Algorithm 1), plain C;
   * ``conflicts`` / ``non_grundy`` -- checkers for a proper / Grundy colouring;
   * ``sgr_numpy``  -- an independent, vectorised re-implementation of the same rounds
                       (sgr_numpy.py) used to cross-check the C oracle;
+  * ``jp_numpy``   -- the same for JP (jp_numpy.py);
   * ``brute``      -- exhaustive chromatic and Grundy numbers of tiny graphs.
 """
 from __future__ import annotations
@@ -23,16 +27,17 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "sgr_oracle.c")
+_SRCS = [os.path.join(_HERE, "sgr_oracle.c"), os.path.join(_HERE, "jp_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib: Optional[ctypes.CDLL] = None
 
 
 def build(force: bool = True) -> str:
     """Compile the C oracle with gcc -O2 into oracle/liboracle.so."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS)
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp] + _SRCS)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -47,6 +52,14 @@ def _load() -> ctypes.CDLL:
         lib.oracle_sgr.restype = ctypes.c_int
         lib.oracle_sgr_rule.argtypes = [ctypes.c_int32, P, P, P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32]
         lib.oracle_sgr_rule.restype = ctypes.c_int
+        lib.oracle_sgr_topo.argtypes = [ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32]
+        lib.oracle_sgr_topo.restype = ctypes.c_int
+        lib.oracle_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        lib.oracle_splitmix64.restype = ctypes.c_uint64
+        lib.oracle_jp_priority.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32]
+        lib.oracle_jp_priority.restype = ctypes.c_uint64
+        lib.oracle_jp.argtypes = [ctypes.c_int32, P, P, ctypes.c_uint64, P, P, P, P, P, ctypes.c_int32]
+        lib.oracle_jp.restype = ctypes.c_int
         lib.oracle_serial_ff.argtypes = [ctypes.c_int32, P, P, P, P]
         lib.oracle_serial_ff.restype = ctypes.c_int
         lib.oracle_count_conflicts.argtypes = [ctypes.c_int32, P, P, P]
@@ -98,6 +111,68 @@ def sgr(n: int, rowptr, colidx, stats_cap: int = 1 << 16, rule: int = RULE_ID) -
     return SGRResult(out[:n].copy(), int(nc[0]), r, ws[:k].copy(), af[:k].copy(), ac[:k].copy())
 
 
+@dataclasses.dataclass
+class TopoResult:
+    colors: np.ndarray       # int32[n], 0-based
+    ncolors: int
+    rounds: int
+    wsize: np.ndarray        # int64[rounds]: vertices that ran FirstFit
+    visits: np.ndarray       # int64[rounds]: vertices visited (n every round)
+
+
+def sgr_topo(n: int, rowptr, colidx, stats_cap: int = 1 << 16, rule: int = RULE_ID) -> TopoResult:
+    """Topology-driven SGR (Algorithm Topo-GC).  Raises on malformed input."""
+    lib = _load()
+    rp, ci = _as_i32(rowptr), _as_i32(colidx)
+    out = np.zeros(max(n, 1), dtype=np.int32)
+    nc = np.zeros(1, dtype=np.int32)
+    rr = np.zeros(1, dtype=np.int32)
+    ws = np.zeros(stats_cap, dtype=np.int64)
+    vi = np.zeros(stats_cap, dtype=np.int64)
+    rc = lib.oracle_sgr_topo(n, _ptr(rp), _ptr(ci), _ptr(out), _ptr(nc), _ptr(rr), _ptr(ws), _ptr(vi),
+                             stats_cap, rule)
+    if rc != 0:
+        raise ValueError(f"oracle_sgr_topo failed with status {rc}")
+    k = min(int(rr[0]), stats_cap)
+    return TopoResult(out[:n].copy(), int(nc[0]), int(rr[0]), ws[:k].copy(), vi[:k].copy())
+
+
+def splitmix64(seed: int, k: int) -> int:
+    """Output number k (k >= 1) of SplitMix64 seeded with `seed`."""
+    return int(_load().oracle_splitmix64(seed & (2**64 - 1), k & (2**64 - 1)))
+
+
+def jp_priority(seed: int, rnd: int, v: int) -> int:
+    """JP priority of vertex v in round rnd (1-based): SplitMix64 output rnd * 2^32 + v."""
+    return int(_load().oracle_jp_priority(seed & (2**64 - 1), rnd, v))
+
+
+@dataclasses.dataclass
+class JPResult:
+    colors: np.ndarray       # int32[n], 0-based
+    ncolors: int
+    rounds: int
+    wsize: np.ndarray        # int64[rounds]: |W_r|
+    arcs: np.ndarray         # int64[rounds]: sum of row lengths over W_r
+
+
+def jp(n: int, rowptr, colidx, seed: int = 0, stats_cap: int = 1 << 16) -> JPResult:
+    """Jones-Plassmann colouring (Algorithm 3).  Raises on malformed input."""
+    lib = _load()
+    rp, ci = _as_i32(rowptr), _as_i32(colidx)
+    out = np.zeros(max(n, 1), dtype=np.int32)
+    nc = np.zeros(1, dtype=np.int32)
+    rr = np.zeros(1, dtype=np.int32)
+    ws = np.zeros(stats_cap, dtype=np.int64)
+    ar = np.zeros(stats_cap, dtype=np.int64)
+    rc = lib.oracle_jp(n, _ptr(rp), _ptr(ci), seed & (2**64 - 1), _ptr(out), _ptr(nc), _ptr(rr),
+                       _ptr(ws), _ptr(ar), stats_cap)
+    if rc != 0:
+        raise ValueError(f"oracle_jp failed with status {rc}")
+    k = min(int(rr[0]), stats_cap)
+    return JPResult(out[:n].copy(), int(nc[0]), int(rr[0]), ws[:k].copy(), ar[:k].copy())
+
+
 def serial_ff(n: int, rowptr, colidx):
     """Natural-order sequential greedy: returns (colors 0-based, ncolors)."""
     lib = _load()
@@ -145,4 +220,5 @@ def bytes_model(res: SGRResult, n: int) -> int:
 
 
 from .sgr_numpy import sgr_numpy  # noqa: E402
+from .jp_numpy import jp_numpy  # noqa: E402
 from . import brute  # noqa: E402

@@ -155,6 +155,83 @@ int oracle_sgr_rule(int32_t n, const int32_t *rowptr, const int32_t *colidx,
     return 0;
 }
 
+/* Topology-driven variant (Sec. 3.1, Algorithm Topo-GC): every round visits every
+ * vertex; an uncoloured one (colour 0) runs FirstFit against the previous round's
+ * colours, and every vertex not yet marked coloured runs the conflict test and is
+ * marked coloured when it has no conflict.  The loop ends after a round in which no
+ * vertex was uncoloured.  Same readings as oracle_sgr_rule (snapshot FirstFit,
+ * pairwise test, loser cleared, rule 0/1 requeue direction).  Statistics per round:
+ * wsize[r] = vertices that ran FirstFit, visits[r] = vertices visited (always n).
+ * The worklist of the data-driven algorithm is exactly the set of uncoloured
+ * vertices, so the colouring must equal oracle_sgr_rule's. */
+int oracle_sgr_topo(int32_t n, const int32_t *rowptr, const int32_t *colidx,
+                    int32_t *colors_out, int32_t *ncolors_out, int32_t *rounds_out,
+                    int64_t *wsize, int64_t *visits, int32_t stats_cap, int32_t rule)
+{
+    *ncolors_out = 0;
+    *rounds_out = 0;
+    if (n <= 0) return 0;
+    for (int64_t e = 0; e < rowptr[n]; ++e)
+        if (colidx[e] < 0 || colidx[e] >= n) return -2;
+    int32_t *color = calloc((size_t)n, sizeof(int32_t));   /* 0 = uncoloured */
+    int32_t *tent = calloc((size_t)n, sizeof(int32_t));    /* this round's FirstFit result */
+    uint8_t *colored = calloc((size_t)n, 1);
+    uint8_t *lose = calloc((size_t)n, 1);
+    int64_t *stamp = calloc((size_t)n + 2, sizeof(int64_t));
+    if (!color || !tent || !colored || !lose || !stamp) {
+        free(color); free(tent); free(colored); free(lose); free(stamp);
+        return -1;
+    }
+    int32_t r = 0;
+    for (;;) {
+        int64_t ran = 0;
+        /* FirstFit over V for the uncoloured vertices, reading last round's colours */
+        for (int32_t v = 0; v < n; ++v) {
+            if (color[v] != 0) { tent[v] = color[v]; continue; }
+            for (int64_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+                int32_t w = colidx[e];
+                if (w != v) stamp[color[w]] = (int64_t)v + 1;
+            }
+            int32_t c = 1;
+            while (stamp[c] == (int64_t)v + 1) ++c;
+            tent[v] = c;
+            ++ran;
+        }
+        if (ran == 0) break;
+        /* conflict test over V for the vertices not yet marked coloured */
+        for (int32_t v = 0; v < n; ++v) {
+            lose[v] = 0;
+            if (colored[v]) continue;
+            for (int64_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+                int32_t w = colidx[e];
+                if (w != v && tent[w] == tent[v] && beats(rowptr, w, v, rule)) {
+                    lose[v] = 1;
+                    break;
+                }
+            }
+        }
+        for (int32_t v = 0; v < n; ++v) {
+            if (colored[v]) continue;
+            if (lose[v]) color[v] = 0;
+            else { color[v] = tent[v]; colored[v] = 1; }
+        }
+        if (r < stats_cap) {
+            if (wsize) wsize[r] = ran;
+            if (visits) visits[r] = n;
+        }
+        ++r;
+    }
+    int32_t mx = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        colors_out[v] = color[v] - 1;
+        if (color[v] > mx) mx = color[v];
+    }
+    *ncolors_out = mx;
+    *rounds_out = r;
+    free(color); free(tent); free(colored); free(lose); free(stamp);
+    return 0;
+}
+
 /* Sequential greedy colouring in natural vertex order (Sec. 2.1, Algorithm 1):
  * vertex v takes the smallest positive colour not held by an already-coloured
  * neighbour.  Output colours are 0-based. */

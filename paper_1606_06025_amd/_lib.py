@@ -25,6 +25,10 @@ ELIMIT = -7
 RULE_ID = 0
 RULE_DEGREE = 1
 
+ALGO_SGR = 0
+ALGO_SGR_TOPO = 1
+ALGO_JP = 2
+
 MODE_AUTO = 0
 MODE_LOOP = 1
 MODE_PERSISTENT = 2
@@ -39,7 +43,8 @@ class Opts(ctypes.Structure):
                 ("t_split", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("sync_every", ctypes.c_int32), ("lane_assign", ctypes.c_int32),
                 ("lane_detect", ctypes.c_int32), ("firstfit", ctypes.c_int32),
-                ("rule", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("rule", ctypes.c_int32), ("algorithm", ctypes.c_int32), ("seed_lo", ctypes.c_uint32),
+                ("seed_hi", ctypes.c_uint32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):

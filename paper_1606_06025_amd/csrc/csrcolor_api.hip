@@ -21,6 +21,7 @@
 
 #include "../../include/csrcolor.h"
 #include "sgr_kernels.h"
+#include "sgr_topo.h"
 
 namespace csrcolor {
 namespace {
@@ -260,7 +261,22 @@ struct Options {
     int lane_detect = 0xF;    // lane-per-vertex conflict test (early exit) in every tile bucket
     int pushff = 1;           // push-mode FirstFit
     int rule = 0;             // conflict rule (csrcolor_rule)
+    int algo = CSRCOLOR_ALGO_SGR;
+    unsigned long long seed = 0;
 };
+
+// Range checks shared by the entry points; `single` is false for the batched and
+// multi-graph calls, which do not take JP (its priorities depend on global ids).
+bool opts_valid(const csrcolor_opts* o, bool single) {
+    if (!o) return true;
+    if (o->mode < 0 || o->mode > CSRCOLOR_MODE_GRAPH || o->validate < 0 || o->firstfit < 0 || o->firstfit > 2 ||
+        o->rule < 0 || o->rule > 1 || o->algorithm < 0 || o->algorithm > CSRCOLOR_ALGO_JP)
+        return false;
+    if (o->algorithm != CSRCOLOR_ALGO_SGR && (o->mode == CSRCOLOR_MODE_PERSISTENT || o->mode == CSRCOLOR_MODE_GRAPH))
+        return false;
+    if (!single && o->algorithm == CSRCOLOR_ALGO_JP) return false;
+    return true;
+}
 
 Options parse_opts(const csrcolor_opts* o) {
     Options r;
@@ -276,6 +292,13 @@ Options parse_opts(const csrcolor_opts* o) {
     if (o->lane_detect) r.lane_detect = o->lane_detect < 0 ? 0 : (o->lane_detect & 0xF);
     if (o->firstfit) r.pushff = o->firstfit != 1;
     r.rule = o->rule;
+    r.algo = o->algorithm;
+    r.seed = ((unsigned long long)o->seed_hi << 32) | o->seed_lo;
+    if (r.algo != CSRCOLOR_ALGO_SGR) r.mode = CSRCOLOR_MODE_LOOP;
+    if (r.algo == CSRCOLOR_ALGO_JP) {
+        r.rule = RULE_JP;
+        r.pushff = 0;
+    }
     return r;
 }
 
@@ -320,7 +343,8 @@ struct Job {
 int drive_loop(Workspace* w, Job& J, RoundArgs& a, int ub[NB], int budget, KTimer& T) {
     hipStream_t st = w->stream;
     int par = 1;             // parity of the worklist holding W of the next round
-    long long launched = 1;
+    const bool jp = a.rule == RULE_JP;
+    long long launched = jp ? 0 : 1;   // rounds enqueued so far (SGR round 1 is k_round1)
     int k = 2;
     a.dev_plan = 0;
     for (;;) {
@@ -334,7 +358,12 @@ int drive_loop(Workspace* w, Job& J, RoundArgs& a, int ub[NB], int budget, KTime
             a.par_out = par ^ 1;
             a.wl_in = w->wl[par];
             a.wl_out = w->wl[par ^ 1];
-            T.run(1, [&] { k_assign<<<grid, WG, 0, st>>>(a); });
+            if (jp) {
+                a.jpc = (int)launched + 1;    // colour of this JP round
+                T.run(1, [&] { k_jp_prep<<<1, 64, 0, st>>>(a.ctl, a.par_out); });
+            } else {
+                T.run(1, [&] { k_assign<<<grid, WG, 0, st>>>(a); });
+            }
             T.run(2, [&] { k_detect<<<grid, WG, 0, st>>>(a); });
             if (a.pushff && ub[BSPLIT] > 0) {
                 const int pg = std::min(ub[BSPLIT], budget);
@@ -446,46 +475,53 @@ int drive_graph(Workspace* w, Job& J, RoundArgs& a, int budget) {
     return CSRCOLOR_OK;
 }
 
-int run_job(Workspace* w, Job& J, const long long* voff, int G) {
+// Topology-driven rounds: FirstFit and the conflict test over all n vertices; the
+// loser count of the last enqueued round is read back every few rounds.
+int drive_topo(Workspace* w, Job& J, int budget, int st_cap, KTimer& T) {
+    hipStream_t st = w->stream;
+    const int n = J.n;
+    const int cus = num_cus(w->device);
+    // X = 0 (every vertex uncoloured); "losers of round 0" = n, so round 1 is booked
+    T.run(0, [&] {
+        k_fill<<<std::min((n + WG - 1) / WG, cus * 8), WG, 0, st>>>(w->X, n, 0);
+        k_fill<<<1, 64, 0, st>>>(&w->ctl->cnt[1][0], 1, n);
+    });
+    const int grid = (int)std::max<long long>(1, std::min<long long>(((long long)n + WG - 1) / WG, budget));
+    long long* wsz = st_cap ? w->st_wsize : nullptr;
+    int par = 0;
+    long long launched = 0;
+    int k = 2;
+    for (;;) {
+        for (int i = 0; i < k; ++i) {
+            T.run(1, [&] {
+                k_topo_assign<<<grid, WG, 0, st>>>(n, J.rowptr, J.colidx, w->X, w->ctl, par, wsz, st_cap);
+            });
+            T.run(2, [&] {
+                k_topo_detect<<<grid, WG, 0, st>>>(n, J.rowptr, J.colidx, w->X, J.colors_out, w->ctl, par,
+                                                   J.sorted, J.opt.rule);
+            });
+            par ^= 1;
+            ++launched;
+        }
+        HIP_TRY(hipGetLastError());
+        int rc = read_ctl(w);
+        if (rc) return rc;
+        if (w->ctl_h->err) return CSRCOLOR_EHIP;
+        if (w->ctl_h->cnt[par ^ 1][0] == 0) break;
+        if (launched > (long long)n + 2) return CSRCOLOR_ELIMIT;
+        k = std::min(k * 2, J.opt.sync_every);
+    }
+    return CSRCOLOR_OK;
+}
+
+// Worklist rounds (SGR and JP): split-row scratch, push bitmaps, round 1 (JP: the
+// initial worklist), then the rounds in the requested drive mode.
+int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_cap, KTimer& T) {
     const int n = J.n;
     hipStream_t st = w->stream;
-    const int st_cap = J.stats ? std::max(J.stats->cap, 0) : 0;
-    int rc = ensure_capacity(w, (size_t)n, st_cap);
-    if (rc) return rc;
     const int cus = num_cus(w->device);
     const int twave = J.opt.twave;
-
-    KTimer T(w, J.stats && J.stats->time_kernels);
-    T.run(0, [&] { k_init<<<1, WG, 0, st>>>(w->ctl); });
-    const int vblocks = (int)std::min<long long>(((long long)n + WG - 1) / WG, (long long)cus * 4);
-    T.run(0, [&] {
-        k_validate_rows<<<std::max(vblocks, 1), WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl, twave,
-                                                             J.opt.tsplit);
-    });
-    // the arc pass skips itself when the row pass found an error, so one read-back covers both
-    T.run(0, [&] { k_validate_arcs<<<cus * 4, WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl); });
-    if (voff) k_validate_batch<<<std::min(G, cus * 16), WG, 0, st>>>(G, n, voff, J.rowptr, J.colidx, w->ctl);
-    HIP_TRY(hipGetLastError());
-    if ((rc = read_ctl(w))) return rc;
-    if (w->ctl_h->err) return CSRCOLOR_EBADCSR;
-    J.sorted = w->ctl_h->desc_total == w->ctl_h->desc_bound;
-    J.maxdeg = w->ctl_h->maxdeg;
-    if (J.opt.validate >= 1) {
-        if (!J.sorted) return CSRCOLOR_EINVAL;   // symmetry check needs sorted rows
-        k_check_symmetric<<<vblocks, WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl);
-        HIP_TRY(hipGetLastError());
-        if ((rc = read_ctl(w))) return rc;
-        if (w->ctl_h->err & 4) return CSRCOLOR_ENOTSYM;
-        if (w->ctl_h->err) return CSRCOLOR_EBADCSR;
-    }
-    int hist[NB];
-    Seg seg;
-    seg.s[0] = 0;
-    for (int b = 0; b < NB; ++b) {
-        hist[b] = w->ctl_h->hist[b];
-        seg.s[b + 1] = seg.s[b] + hist[b];
-    }
-
+    int rc = 0;
     // split-row scratch: cstart[2] (hubs), owner[2] (chunks), hub bitmaps, done counters, lost flags
     const int nhub = hist[BSPLIT];
     const int nchunk = w->ctl_h->hchunks;
@@ -517,7 +553,7 @@ int run_job(Workspace* w, Job& J, const long long* voff, int G) {
     T.run(0, [&] {
         k_round1<<<r1blocks, WG, 0, st>>>(n, J.rowptr, J.colidx, w->X, J.colors_out, w->wl[1], w->ctl,
                                           J.sorted, twave, J.opt.tsplit, seg, cstart1, owner1, F,
-                                          w->ctl_h->nnz, J.opt.rule);
+                                          w->ctl_h->nnz, J.opt.rule, J.opt.algo == CSRCOLOR_ALGO_JP);
     });
     HIP_TRY(hipGetLastError());
 
@@ -564,6 +600,56 @@ int run_job(Workspace* w, Job& J, const long long* voff, int G) {
         for (int b = 0; b < NB; ++b) ub[b] = hist[b];
         ub[BSPLIT] = nchunk;
         rc = drive_loop(w, J, a, ub, budget, T);
+    }
+    return rc;
+}
+
+int run_job(Workspace* w, Job& J, const long long* voff, int G) {
+    const int n = J.n;
+    hipStream_t st = w->stream;
+    const int st_cap = J.stats ? std::max(J.stats->cap, 0) : 0;
+    int rc = ensure_capacity(w, (size_t)n, st_cap);
+    if (rc) return rc;
+    const int cus = num_cus(w->device);
+    const int twave = J.opt.twave;
+
+    KTimer T(w, J.stats && J.stats->time_kernels);
+    T.run(0, [&] { k_init<<<1, WG, 0, st>>>(w->ctl); });
+    const int vblocks = (int)std::min<long long>(((long long)n + WG - 1) / WG, (long long)cus * 4);
+    T.run(0, [&] {
+        k_validate_rows<<<std::max(vblocks, 1), WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl, twave,
+                                                             J.opt.tsplit);
+    });
+    // the arc pass skips itself when the row pass found an error, so one read-back covers both
+    T.run(0, [&] { k_validate_arcs<<<cus * 4, WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl); });
+    if (voff) k_validate_batch<<<std::min(G, cus * 16), WG, 0, st>>>(G, n, voff, J.rowptr, J.colidx, w->ctl);
+    HIP_TRY(hipGetLastError());
+    if ((rc = read_ctl(w))) return rc;
+    if (w->ctl_h->err) return CSRCOLOR_EBADCSR;
+    J.sorted = w->ctl_h->desc_total == w->ctl_h->desc_bound;
+    J.maxdeg = w->ctl_h->maxdeg;
+    if (J.opt.validate >= 1) {
+        if (!J.sorted) return CSRCOLOR_EINVAL;   // symmetry check needs sorted rows
+        k_check_symmetric<<<vblocks, WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl);
+        HIP_TRY(hipGetLastError());
+        if ((rc = read_ctl(w))) return rc;
+        if (w->ctl_h->err & 4) return CSRCOLOR_ENOTSYM;
+        if (w->ctl_h->err) return CSRCOLOR_EBADCSR;
+    }
+    int hist[NB];
+    Seg seg;
+    seg.s[0] = 0;
+    for (int b = 0; b < NB; ++b) {
+        hist[b] = w->ctl_h->hist[b];
+        seg.s[b + 1] = seg.s[b] + hist[b];
+    }
+
+    if (J.opt.algo == CSRCOLOR_ALGO_SGR_TOPO) {
+        if (st_cap) HIP_TRY(hipMemsetAsync(w->st_wsize, 0, st_cap * sizeof(long long), st));
+        if (st_cap) HIP_TRY(hipMemsetAsync(w->st_arcs, 0, st_cap * sizeof(long long), st));
+        rc = drive_topo(w, J, cus * J.opt.blocks_per_cu, st_cap, T);
+    } else {
+        rc = run_rounds(w, J, hist, seg, st_cap, T);
     }
     if (rc) return rc;
     if ((rc = read_ctl(w))) return rc;
@@ -617,9 +703,7 @@ int csrcolor_color_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx, i
                       int32_t* ncolors_host, const csrcolor_opts* opts, csrcolor_stats* stats,
                       hipStream_t stream) {
     if (n < 0) return CSRCOLOR_EINVAL;
-    if (opts && (opts->mode < 0 || opts->mode > CSRCOLOR_MODE_GRAPH || opts->validate < 0 ||
-                 opts->firstfit < 0 || opts->firstfit > 2 || opts->rule < 0 || opts->rule > 1))
-        return CSRCOLOR_EINVAL;
+    if (!opts_valid(opts, true)) return CSRCOLOR_EINVAL;
     if (stats && stats->cap > 0 && stats->cap > (1 << 24)) return CSRCOLOR_EINVAL;
     if (n == 0) {
         if (ncolors_host) *ncolors_host = 0;
@@ -660,8 +744,7 @@ int csrcolor_color_batched(int32_t G, int32_t n_total, const int64_t* voff, cons
     if (G < 0 || n_total < 0) return CSRCOLOR_EINVAL;
     if (G == 0) return n_total == 0 ? CSRCOLOR_OK : CSRCOLOR_EINVAL;
     if (!voff || !ncolors_out) return CSRCOLOR_EINVAL;
-    if (opts && (opts->mode < 0 || opts->mode > CSRCOLOR_MODE_GRAPH || opts->validate < 0))
-        return CSRCOLOR_EINVAL;
+    if (!opts_valid(opts, false)) return CSRCOLOR_EINVAL;
     if (n_total > 0 && (!rowptr || !colors_out)) return CSRCOLOR_EINVAL;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return CSRCOLOR_EHIP;
@@ -699,9 +782,7 @@ int csrcolor_color_multi(int32_t G, const int32_t* n_host, const int64_t* nnz_ho
     if (G == 0) return CSRCOLOR_OK;
     if (!n_host || !nnz_host || !rowptr_host || !colidx_host || !colors_host || !ncolors_out)
         return CSRCOLOR_EINVAL;
-    if (opts && (opts->mode < 0 || opts->mode > CSRCOLOR_MODE_GRAPH || opts->validate < 0 ||
-                 opts->firstfit < 0 || opts->firstfit > 2 || opts->rule < 0 || opts->rule > 1))
-        return CSRCOLOR_EINVAL;
+    if (!opts_valid(opts, false)) return CSRCOLOR_EINVAL;
     long long N = 0, E = 0;
     for (int g = 0; g < G; ++g) {
         if (n_host[g] < 0 || nnz_host[g] < 0) return CSRCOLOR_EINVAL;

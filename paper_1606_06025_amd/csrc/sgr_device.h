@@ -73,6 +73,25 @@ __device__ __forceinline__ void push_colour(unsigned* F, const int* __restrict__
     }
 }
 
+// Internal rule number of the Jones-Plassmann independent-set colouring (Sec. 2.2,
+// Algorithm 3): in round c a worklist vertex takes colour c iff its priority exceeds
+// that of every neighbour still uncoloured (colour 0) or coloured this round (c).
+constexpr int RULE_JP = 2;
+
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output number k of the generator
+// seeded with s is the published output function applied to s + k * golden gamma.
+__host__ __device__ __forceinline__ unsigned long long splitmix64(unsigned long long s, unsigned long long k) {
+    unsigned long long z = s + k * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// JP priority of vertex v in round c: output number c * 2^32 + v, compared unsigned.
+__host__ __device__ __forceinline__ unsigned long long jp_prio(unsigned long long seed, int c, int v) {
+    return splitmix64(seed, ((unsigned long long)(unsigned)c << 32) + (unsigned)v);
+}
+
 // Device-resident control block.
 struct Ctl {
     int cnt[2][8];      // worklist length per bucket, double-buffered by round parity
@@ -125,6 +144,9 @@ struct RoundArgs {
     // conflict rule: 0 = the higher id is requeued; 1 = the smaller degree (row
     // length) is requeued, the higher id on equal degree (heuristic of Sec. 3.2)
     int rule;
+    // JP (rule RULE_JP): this round's colour and the priority generator's seed
+    int jpc;
+    unsigned long long seed;
     // split bucket: per queued hub its first chunk; per chunk the hub's queue entry;
     // per queue entry a colour bitmap, a finished-chunk counter and a lost flag
     int* cstart[2];
@@ -138,6 +160,22 @@ struct RoundArgs {
     int seg[NB + 1];    // bucket segment offsets inside the worklist arrays
     int boff[NB + 1];   // block offsets of each bucket inside the grid
 };
+
+// Tentative colour of worklist vertex v: the FirstFit result in X, or under JP the
+// colour of the round.
+__device__ __forceinline__ int tentative(const RoundArgs& a, int v) {
+    return a.rule == RULE_JP ? a.jpc : (a.X[v] & CMASK);
+}
+
+// Is worklist vertex v (tentative colour cv, degree dv) requeued because of row entry
+// w (-1 = none)?  SGR rules: same tentative colour and w beats v.  JP: w is still
+// competing this round and v's priority does not exceed w's (a tie blocks both).
+__device__ __forceinline__ bool loses_to(const RoundArgs& a, int w, int v, int cv, int dv) {
+    if (a.rule != RULE_JP) return conflict(a.rule, a.rowptr, a.X, w, v, cv, dv);
+    if (w < 0 || w == v) return false;
+    const int xw = a.X[w];
+    return (xw == 0 || xw >= cv) && jp_prio(a.seed, cv, v) <= jp_prio(a.seed, cv, w);
+}
 
 __device__ __forceinline__ unsigned long long lanemask_lt() {
     const int l = __lane_id();

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
                                                const int* __restrict__ colidx, int* X, int* out,
                                                int* wl1, Ctl* ctl, int sorted, int twave, int tsplit,
                                                Seg seg, int* cstart1, int* owner1, unsigned* F, int nnz,
-                                               int rule) {
+                                               int rule, int jp) {
     constexpr int ITER = 4;
     __shared__ int buf[WAVES][NB][ITER * 64];
     __shared__ int wcnt[WAVES][NB];
@@ -121,7 +121,10 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
     const int lane = __lane_id();
     const int wv = threadIdx.x >> 6;
     int cnt[NB] = {};
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->rounds = 1;   // this is round 1
+    // SGR: this is round 1.  JP: this only builds W_1 (every vertex with a neighbour;
+    // an isolated vertex is alone in its neighbourhood and takes colour 1 here), and
+    // the conflict-test launches count the rounds.
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->rounds = jp ? 0 : 1;
     const long long chunk0 = (long long)blockIdx.x * (ITER * WG);
     for (int it = 0; it < ITER; ++it) {
         // wavefront wv owns the 64*ITER consecutive vertices starting at chunk0 + wv*64*ITER,
@@ -134,7 +137,9 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
         if (vv < n) {
             const int v = (int)vv;
             const int beg = rowptr[v], end = rowptr[v + 1];
-            if (end > beg) {
+            if (jp) {
+                lose = end > beg;
+            } else if (end > beg) {
                 if (rule == 0 && sorted) {
                     lose = colidx[beg] < v;
                 } else {
@@ -146,7 +151,7 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
                 }
             }
             if (lose) {
-                X[v] = FLAG | 1;
+                X[v] = jp ? 0 : (FLAG | 1);
                 bkt = bucket_of(end - beg, twave, tsplit);
                 if (bkt == BSPLIT) {
                     // split rows are few: one queue slot and one chunk range per vertex

@@ -637,7 +637,7 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
             if (v_l >= 0) {
                 beg_l = a.rowptr[v_l];
                 end_l = a.rowptr[v_l + 1];
-                cv_l = a.X[v_l] & CMASK;
+                cv_l = tentative(a, v_l);
             }
             const int nsub = (nv + V - 1) / V;
             for (int sstep = 0; sstep < nsub; ++sstep) {
@@ -650,7 +650,7 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
                 load_quad(a.colidx, a.nnz, beg, end, q, w);
                 bool hit = false;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) hit |= conflict(a.rule, a.rowptr, a.X, w[k], v, cv, end - beg);
+                for (int k = 0; k < 4; ++k) hit |= loses_to(a, w[k], v, cv, end - beg);
                 const bool lost = ((__ballot(hit) >> gshift) & gmask) != 0;
                 if (q == 0) res[j] = lost;
             }
@@ -688,7 +688,7 @@ __device__ __forceinline__ void detect_lanes(const RoundArgs& a, const int* list
             if (v_l >= 0) {
                 beg = a.rowptr[v_l];
                 end = a.rowptr[v_l + 1];
-                cv = a.X[v_l] & CMASK;
+                cv = tentative(a, v_l);
             }
             const int nq = end > beg ? (((end - 1 + mis) >> 2) - ((beg + mis) >> 2) + 1) : 0;
             bool lost = false;
@@ -701,7 +701,7 @@ __device__ __forceinline__ void detect_lanes(const RoundArgs& a, const int* list
                     if (w[k] >= 0) {
                         if (a.rule == 0 && w[k] >= v_l) {
                             stop |= a.sorted != 0;
-                        } else if (conflict(a.rule, a.rowptr, a.X, w[k], v_l, cv, end - beg)) {
+                        } else if (loses_to(a, w[k], v_l, cv, end - beg)) {
                             lost = true;
                         }
                     }
@@ -738,7 +738,7 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
             if (v_l >= 0) {
                 beg_l = a.rowptr[v_l];
                 end_l = a.rowptr[v_l + 1];
-                cv_l = a.X[v_l] & CMASK;
+                cv_l = tentative(a, v_l);
             }
             bool lost_l = false;
             for (int j = 0; j < nv; ++j) {
@@ -754,7 +754,7 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
                     bool hit = false, stop = false;
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        hit |= conflict(a.rule, a.rowptr, a.X, w[k], v, cv, end - beg);
+                        hit |= loses_to(a, w[k], v, cv, end - beg);
                         stop |= a.sorted && a.rule == 0 && w[k] >= v;
                     }
                     if (__ballot(hit)) {
@@ -792,7 +792,7 @@ __device__ __forceinline__ void detect_wg(const RoundArgs& a, const int* list, i
         if (i >= cnt) break;
         const int v = list[i];
         const int beg = a.rowptr[v], end = a.rowptr[v + 1];
-        const int cv = a.X[v] & CMASK;
+        const int cv = tentative(a, v);
         const int nq = ((end - beg) + 3 + 3) / 4 + 1;
         bool lost = false;
         for (int q0 = 0; q0 < nq; q0 += WG) {
@@ -801,7 +801,7 @@ __device__ __forceinline__ void detect_wg(const RoundArgs& a, const int* list, i
             bool hit = false, stop = false;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                hit |= conflict(a.rule, a.rowptr, a.X, w[k], v, cv, end - beg);
+                hit |= loses_to(a, w[k], v, cv, end - beg);
                 stop |= a.sorted && a.rule == 0 && w[k] >= v;
             }
             const int anyhit = __syncthreads_or(hit);
@@ -842,7 +842,7 @@ __device__ __forceinline__ void detect_split(const RoundArgs& a, const int* list
         const int rb = a.rowptr[v], re = a.rowptr[v + 1];
         const int nch = split_chunks(re - rb);
         const int beg = rb + k * SPLIT_CH, end = min(beg + SPLIT_CH, re);
-        const int cv = a.X[v] & CMASK;
+        const int cv = tentative(a, v);
         bool hit = false;
         const bool skip = ld_agent(&a.hublost[p]) != 0 || (a.rule == 0 && a.sorted && a.colidx[beg] >= v);
         if (!skip) {
@@ -851,7 +851,7 @@ __device__ __forceinline__ void detect_split(const RoundArgs& a, const int* list
                 int w[4];
                 load_quad(a.colidx, a.nnz, beg, end, q0 + tid, w);
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk) hit |= conflict(a.rule, a.rowptr, a.X, w[kk], v, cv, re - rb);
+                for (int kk = 0; kk < 4; ++kk) hit |= loses_to(a, w[kk], v, cv, re - rb);
             }
         }
         const int anyhit = __syncthreads_or(hit);
@@ -923,6 +923,17 @@ __device__ __forceinline__ void detect_phase(const RoundArgs& a, RoundLds& s, in
             default: detect_split(a, list, a.ctl->ccnt[a.par_in], j, nbk, s, outl, cnt_out, cmax); break;
         }
     }
+}
+
+// JP rounds have no FirstFit phase, whose first block otherwise clears the output
+// queue counters and the conflict-test work counters of the round.
+__global__ void k_jp_prep(Ctl* ctl, int par_out) {
+    const int k = threadIdx.x;
+    if (k < NB) {
+        ctl->cnt[par_out][k] = 0;
+        ctl->dyn[1][k] = 0;
+    }
+    if (k == 0) ctl->ccnt[par_out] = 0;
 }
 
 __global__ __launch_bounds__(WG) void k_detect(RoundArgs a) {

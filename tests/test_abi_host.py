@@ -66,8 +66,39 @@ def test_empty_graph_is_host_only(lib):
     assert st.rounds == 0 and st.ncolors == 0
 
 
+def test_algorithm_option_errors_without_device_work(lib):
+    def opts(**kw):
+        o = L.Opts()
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return ctypes.byref(o)
+    ex = lambda o: lib.csrcolor_color_ex(3, 1, 1, 1, None, o, None, None)
+    assert ex(opts(algorithm=3)) == L.EINVAL
+    assert ex(opts(algorithm=-1)) == L.EINVAL
+    assert ex(opts(rule=2)) == L.EINVAL
+    assert ex(opts(firstfit=3)) == L.EINVAL
+    for algo in (L.ALGO_SGR_TOPO, L.ALGO_JP):
+        for mode in (L.MODE_PERSISTENT, L.MODE_GRAPH):
+            assert ex(opts(algorithm=algo, mode=mode)) == L.EINVAL
+    # JP priorities depend on global ids, so the batched and multi entry points refuse it
+    assert lib.csrcolor_color_batched(1, 3, 1, 1, 1, 1, 1, opts(algorithm=L.ALGO_JP), None) == L.EINVAL
+    assert lib.csrcolor_color_batched(1, 3, 1, 1, 1, 1, 1, opts(rule=5), None) == L.EINVAL
+    n = (ctypes.c_int32 * 1)(3)
+    m = (ctypes.c_int64 * 1)(0)
+    p = (ctypes.c_void_p * 1)(1)
+    assert lib.csrcolor_color_multi(1, n, m, p, p, p, 1, opts(algorithm=L.ALGO_JP), None) == L.EINVAL
+
+
+def _header_struct_fields(name):
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + ";", txt).group(1)
+    return re.findall(r"\b(\w+)\s*(?:\[\d+\])?;", body)
+
+
 def test_struct_layouts_match_header():
-    # csrcolor_opts: 8 int32 + 8 reserved
+    # csrcolor_opts: 16 x 32-bit fields (10 options, algorithm, two seed halves, 3 reserved)
     # csrcolor_stats: 4 int32, int64, 2 int32, 2 pointers, 3 double, 2 int32
     assert ctypes.sizeof(L.Opts) == 16 * 4
     assert ctypes.sizeof(L.Stats) == 4 * 4 + 8 + 2 * 4 + 2 * 8 + 3 * 8 + 2 * 4
+    assert _header_struct_fields("csrcolor_opts") == [f[0] for f in L.Opts._fields_]
+    assert _header_struct_fields("csrcolor_stats") == [f[0] for f in L.Stats._fields_]
