@@ -200,27 +200,15 @@ def _rmat_chunk(key: np.uint64, start: int, cnt: int, scale: int, nh: int,
     return u, v
 
 
-def rmat(scale: int, edge_factor: int, seed: int, abcd: Sequence[float] = RMAT_DEFAULT,
-         permute: bool = True, sub: int = 0, chunk: int = 1 << 22, threads: Optional[int] = None) -> CSR:
-    """R-MAT graph (Sec. 4): 2^scale vertices, edge_factor * 2^scale edge samples.
-
-    Each sample picks one of four quadrants per level with probabilities (a, b, c, d)
-    (32-bit thresholds), which fixes one bit of the row and one of the column.  No
-    noise is added.  With ``permute`` the vertex ids are relabelled by a seeded random
-    permutation.  The samples are symmetrised; self-loops and duplicates dropped.
-    Chunks of samples are drawn on a thread pool; the result does not depend on the
-    chunk size or the thread count (counter-based draws)."""
+def _rmat_samples(scale: int, m: int, key: np.uint64, abcd: Sequence[float], chunk: int,
+                  threads: Optional[int]) -> Tuple[np.ndarray, np.ndarray]:
+    """Endpoints of R-MAT samples 0 .. m-1 of stream `key` at `scale` levels."""
     import concurrent.futures
     import os
-    if scale > 30:
-        raise ValueError("scale must be <= 30 for int32 ids")
-    n = 1 << scale
-    m = edge_factor * n
     a, b, c, _d = abcd
     t1 = np.uint32(min(int(a * 2 ** 32), 2 ** 32 - 1))
     t2 = np.uint32(min(int((a + b) * 2 ** 32), 2 ** 32 - 1))
     t3 = np.uint32(min(int((a + b + c) * 2 ** 32), 2 ** 32 - 1))
-    key = stream_key(seed, STREAM_RMAT_BITS, sub)
     nh = (scale + 1) // 2                      # two 32-bit level draws per uint64
     starts = list(range(0, m, chunk))
     nthr = threads or min(16, os.cpu_count() or 1)
@@ -239,11 +227,64 @@ def rmat(scale: int, edge_factor: int, seed: int, abcd: Sequence[float] = RMAT_D
     else:
         for st in starts:
             work(st)
+    return u, v
+
+
+def _permutation(seed: int, n: int, sub: int) -> np.ndarray:
+    """newid[old] of a seeded random relabelling of n ids."""
+    pk = draws(stream_key(seed, STREAM_RMAT_PERM, sub), 0, n)
+    order = np.argsort(pk, kind="stable")
+    newid = np.empty(n, dtype=np.int64)
+    newid[order] = np.arange(n, dtype=np.int64)
+    return newid
+
+
+RMAT_ER = (0.25, 0.25, 0.25, 0.25)     # Sec. 4: Rmat-er
+RMAT_G = (0.45, 0.15, 0.15, 0.25)      # Sec. 4: Rmat-g
+
+
+def rmat_n(n: int, avg_degree: float, seed: int, abcd: Sequence[float] = RMAT_ER, sub: int = 0,
+           chunk: int = 1 << 22, threads: Optional[int] = None) -> CSR:
+    """R-MAT graph with any vertex count n and a target average degree (the size and
+    density sweeps of Sec. 4): samples are drawn on 2^s >= n ids, the ids relabelled by
+    a seeded random permutation, and only samples with both endpoints below n kept.
+    round(n * avg_degree / 2 * (2^s / n)^2) samples are drawn, so about n * avg_degree / 2
+    of them survive the restriction; after symmetrising and dropping self-loops and
+    duplicates the average degree is slightly below the target."""
+    if n < 2:
+        raise ValueError("n must be >= 2")
+    scale = max(1, int(np.ceil(np.log2(n))))
+    if scale > 30:
+        raise ValueError("n must be <= 2^30")
+    N = 1 << scale
+    m = int(round(n * avg_degree / 2.0 * (N / n) ** 2))
+    key = stream_key(seed, STREAM_RMAT_BITS, 1000 + sub)
+    u, v = _rmat_samples(scale, m, key, abcd, chunk, threads)
+    newid = _permutation(seed, N, 1000 + sub)
+    u = newid[u]
+    v = newid[v]
+    keep = (u < n) & (v < n)
+    tag = "er" if tuple(abcd) == RMAT_ER else ("g" if tuple(abcd) == RMAT_G else "x")
+    return csr_from_arcs(n, u[keep], v[keep], name=f"rmat{tag}_n{n}_d{avg_degree:g}_s{seed}")
+
+
+def rmat(scale: int, edge_factor: int, seed: int, abcd: Sequence[float] = RMAT_DEFAULT,
+         permute: bool = True, sub: int = 0, chunk: int = 1 << 22, threads: Optional[int] = None) -> CSR:
+    """R-MAT graph (Sec. 4): 2^scale vertices, edge_factor * 2^scale edge samples.
+
+    Each sample picks one of four quadrants per level with probabilities (a, b, c, d)
+    (32-bit thresholds), which fixes one bit of the row and one of the column.  No
+    noise is added.  With ``permute`` the vertex ids are relabelled by a seeded random
+    permutation.  The samples are symmetrised; self-loops and duplicates dropped.
+    Chunks of samples are drawn on a thread pool; the result does not depend on the
+    chunk size or the thread count (counter-based draws)."""
+    if scale > 30:
+        raise ValueError("scale must be <= 30 for int32 ids")
+    n = 1 << scale
+    m = edge_factor * n
+    u, v = _rmat_samples(scale, m, stream_key(seed, STREAM_RMAT_BITS, sub), abcd, chunk, threads)
     if permute:
-        pk = draws(stream_key(seed, STREAM_RMAT_PERM, sub), 0, n)
-        order = np.argsort(pk, kind="stable")
-        newid = np.empty(n, dtype=np.int64)
-        newid[order] = np.arange(n, dtype=np.int64)
+        newid = _permutation(seed, n, sub)
         u = newid[u]
         v = newid[v]
     return csr_from_arcs(n, u, v, name=f"rmat_s{scale}_ef{edge_factor}_s{seed}")

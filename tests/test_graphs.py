@@ -101,3 +101,26 @@ def test_serve_stream_poisson():
             assert 10 <= r.spec.params[0] <= 20 and 8 <= r.spec.params[1] <= 32
         else:
             assert 1000 <= r.spec.params[0] <= 1e6
+
+
+@pytest.mark.parametrize("n,d,abcd", [(1000, 10, gg.RMAT_ER), (3000, 4, gg.RMAT_G), (5000, 20, gg.RMAT_ER),
+                                      (2, 3, gg.RMAT_G)])
+def test_rmat_n_sweep_graphs(n, d, abcd):
+    g = gg.rmat_n(n, d, 5, abcd=abcd)
+    assert g.n == n and g.rowptr[0] == 0 and np.all(np.diff(g.rowptr) >= 0)
+    assert g.colidx.min(initial=0) >= 0 and (g.nnz == 0 or g.colidx.max() < n)
+    src = np.repeat(np.arange(n), np.diff(g.rowptr))
+    assert not np.any(src == g.colidx)
+    fwd = set(zip(src.tolist(), g.colidx.tolist()))
+    assert all((w, v) in fwd for v, w in fwd)
+    if n >= 1000:
+        # duplicates and the id restriction cost a little; skewed parameters cost more
+        assert 0.6 * d <= g.nnz / n <= 1.05 * d
+    h = gg.rmat_n(n, d, 5, abcd=abcd)
+    assert np.array_equal(g.colidx, h.colidx)
+
+
+def test_rmat_n_skew():
+    er = gg.rmat_n(1 << 15, 10, 1, abcd=gg.RMAT_ER)
+    rg = gg.rmat_n(1 << 15, 10, 1, abcd=gg.RMAT_G)
+    assert rg.max_degree() > 3 * er.max_degree()
