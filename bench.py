@@ -70,6 +70,33 @@ def detect_bytes(wsize, arcs_cr, pushed_arcs: int, push: bool) -> int:
     return b + (20 * pushed_arcs if push else 0)
 
 
+def kernel_source_digest() -> str:
+    """sha256 over the HIP sources of the library: counter readings taken on other
+    sources no longer describe the kernels."""
+    import hashlib
+    import glob
+    h = hashlib.sha256()
+    for fn in sorted(glob.glob(os.path.join(ROOT, "paper_1606_06025_amd", "csrc", "*"))):
+        with open(fn, "rb") as f:
+            h.update(os.path.basename(fn).encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary of this
+    workload (profiles/traffic_<workload>.json), or None when there is none or the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha256") != kernel_source_digest() or kernel not in t.get("kernels", {}):
+        return None
+    k = t["kernels"][kernel]
+    return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+
+
 def oracle_stats(g, workload: str):
     """Per-round statistics of the oracle (stored digests when available)."""
     import oracle
@@ -111,8 +138,60 @@ def copy_probe(mib: int, reps: int = 5) -> int:
         dst.copy_(src)
     torch.cuda.synchronize()
     ok = bool(torch.equal(dst, src))
+    # an elementwise kernel that reads and writes the same sizes, in case the runtime
+    # serves the device copy without a kernel dispatch
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes": n * 4, "reps": reps, "ok": ok}), flush=True)
     return 0 if ok else 1
+
+
+def traffic_summary(workload: str, fetch_dir: str, write_dir: str, cfetch_dir: str, cwrite_dir: str,
+                    copy_mib: int) -> int:
+    """Writes profiles/traffic_<workload>.json from four rocprofv3 --pmc runs: the
+    workload's FETCH_SIZE and WRITE_SIZE (KiB per dispatch) and the same counters for
+    the copy probe of copy_mib MiB, whose known size gives the counter-to-byte factor."""
+    import io
+    import contextlib
+
+    def dig(d):
+        buf = io.StringIO()
+        with contextlib.redirect_stdout(buf):
+            digest_pmc(d)
+        return json.loads(buf.getvalue())["kernels"]
+
+    probe = copy_mib * (1 << 20)
+
+    def factor(d, counter):
+        ks = dig(d)
+        name = next((k for k in ks if "copy" in k.lower() and counter in ks[k]), None)
+        name = name or next((k for k in ks if "neg" in k.lower() and counter in ks[k]), None)
+        if name is None:
+            raise SystemExit(f"no copy kernel with {counter} in {d}")
+        return ks[name][counter]["per_dispatch"] * 1024.0 / probe, name
+
+    ff, fname = factor(cfetch_dir, "FETCH_SIZE")
+    wf, wname = factor(cwrite_dir, "WRITE_SIZE")
+    fk, wk = dig(fetch_dir), dig(write_dir)
+    out = {"workload": workload, "source_sha256": kernel_source_digest(),
+           "copy_probe_bytes": probe, "copy_kernel": [fname, wname],
+           "fetch_factor": ff, "write_factor": wf, "kernels": {}}
+    for k in sorted(set(fk) & set(wk)):
+        if "FETCH_SIZE" not in fk[k] or "WRITE_SIZE" not in wk[k]:
+            continue
+        fd, wd = fk[k]["FETCH_SIZE"], wk[k]["WRITE_SIZE"]
+        out["kernels"][k] = {"dispatches": fd["dispatches"],
+                             "fetch_kib_per_dispatch": fd["per_dispatch"],
+                             "write_kib_per_dispatch": wd["per_dispatch"],
+                             "fetch_bytes_per_launch": fd["per_dispatch"] * 1024.0 / ff,
+                             "write_bytes_per_launch": wd["per_dispatch"] * 1024.0 / wf}
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    print(json.dumps(out, indent=1, sort_keys=True))
+    return 0
 
 
 def digest_pmc(path: str) -> int:
@@ -375,10 +454,15 @@ def main() -> int:
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--digest-pmc", default="", metavar="DIR",
                     help="only summarise rocprofv3 counter CSV files under DIR per kernel")
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="only write profiles/traffic_<workload>.json from four rocprofv3 --pmc output dirs")
+    ap.add_argument("--copy-mib", type=int, default=256, help="size of the copy probe behind --traffic-summary")
     args = ap.parse_args()
 
     if args.digest_pmc:
         return digest_pmc(args.digest_pmc)
+    if args.traffic_summary:
+        return traffic_summary(args.workload, *args.traffic_summary, copy_mib=args.copy_mib)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build colours one graph on one GPU; runs on more than one GPU "
@@ -489,7 +573,7 @@ def main() -> int:
         achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if nl else 0.0
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": None, "bytes_per_launch": round(bytes_per_launch),
+                    "traffic": measured_traffic(args.workload, dom), "bytes_per_launch": round(bytes_per_launch),
                     "avg_launch_us": round(avg_launch_ms * 1e3, 2),
                     "launches_per_step": launches_per_step,
                     "other_kernels_gbs": {k: round(v[0] * args.steps / (v[1] * 1e-3) / 1e9, 1)

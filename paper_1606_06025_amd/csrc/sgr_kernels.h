@@ -171,19 +171,8 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
                 wend = end;
             }
         }
-        if (F != nullptr) {
-            // round-1 winners push colour 1: short rows by their own lane, long rows by
-            // the whole wavefront
-            const bool longrow = winpush && wend - wbeg > 64;
-            if (winpush && !longrow) push_row_lane(F, rowptr, colidx, nnz, (int)vv, 1, wbeg, wend);
-            unsigned long long lr = __ballot(longrow);
-            while (lr) {
-                const int j = __ffsll((long long)lr) - 1;
-                lr &= lr - 1;
-                push_row_coop(F, rowptr, colidx, nnz, (int)__builtin_amdgcn_readlane((int)vv, j), 1,
-                              __builtin_amdgcn_readlane(wbeg, j), __builtin_amdgcn_readlane(wend, j), lane, 64);
-            }
-        }
+        // round-1 winners push colour 1, the whole wavefront over their concatenated rows
+        if (F != nullptr) push_rows_wave(F, rowptr, colidx, nnz, winpush, (int)vv, 1, wbeg, wend);
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const unsigned long long m = __ballot(bkt == b);

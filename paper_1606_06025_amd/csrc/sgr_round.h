@@ -135,24 +135,6 @@ __device__ __forceinline__ void wave_slice(int lo, int hi, int& wlo, int& whi) {
 // which is the snapshot FirstFit of Sec. 3 reads, so the colouring is unchanged.
 // ---------------------------------------------------------------------------
 
-// One lane pushes colour c of vertex v to every neighbour in row [beg, end).
-__device__ __forceinline__ void push_row_lane(unsigned* F, const int* __restrict__ rowptr,
-                                              const int* __restrict__ colidx, int nnz, int v, int c, int beg,
-                                              int end) {
-    const int mis = (int)((reinterpret_cast<uintptr_t>(colidx) >> 2) & 3);
-    const int nq = end > beg ? (((end - 1 + mis) >> 2) - ((beg + mis) >> 2) + 1) : 0;
-    for (int q = 0; q < nq; ++q) {
-        int w[4];
-        load_quad(colidx, nnz, beg, end, q, w);
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (w[k] >= 0 && w[k] != v) push_colour(F, rowptr, w[k], c);
-    }
-}
-__device__ __forceinline__ void push_row_lane(const RoundArgs& a, int v, int c, int beg, int end) {
-    push_row_lane(a.F, a.rowptr, a.colidx, a.nnz, v, c, beg, end);
-}
-
 // `nthr` threads (thread index t) push colour c of v over row [beg, end) together.
 __device__ __forceinline__ void push_row_coop(unsigned* F, const int* __restrict__ rowptr,
                                               const int* __restrict__ colidx, int nnz, int v, int c, int beg,
@@ -169,6 +151,50 @@ __device__ __forceinline__ void push_row_coop(unsigned* F, const int* __restrict
 __device__ __forceinline__ void push_row_coop(const RoundArgs& a, int v, int c, int beg, int end, int t,
                                               int nthr) {
     push_row_coop(a.F, a.rowptr, a.colidx, a.nnz, v, c, beg, end, t, nthr);
+}
+
+// The whole wavefront pushes the colours of its winners: lane l contributes the row
+// [beg, end) of vertex v with colour c when `win`.  The rows are concatenated quad by
+// quad (a prefix sum over the lanes) and the 64 lanes walk the concatenation, each
+// finding its row by a binary search over the prefix, so a wavefront with one long
+// or a few short winner rows does not serialise on one lane.  Every lane must call.
+__device__ __forceinline__ void push_rows_wave(unsigned* F, const int* __restrict__ rowptr,
+                                               const int* __restrict__ colidx, int nnz, bool win, int v, int c,
+                                               int beg, int end) {
+    const int lane = __lane_id();
+    const int mis = (int)((reinterpret_cast<uintptr_t>(colidx) >> 2) & 3);
+    const int nq = win && end > beg ? (((end - 1 + mis) >> 2) - ((beg + mis) >> 2) + 1) : 0;
+    int incl = nq;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    const int total = __shfl(incl, 63, 64);
+    for (int base = 0; base < total; base += 64) {
+        const int item = base + lane;
+        // j = number of lanes whose inclusive prefix is <= item: the row holding the item
+        int j = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            if (__shfl(incl, j + step - 1, 64) <= item) j += step;
+        }
+        const int q = item - (__shfl(incl, j, 64) - __shfl(nq, j, 64));
+        const int vj = __shfl(v, j, 64);
+        const int cj = __shfl(c, j, 64);
+        const int bj = __shfl(beg, j, 64);
+        const int ej = __shfl(end, j, 64);
+        if (item < total) {
+            int w[4];
+            load_quad(colidx, nnz, bj, ej, q, w);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (w[k] >= 0 && w[k] != vj) push_colour(F, rowptr, w[k], cj);
+        }
+    }
+}
+__device__ __forceinline__ void push_rows_wave(const RoundArgs& a, bool win, int v, int c, int beg, int end) {
+    push_rows_wave(a.F, a.rowptr, a.colidx, a.nnz, win, v, c, beg, end);
 }
 
 // Push-mode FirstFit for any bucket: one lane per vertex finds the first clear bit
@@ -657,10 +683,8 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
             __builtin_amdgcn_wave_barrier();
             const bool lost_l = res[lane] != 0;
             __builtin_amdgcn_wave_barrier();
-            if (v_l >= 0 && !lost_l) {
-                settle(a, v_l, cv_l, cmax);
-                if (a.pushff) push_row_lane(a, v_l, cv_l, beg_l, end_l);
-            }
+            if (v_l >= 0 && !lost_l) settle(a, v_l, cv_l, cmax);
+            if (a.pushff) push_rows_wave(a, v_l >= 0 && !lost_l, v_l, cv_l, beg_l, end_l);
             push_losers(v_l, lost_l, mybuf, wc);
         }
         flush_losers(s, wc, outl, cnt_out);
@@ -708,10 +732,8 @@ __device__ __forceinline__ void detect_lanes(const RoundArgs& a, const int* list
                 }
                 if (lost || stop) break;
             }
-            if (v_l >= 0 && !lost) {
-                settle(a, v_l, cv, cmax);
-                if (a.pushff) push_row_lane(a, v_l, cv, beg, end);
-            }
+            if (v_l >= 0 && !lost) settle(a, v_l, cv, cmax);
+            if (a.pushff) push_rows_wave(a, v_l >= 0 && !lost, v_l, cv, beg, end);
             push_losers(v_l, lost, mybuf, wc);
         }
         flush_losers(s, wc, outl, cnt_out);
@@ -766,16 +788,7 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
                 if (lane == j) lost_l = lost;
             }
             if (v_l >= 0 && !lost_l) settle(a, v_l, cv_l, cmax);
-            if (a.pushff) {
-                unsigned long long win = __ballot(v_l >= 0 && !lost_l);
-                while (win) {
-                    const int j = __ffsll((long long)win) - 1;
-                    win &= win - 1;
-                    push_row_coop(a, __builtin_amdgcn_readlane(v_l, j), __builtin_amdgcn_readlane(cv_l, j),
-                                  __builtin_amdgcn_readlane(beg_l, j), __builtin_amdgcn_readlane(end_l, j),
-                                  lane, 64);
-                }
-            }
+            if (a.pushff) push_rows_wave(a, v_l >= 0 && !lost_l, v_l, cv_l, beg_l, end_l);
             push_losers(v_l, lost_l, mybuf, wc);
         }
         flush_losers(s, wc, outl, cnt_out);
