@@ -581,6 +581,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     a.pushff = J.opt.pushff;
     a.F = F;
     a.rule = J.opt.rule;
+    a.seed = J.opt.seed;
     a.st_cap = st_cap;
     a.st_wsize = st_cap ? w->st_wsize : nullptr;
     a.st_arcs = st_cap ? w->st_arcs : nullptr;
