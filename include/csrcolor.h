@@ -113,7 +113,10 @@ typedef struct {
     int32_t algorithm;      /* csrcolor_algorithm (default CSRCOLOR_ALGO_SGR) */
     uint32_t seed_lo;       /* JP: low and high 32 bits of the 64-bit priority seed */
     uint32_t seed_hi;
-    int32_t reserved[3];
+    int32_t hints;          /* 0: default (on); 1: on; -1: off.  Conflict hints (id rule): the conflict test
+                               first checks the neighbour that requeued the vertex last time and reads the
+                               vertex's row only when that one no longer conflicts (same colouring) */
+    int32_t reserved[2];
 } csrcolor_opts;
 
 /* Optional run statistics (HOST struct).  Set `cap`, `time_kernels` and the array

@@ -32,6 +32,7 @@ struct Workspace {
     size_t cap_n = 0;            // vertices the arrays below can hold
     int* X = nullptr;            // colour state
     int* wl[2] = {nullptr, nullptr};
+    int* hint = nullptr;         // conflict hints: a neighbour that beat the vertex
     Ctl* ctl = nullptr;          // device control block
     Ctl* ctl_h = nullptr;        // pinned host mirror
     int st_cap = 0;
@@ -173,7 +174,8 @@ void free_vertex_arrays(Workspace* w) {
     if (w->X) (void)hipFree(w->X);
     if (w->wl[0]) (void)hipFree(w->wl[0]);
     if (w->wl[1]) (void)hipFree(w->wl[1]);
-    w->X = w->wl[0] = w->wl[1] = nullptr;
+    if (w->hint) (void)hipFree(w->hint);
+    w->X = w->wl[0] = w->wl[1] = w->hint = nullptr;
     w->cap_n = 0;
 }
 
@@ -200,7 +202,8 @@ int ensure_capacity(Workspace* w, size_t n, int st_cap) {
         size_t want = std::max(n, (size_t)1024);
         if (hipMalloc(&w->X, want * sizeof(int)) != hipSuccess ||
             hipMalloc(&w->wl[0], want * sizeof(int)) != hipSuccess ||
-            hipMalloc(&w->wl[1], want * sizeof(int)) != hipSuccess) {
+            hipMalloc(&w->wl[1], want * sizeof(int)) != hipSuccess ||
+            hipMalloc(&w->hint, want * sizeof(int)) != hipSuccess) {
             free_vertex_arrays(w);
             return CSRCOLOR_ENOMEM;
         }
@@ -260,6 +263,7 @@ struct Options {
     int lane_assign = 0;      // tile buckets run with 2/4/8/16 lanes per vertex
     int lane_detect = 0xF;    // lane-per-vertex conflict test (early exit) in every tile bucket
     int pushff = 1;           // push-mode FirstFit
+    int hints = 1;            // conflict hints (id rule)
     int rule = 0;             // conflict rule (csrcolor_rule)
     int algo = CSRCOLOR_ALGO_SGR;
     unsigned long long seed = 0;
@@ -270,7 +274,8 @@ struct Options {
 bool opts_valid(const csrcolor_opts* o, bool single) {
     if (!o) return true;
     if (o->mode < 0 || o->mode > CSRCOLOR_MODE_GRAPH || o->validate < 0 || o->firstfit < 0 || o->firstfit > 2 ||
-        o->rule < 0 || o->rule > 1 || o->algorithm < 0 || o->algorithm > CSRCOLOR_ALGO_JP)
+        o->rule < 0 || o->rule > 1 || o->algorithm < 0 || o->algorithm > CSRCOLOR_ALGO_JP || o->hints < -1 ||
+        o->hints > 1)
         return false;
     if (o->algorithm != CSRCOLOR_ALGO_SGR && (o->mode == CSRCOLOR_MODE_PERSISTENT || o->mode == CSRCOLOR_MODE_GRAPH))
         return false;
@@ -291,6 +296,7 @@ Options parse_opts(const csrcolor_opts* o) {
     if (o->lane_assign) r.lane_assign = o->lane_assign < 0 ? 0 : (o->lane_assign & 0xF);
     if (o->lane_detect) r.lane_detect = o->lane_detect < 0 ? 0 : (o->lane_detect & 0xF);
     if (o->firstfit) r.pushff = o->firstfit != 1;
+    if (o->hints) r.hints = o->hints > 0;
     r.rule = o->rule;
     r.algo = o->algorithm;
     r.seed = ((unsigned long long)o->seed_hi << 32) | o->seed_lo;
@@ -549,11 +555,13 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
         });
     }
 
+    // conflict hints serve the id rule (the degree rule would need the neighbour's degree too)
+    int* hint = (J.opt.hints && J.opt.rule == 0) ? w->hint : nullptr;
     const int r1blocks = (int)(((long long)n + 4 * WG - 1) / (4 * WG));
     T.run(0, [&] {
         k_round1<<<r1blocks, WG, 0, st>>>(n, J.rowptr, J.colidx, w->X, J.colors_out, w->wl[1], w->ctl,
                                           J.sorted, twave, J.opt.tsplit, seg, cstart1, owner1, F,
-                                          w->ctl_h->nnz, J.opt.rule, J.opt.algo == CSRCOLOR_ALGO_JP);
+                                          w->ctl_h->nnz, J.opt.rule, J.opt.algo == CSRCOLOR_ALGO_JP, hint);
     });
     HIP_TRY(hipGetLastError());
 
@@ -582,6 +590,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     a.F = F;
     a.rule = J.opt.rule;
     a.seed = J.opt.seed;
+    a.hint = hint;
     a.st_cap = st_cap;
     a.st_wsize = st_cap ? w->st_wsize : nullptr;
     a.st_arcs = st_cap ? w->st_arcs : nullptr;

@@ -144,6 +144,10 @@ struct RoundArgs {
     // conflict rule: 0 = the higher id is requeued; 1 = the smaller degree (row
     // length) is requeued, the higher id on equal degree (heuristic of Sec. 3.2)
     int rule;
+    // conflict hints (id rule only; nullptr = off): hint[v] is a neighbour that beat v
+    // in an earlier round; the test checks it first and reads v's row only if it no
+    // longer conflicts
+    int* hint;
     // JP (rule RULE_JP): this round's colour and the priority generator's seed
     int jpc;
     unsigned long long seed;
@@ -165,6 +169,16 @@ struct RoundArgs {
 // colour of the round.
 __device__ __forceinline__ int tentative(const RoundArgs& a, int v) {
     return a.rule == RULE_JP ? a.jpc : (a.X[v] & CMASK);
+}
+
+// Does the remembered neighbour of worklist vertex v still requeue it?  A neighbour
+// that settled in an earlier round cannot hold v's tentative colour (FirstFit excluded
+// it), so an equal colour part means a worklist neighbour of this round that beats v:
+// the same verdict the full scan would reach.
+__device__ __forceinline__ bool hint_hit(const RoundArgs& a, int v, int cv) {
+    if (!a.hint) return false;
+    const int h = a.hint[v];
+    return h >= 0 && h < v && (a.X[h] & CMASK) == cv;
 }
 
 // Is worklist vertex v (tentative colour cv, degree dv) requeued because of row entry

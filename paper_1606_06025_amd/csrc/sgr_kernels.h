@@ -113,7 +113,7 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
                                                const int* __restrict__ colidx, int* X, int* out,
                                                int* wl1, Ctl* ctl, int sorted, int twave, int tsplit,
                                                Seg seg, int* cstart1, int* owner1, unsigned* F, int nnz,
-                                               int rule, int jp) {
+                                               int rule, int jp, int* hint) {
     constexpr int ITER = 4;
     __shared__ int buf[WAVES][NB][ITER * 64];
     __shared__ int wcnt[WAVES][NB];
@@ -137,19 +137,26 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
         if (vv < n) {
             const int v = (int)vv;
             const int beg = rowptr[v], end = rowptr[v + 1];
+            int by = -1;   // the neighbour that beat v (conflict hint for the next rounds)
             if (jp) {
                 lose = end > beg;
             } else if (end > beg) {
                 if (rule == 0 && sorted) {
-                    lose = colidx[beg] < v;
+                    by = colidx[beg];
+                    lose = by < v;
                 } else {
                     // all tentative colours are 1: requeued iff some neighbour beats v
                     for (int e = beg; e < end; ++e) {
                         const int w = colidx[e];
-                        if (w != v && beats(rule, rowptr, w, v, end - beg)) { lose = true; break; }
+                        if (w != v && beats(rule, rowptr, w, v, end - beg)) {
+                            lose = true;
+                            by = w;
+                            break;
+                        }
                     }
                 }
             }
+            if (lose && hint) hint[v] = by;
             if (lose) {
                 X[v] = jp ? 0 : (FLAG | 1);
                 bkt = bucket_of(end - beg, twave, tsplit);

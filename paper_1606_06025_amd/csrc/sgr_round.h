@@ -660,10 +660,14 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
             const int nv = min(64, whi - t0);
             const int v_l = lane < nv ? list[t0 + lane] : -1;
             int beg_l = 0, end_l = 0, cv_l = 0;
+            bool hinted_l = false;
             if (v_l >= 0) {
-                beg_l = a.rowptr[v_l];
-                end_l = a.rowptr[v_l + 1];
                 cv_l = tentative(a, v_l);
+                hinted_l = hint_hit(a, v_l, cv_l);
+                if (!hinted_l) {
+                    beg_l = a.rowptr[v_l];
+                    end_l = a.rowptr[v_l + 1];
+                }
             }
             const int nsub = (nv + V - 1) / V;
             for (int sstep = 0; sstep < nsub; ++sstep) {
@@ -674,14 +678,16 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
                 const int cv = __shfl(cv_l, j, 64);
                 int w[4];
                 load_quad(a.colidx, a.nnz, beg, end, q, w);
-                bool hit = false;
+                int found = -1;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) hit |= loses_to(a, w[k], v, cv, end - beg);
-                const bool lost = ((__ballot(hit) >> gshift) & gmask) != 0;
+                for (int k = 0; k < 4; ++k)
+                    if (loses_to(a, w[k], v, cv, end - beg)) found = w[k];
+                if (found >= 0 && a.hint) a.hint[v] = found;    // any conflicting neighbour will do
+                const bool lost = ((__ballot(found >= 0) >> gshift) & gmask) != 0;
                 if (q == 0) res[j] = lost;
             }
             __builtin_amdgcn_wave_barrier();
-            const bool lost_l = res[lane] != 0;
+            const bool lost_l = hinted_l || res[lane] != 0;
             __builtin_amdgcn_wave_barrier();
             if (v_l >= 0 && !lost_l) settle(a, v_l, cv_l, cmax);
             if (a.pushff) push_rows_wave(a, v_l >= 0 && !lost_l, v_l, cv_l, beg_l, end_l);
@@ -709,13 +715,17 @@ __device__ __forceinline__ void detect_lanes(const RoundArgs& a, const int* list
             const int nv = min(64, whi - t0);
             const int v_l = lane < nv ? list[t0 + lane] : -1;
             int beg = 0, end = 0, cv = 0;
+            bool lost = false;
             if (v_l >= 0) {
-                beg = a.rowptr[v_l];
-                end = a.rowptr[v_l + 1];
                 cv = tentative(a, v_l);
+                lost = hint_hit(a, v_l, cv);
+                if (!lost) {
+                    beg = a.rowptr[v_l];
+                    end = a.rowptr[v_l + 1];
+                }
             }
             const int nq = end > beg ? (((end - 1 + mis) >> 2) - ((beg + mis) >> 2) + 1) : 0;
-            bool lost = false;
+            int found = -1;
             for (int q = 0; q < nq; ++q) {
                 int w[4];
                 load_quad(a.colidx, a.nnz, beg, end, q, w);
@@ -725,12 +735,16 @@ __device__ __forceinline__ void detect_lanes(const RoundArgs& a, const int* list
                     if (w[k] >= 0) {
                         if (a.rule == 0 && w[k] >= v_l) {
                             stop |= a.sorted != 0;
-                        } else if (loses_to(a, w[k], v_l, cv, end - beg)) {
-                            lost = true;
+                        } else if (found < 0 && loses_to(a, w[k], v_l, cv, end - beg)) {
+                            found = w[k];
                         }
                     }
                 }
-                if (lost || stop) break;
+                if (found >= 0 || stop) break;
+            }
+            if (found >= 0) {
+                lost = true;
+                if (a.hint) a.hint[v_l] = found;
             }
             if (v_l >= 0 && !lost) settle(a, v_l, cv, cmax);
             if (a.pushff) push_rows_wave(a, v_l >= 0 && !lost, v_l, cv, beg, end);
@@ -757,13 +771,17 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
             const int nv = min(64, whi - t0);
             const int v_l = lane < nv ? list[t0 + lane] : -1;
             int beg_l = 0, end_l = 0, cv_l = 0;
+            bool lost_l = false;
             if (v_l >= 0) {
+                cv_l = tentative(a, v_l);
+                lost_l = hint_hit(a, v_l, cv_l);
                 beg_l = a.rowptr[v_l];
                 end_l = a.rowptr[v_l + 1];
-                cv_l = tentative(a, v_l);
             }
-            bool lost_l = false;
-            for (int j = 0; j < nv; ++j) {
+            unsigned long long todo = __ballot(v_l >= 0 && !lost_l);
+            while (todo) {
+                const int j = __ffsll((long long)todo) - 1;
+                todo &= todo - 1;
                 const int v = __builtin_amdgcn_readlane(v_l, j);
                 const int beg = __builtin_amdgcn_readlane(beg_l, j);
                 const int end = __builtin_amdgcn_readlane(end_l, j);
@@ -773,13 +791,15 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
                 for (int q0 = 0; q0 < nq; q0 += 64) {
                     int w[4];
                     load_quad(a.colidx, a.nnz, beg, end, q0 + lane, w);
-                    bool hit = false, stop = false;
+                    int found = -1;
+                    bool stop = false;
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        hit |= loses_to(a, w[k], v, cv, end - beg);
+                        if (loses_to(a, w[k], v, cv, end - beg)) found = w[k];
                         stop |= a.sorted && a.rule == 0 && w[k] >= v;
                     }
-                    if (__ballot(hit)) {
+                    if (found >= 0 && a.hint) a.hint[v] = found;   // any conflicting neighbour will do
+                    if (__ballot(found >= 0)) {
                         lost = true;
                         break;
                     }
@@ -798,23 +818,32 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
 __device__ __forceinline__ void detect_wg(const RoundArgs& a, const int* list, int cnt, RoundLds& s,
                                           int* outl, int* cnt_out, int& cmax) {
     for (;;) {
-        if (threadIdx.x == 0) s.sh[0] = atomicAdd(&a.ctl->dyn[1][5], 1);
+        // thread 0 takes the next vertex and evaluates its hint once, so every thread of
+        // the block sees the same verdict (the scan below may rewrite the hint)
+        if (threadIdx.x == 0) {
+            const int i0 = atomicAdd(&a.ctl->dyn[1][5], 1);
+            s.sh[0] = i0;
+            s.sh[1] = i0 < cnt ? (int)hint_hit(a, list[i0], tentative(a, list[i0])) : 0;
+        }
         __syncthreads();
         const int i = s.sh[0];
+        bool lost = s.sh[1] != 0;
         __syncthreads();
         if (i >= cnt) break;
         const int v = list[i];
         const int beg = a.rowptr[v], end = a.rowptr[v + 1];
         const int cv = tentative(a, v);
-        const int nq = ((end - beg) + 3 + 3) / 4 + 1;
-        bool lost = false;
+        const int nq = lost ? 0 : ((end - beg) + 3 + 3) / 4 + 1;
         for (int q0 = 0; q0 < nq; q0 += WG) {
             int w[4];
             load_quad(a.colidx, a.nnz, beg, end, q0 + (int)threadIdx.x, w);
             bool hit = false, stop = false;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                hit |= loses_to(a, w[k], v, cv, end - beg);
+                if (loses_to(a, w[k], v, cv, end - beg)) {
+                    hit = true;
+                    if (a.hint) a.hint[v] = w[k];
+                }
                 stop |= a.sorted && a.rule == 0 && w[k] >= v;
             }
             const int anyhit = __syncthreads_or(hit);
@@ -856,15 +885,21 @@ __device__ __forceinline__ void detect_split(const RoundArgs& a, const int* list
         const int nch = split_chunks(re - rb);
         const int beg = rb + k * SPLIT_CH, end = min(beg + SPLIT_CH, re);
         const int cv = tentative(a, v);
-        bool hit = false;
-        const bool skip = ld_agent(&a.hublost[p]) != 0 || (a.rule == 0 && a.sorted && a.colidx[beg] >= v);
+        // the remembered neighbour decides for every chunk of the hub at once
+        bool hit = hint_hit(a, v, cv);
+        const bool skip = hit || ld_agent(&a.hublost[p]) != 0 || (a.rule == 0 && a.sorted && a.colidx[beg] >= v);
         if (!skip) {
             const int nq = ((end - beg) + 3 + 3) / 4 + 1;
             for (int q0 = 0; q0 < nq; q0 += WG) {
                 int w[4];
                 load_quad(a.colidx, a.nnz, beg, end, q0 + tid, w);
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk) hit |= loses_to(a, w[kk], v, cv, re - rb);
+                for (int kk = 0; kk < 4; ++kk) {
+                    if (loses_to(a, w[kk], v, cv, re - rb)) {
+                        hit = true;
+                        if (a.hint) a.hint[v] = w[kk];
+                    }
+                }
             }
         }
         const int anyhit = __syncthreads_or(hit);

@@ -122,7 +122,8 @@ def test_mixed_stencils(dev):
 
 @pytest.mark.parametrize("kw", [dict(t_wave=61), dict(t_wave=64), dict(t_wave=200),
                                 dict(blocks_per_cu=1), dict(blocks_per_cu=3), dict(sync_every=1),
-                                dict(sync_every=5), dict(t_wave=70, blocks_per_cu=2, sync_every=3)])
+                                dict(sync_every=5), dict(t_wave=70, blocks_per_cu=2, sync_every=3),
+                                dict(hints=-1), dict(hints=1, lane_detect=-1), dict(hints=-1, lane_detect=-1)])
 def test_launch_options_do_not_change_result(dev, kw):
     import oracle
     g = gg.rmat(13, 16, 9)
@@ -372,3 +373,17 @@ def test_degree_rule_split_and_unsorted(dev):
     g = gg.rmat(16, 16, 13)
     _assert_parity(g, dev, rule=1, t_split=1024, t_wave=61)
     _assert_parity(gg.shuffle_rows(g, 5), dev, rule=1)
+
+
+@pytest.mark.parametrize("hints", [-1, 1])
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_conflict_hints_on_and_off(dev, hints, mode):
+    """The conflict test may first check the neighbour that requeued a vertex before;
+    on or off, every bucket (tiles, lanes, wavefront, workgroup, split rows) and every
+    drive mode gives the oracle's colouring, also with unsorted rows."""
+    graphs = [gg.stencil27(24, 20, 16), gg.rmat(14, 16, 7),
+              _degree_ladder([5, 13, 29, 61, 300, 1500, 2500, 9000], 5),
+              gg.shuffle_rows(gg.erdos_renyi(20000, 200000, 6), 3), gg.complete(200)]
+    for g in graphs:
+        _assert_parity(g, dev, mode=mode, hints=hints)
+        _assert_parity(g, dev, mode=mode, hints=hints, lane_detect=-1, t_wave=128, t_split=1024)
