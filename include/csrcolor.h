@@ -116,7 +116,10 @@ typedef struct {
     int32_t hints;          /* 0: default (on); 1: on; -1: off.  Conflict hints (id rule): the conflict test
                                first checks the neighbour that requeued the vertex last time and reads the
                                vertex's row only when that one no longer conflicts (same colouring) */
-    int32_t reserved[2];
+    int32_t live_lists;     /* 0: default (on); 1: on; -1: off.  Live lists (id rule): a vertex of degree > 61
+                               tests a list of its lower neighbours that were still uncoloured when last seen,
+                               shrunk as they settle, instead of its row (same colouring) */
+    int32_t reserved[1];
 } csrcolor_opts;
 
 /* Optional run statistics (HOST struct).  Set `cap`, `time_kernels` and the array

@@ -33,6 +33,9 @@ struct Workspace {
     int* X = nullptr;            // colour state
     int* wl[2] = {nullptr, nullptr};
     int* hint = nullptr;         // conflict hints: a neighbour that beat the vertex
+    int* llen = nullptr;         // live-list lengths (or a split row's chunk-slot base)
+    int* live = nullptr;         // live lists, same offsets as colidx
+    size_t live_cap = 0;         // ints
     Ctl* ctl = nullptr;          // device control block
     Ctl* ctl_h = nullptr;        // pinned host mirror
     int st_cap = 0;
@@ -175,7 +178,8 @@ void free_vertex_arrays(Workspace* w) {
     if (w->wl[0]) (void)hipFree(w->wl[0]);
     if (w->wl[1]) (void)hipFree(w->wl[1]);
     if (w->hint) (void)hipFree(w->hint);
-    w->X = w->wl[0] = w->wl[1] = w->hint = nullptr;
+    if (w->llen) (void)hipFree(w->llen);
+    w->X = w->wl[0] = w->wl[1] = w->hint = w->llen = nullptr;
     w->cap_n = 0;
 }
 
@@ -188,6 +192,9 @@ void free_ws_arrays(Workspace* w) {
     if (w->split) (void)hipFree(w->split);
     w->split = nullptr;
     w->split_cap = 0;
+    if (w->live) (void)hipFree(w->live);
+    w->live = nullptr;
+    w->live_cap = 0;
     free_vertex_arrays(w);
 }
 
@@ -203,7 +210,8 @@ int ensure_capacity(Workspace* w, size_t n, int st_cap) {
         if (hipMalloc(&w->X, want * sizeof(int)) != hipSuccess ||
             hipMalloc(&w->wl[0], want * sizeof(int)) != hipSuccess ||
             hipMalloc(&w->wl[1], want * sizeof(int)) != hipSuccess ||
-            hipMalloc(&w->hint, want * sizeof(int)) != hipSuccess) {
+            hipMalloc(&w->hint, want * sizeof(int)) != hipSuccess ||
+            hipMalloc(&w->llen, want * sizeof(int)) != hipSuccess) {
             free_vertex_arrays(w);
             return CSRCOLOR_ENOMEM;
         }
@@ -247,6 +255,18 @@ int ensure_F(Workspace* w, size_t words) {
     return CSRCOLOR_OK;
 }
 
+int ensure_live(Workspace* w, size_t ints) {
+    if (ints <= w->live_cap) return CSRCOLOR_OK;
+    (void)hipStreamSynchronize(w->stream);
+    if (w->live) (void)hipFree(w->live);
+    w->live = nullptr;
+    w->live_cap = 0;
+    const size_t want = std::max(ints, (size_t)4096);
+    if (hipMalloc(&w->live, want * sizeof(int)) != hipSuccess) return CSRCOLOR_ENOMEM;
+    w->live_cap = want;
+    return CSRCOLOR_OK;
+}
+
 int read_ctl(Workspace* w) {
     HIP_TRY(hipMemcpyAsync(w->ctl_h, w->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, w->stream));
     HIP_TRY(hipStreamSynchronize(w->stream));
@@ -264,6 +284,7 @@ struct Options {
     int lane_detect = 0xF;    // lane-per-vertex conflict test (early exit) in every tile bucket
     int pushff = 1;           // push-mode FirstFit
     int hints = 1;            // conflict hints (id rule)
+    int live = 1;             // live lists for degree > 61 (id rule)
     int rule = 0;             // conflict rule (csrcolor_rule)
     int algo = CSRCOLOR_ALGO_SGR;
     unsigned long long seed = 0;
@@ -275,7 +296,7 @@ bool opts_valid(const csrcolor_opts* o, bool single) {
     if (!o) return true;
     if (o->mode < 0 || o->mode > CSRCOLOR_MODE_GRAPH || o->validate < 0 || o->firstfit < 0 || o->firstfit > 2 ||
         o->rule < 0 || o->rule > 1 || o->algorithm < 0 || o->algorithm > CSRCOLOR_ALGO_JP || o->hints < -1 ||
-        o->hints > 1)
+        o->hints > 1 || o->live_lists < -1 || o->live_lists > 1)
         return false;
     if (o->algorithm != CSRCOLOR_ALGO_SGR && (o->mode == CSRCOLOR_MODE_PERSISTENT || o->mode == CSRCOLOR_MODE_GRAPH))
         return false;
@@ -297,6 +318,7 @@ Options parse_opts(const csrcolor_opts* o) {
     if (o->lane_detect) r.lane_detect = o->lane_detect < 0 ? 0 : (o->lane_detect & 0xF);
     if (o->firstfit) r.pushff = o->firstfit != 1;
     if (o->hints) r.hints = o->hints > 0;
+    if (o->live_lists) r.live = o->live_lists > 0;
     r.rule = o->rule;
     r.algo = o->algorithm;
     r.seed = ((unsigned long long)o->seed_hi << 32) | o->seed_lo;
@@ -531,7 +553,12 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     // split-row scratch: cstart[2] (hubs), owner[2] (chunks), hub bitmaps, done counters, lost flags
     const int nhub = hist[BSPLIT];
     const int nchunk = w->ctl_h->hchunks;
-    const size_t split_ints = 2 * (size_t)nhub + 2 * (size_t)nchunk + (size_t)nhub * (HW + 2);
+    // live lists: the vertices of degree > 61 scan lists of their uncoloured lower
+    // neighbours (id rule, worklist SGR only)
+    const bool use_live = J.opt.live && J.opt.rule == 0 && J.opt.algo == CSRCOLOR_ALGO_SGR &&
+                          hist[NTILE] + hist[NTILE + 1] + hist[BSPLIT] > 0;
+    const size_t split_ints = 2 * (size_t)nhub + 2 * (size_t)nchunk + (size_t)nhub * (HW + 2) +
+                              (use_live ? (size_t)nchunk : 0);
     if ((rc = ensure_split(w, split_ints))) return rc;
     int* cstart0 = w->split;
     int* cstart1 = cstart0 + nhub;
@@ -542,6 +569,8 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
         const int cnt = nhub * (HW + 2);
         k_fill<<<std::min((cnt + WG - 1) / WG, cus * 4), WG, 0, st>>>(hubflags, cnt, 0);
     }
+    int* clen = use_live ? hubflags + (size_t)nhub * (HW + 2) : nullptr;   // per-chunk live lengths
+    if (use_live && (rc = ensure_live(w, std::max<size_t>((size_t)w->ctl_h->nnz, 1)))) return rc;
 
     // push mode: deg(v)+1 bits per vertex, zeroed
     unsigned* F = nullptr;
@@ -561,7 +590,8 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     T.run(0, [&] {
         k_round1<<<r1blocks, WG, 0, st>>>(n, J.rowptr, J.colidx, w->X, J.colors_out, w->wl[1], w->ctl,
                                           J.sorted, twave, J.opt.tsplit, seg, cstart1, owner1, F,
-                                          w->ctl_h->nnz, J.opt.rule, J.opt.algo == CSRCOLOR_ALGO_JP, hint);
+                                          w->ctl_h->nnz, J.opt.rule, J.opt.algo == CSRCOLOR_ALGO_JP, hint,
+                                          use_live ? w->llen : nullptr, clen);
     });
     HIP_TRY(hipGetLastError());
 
@@ -591,6 +621,9 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     a.rule = J.opt.rule;
     a.seed = J.opt.seed;
     a.hint = hint;
+    a.live = use_live ? w->live : nullptr;
+    a.llen = use_live ? w->llen : nullptr;
+    a.clen = clen;
     a.st_cap = st_cap;
     a.st_wsize = st_cap ? w->st_wsize : nullptr;
     a.st_arcs = st_cap ? w->st_arcs : nullptr;

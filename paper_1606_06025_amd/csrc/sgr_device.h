@@ -148,6 +148,13 @@ struct RoundArgs {
     // in an earlier round; the test checks it first and reads v's row only if it no
     // longer conflicts
     int* hint;
+    // live lists (id rule; nullptr = off): for a vertex of degree > 61 the lower
+    // neighbours still uncoloured when last seen, packed at live[rowptr[v] ...];
+    // llen[v] = their number (-1: not built yet) or, for a split row, the base of its
+    // per-chunk lengths clen[llen[v] + k] (-1: chunk not built yet)
+    int* live;
+    int* llen;
+    int* clen;
     // JP (rule RULE_JP): this round's colour and the priority generator's seed
     int jpc;
     unsigned long long seed;
@@ -217,6 +224,19 @@ __device__ __forceinline__ int wave_min(int x) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) x = min(x, __shfl_xor(x, off, 64));
     return x;
+}
+
+// Exclusive prefix over the wavefront's lanes of c; `total` receives the sum.
+__device__ __forceinline__ int wave_excl(int c, int& total) {
+    const int lane = __lane_id();
+    int incl = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    total = __shfl(incl, 63, 64);
+    return incl - c;
 }
 
 __device__ __forceinline__ long long wave_sum64(long long x) {

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
                                                const int* __restrict__ colidx, int* X, int* out,
                                                int* wl1, Ctl* ctl, int sorted, int twave, int tsplit,
                                                Seg seg, int* cstart1, int* owner1, unsigned* F, int nnz,
-                                               int rule, int jp, int* hint) {
+                                               int rule, int jp, int* hint, int* llen, int* clen) {
     constexpr int ITER = 4;
     __shared__ int buf[WAVES][NB][ITER * 64];
     __shared__ int wcnt[WAVES][NB];
@@ -160,6 +160,7 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
             if (lose) {
                 X[v] = jp ? 0 : (FLAG | 1);
                 bkt = bucket_of(end - beg, twave, tsplit);
+                if (llen && bkt >= NTILE && bkt < BSPLIT) llen[v] = -1;   // live list not built yet
                 if (bkt == BSPLIT) {
                     // split rows are few: one queue slot and one chunk range per vertex
                     const int nch = split_chunks(end - beg);
@@ -168,6 +169,12 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
                     wl1[seg.s[BSPLIT] + p] = v;
                     cstart1[p] = cs;
                     for (int k = 0; k < nch; ++k) owner1[cs + k] = p;
+                    if (llen) {
+                        // the round-1 chunk range doubles as the hub's stable slot range
+                        // for its per-chunk live-list lengths
+                        llen[v] = cs;
+                        for (int k = 0; k < nch; ++k) clen[cs + k] = -1;
+                    }
                     bkt = -1;
                 }
             } else {

@@ -26,6 +26,8 @@ struct RoundLds {
     int red[WAVES];
     long long red64[WAVES];
     int sh[4];
+    int lpre[WAVES];                  // live lists: per-wavefront kept counts of a block scan
+    int lsh[4];                       // live lists: block-uniform verdicts of a split chunk
 };
 
 // Bucket of block `bid` under the partition boff, its index j inside the bucket and
@@ -754,6 +756,151 @@ __device__ __forceinline__ void detect_lanes(const RoundArgs& a, const int* list
     }
 }
 
+// ---------------------------------------------------------------------------
+// Live lists (id rule).  A vertex of degree > 61 may stay on the worklist for many
+// rounds, and most of its lower neighbours settle early; once settled, a neighbour
+// can never conflict with it again (FirstFit excluded its colour).  So the first
+// conflict test of such a vertex copies its lower, still uncoloured neighbours into
+// its live list (same offsets as its row, in a separate array), and every later test
+// scans that list instead of the row, dropping the entries it finds settled: packed
+// to the front as it goes; when the scan stops early at a conflict, the gap left in
+// the scanned part is filled from the end of the list, so the list stays contiguous
+// and the unscanned entries are kept.  Entries are tested before they are dropped, so
+// a neighbour settling in this very round is still compared.
+// ---------------------------------------------------------------------------
+
+// Scan step shared by the wavefront and workgroup versions: reads entries of
+// src[beg, end) (quad q of the range), tests them against v and returns the lower
+// neighbours still uncoloured in keep/w.
+__device__ __forceinline__ void live_step(const RoundArgs& a, const int* src, int beg, int end, int q, int v,
+                                          int cv, bool build, int w[4], unsigned& keep, bool& hit, bool& stop) {
+    load_quad(src, a.nnz, beg, end, q, w);
+    keep = 0;
+    int found = -1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (w[k] < 0) continue;
+        if (w[k] < v) {
+            const int x = a.X[w[k]];
+            if ((x & CMASK) == cv) found = w[k];
+            if (x <= 0) keep |= 1u << k;
+        } else {
+            stop |= build && a.sorted;     // sorted rows: no lower entries further on
+        }
+    }
+    if (found >= 0) {
+        hit = true;
+        if (a.hint) a.hint[v] = found;     // any conflicting neighbour will do
+    }
+}
+
+// First position (relative to beg) after the quads 0 .. q-1 of src[beg, ...).
+__device__ __forceinline__ int quad_end(const int* src, int beg, int q) {
+    const int mis = (int)((reinterpret_cast<uintptr_t>(src) >> 2) & 3);
+    return ((beg + mis) & ~3) - mis + 4 * q - beg;
+}
+
+// The whole wavefront runs the conflict test of v (tentative colour cv, row
+// [rb, re)) on its live list of length len (-1: build it from the row).  Updates the
+// list and llen[v]; returns whether v is requeued.  Every lane must call.
+__device__ __forceinline__ bool live_test_wave(const RoundArgs& a, int v, int cv, int rb, int re, int len) {
+    const int lane = __lane_id();
+    const bool build = len < 0;
+    const int* src = build ? a.colidx : a.live;
+    const int send = build ? re : rb + len;
+    const int mis = (int)((reinterpret_cast<uintptr_t>(src) >> 2) & 3);
+    const int nq = send > rb ? (((send - 1 + mis) >> 2) - ((rb + mis) >> 2) + 1) : 0;
+    int K = 0;                 // entries kept so far, packed at live[rb ...]
+    int p = send - rb;         // list positions scanned
+    bool lost = false;
+    for (int q0 = 0; q0 < nq; q0 += 64) {
+        int w[4];
+        unsigned keep;
+        bool hit = false, stop = false;
+        live_step(a, src, rb, send, q0 + lane, v, cv, build, w, keep, hit, stop);
+        int tot;
+        int pos = K + wave_excl(__popc(keep), tot);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (keep >> k & 1) a.live[rb + pos++] = w[k];
+        K += tot;
+        const bool anyhit = __ballot(hit) != 0;
+        lost |= anyhit;
+        if (anyhit && !build) {
+            p = min(send - rb, quad_end(src, rb, q0 + 64));
+            break;
+        }
+        if (__ballot(stop) != 0) break;
+    }
+    int newlen = K;
+    if (!build) {
+        // fill the gap [K, p) from the end of the unscanned part [p, len)
+        const int m = min(p - K, len - p);
+        for (int i = lane; i < m; i += 64) a.live[rb + K + i] = a.live[rb + len - m + i];
+        newlen = len - (p - K);
+    }
+    if (lane == 0) a.llen[v] = newlen;
+    return lost;
+}
+
+// Workgroup version of live_test_wave (every thread must call with the same
+// arguments): the list of v at live[rb ...] (or, when len < 0, its row part
+// colidx[rb, re)) is scanned, compacted, and its new length stored at *lenp.  With
+// `early` the scan of a built list stops at the first conflict; the returned verdict
+// is the same in every thread.
+__device__ __forceinline__ bool live_test_wg(const RoundArgs& a, int v, int cv, int rb, int re, int len,
+                                             int* lenp, bool early, RoundLds& s) {
+    const int tid = threadIdx.x;
+    const int lane = __lane_id();
+    const int wv = tid >> 6;
+    const bool build = len < 0;
+    const int* src = build ? a.colidx : a.live;
+    const int send = build ? re : rb + len;
+    const int mis = (int)((reinterpret_cast<uintptr_t>(src) >> 2) & 3);
+    const int nq = send > rb ? (((send - 1 + mis) >> 2) - ((rb + mis) >> 2) + 1) : 0;
+    int K = 0;
+    int p = send - rb;
+    bool lost = false;
+    for (int q0 = 0; q0 < nq; q0 += WG) {
+        int w[4];
+        unsigned keep;
+        bool hit = false, stop = false;
+        live_step(a, src, rb, send, q0 + tid, v, cv, build, w, keep, hit, stop);
+        int wtot;
+        const int wex = wave_excl(__popc(keep), wtot);
+        if (lane == 0) s.lpre[wv] = wtot;
+        __syncthreads();
+        int before = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < WAVES; ++k) {
+            before += k < wv ? s.lpre[k] : 0;
+            tot += s.lpre[k];
+        }
+        int pos = K + before + wex;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (keep >> k & 1) a.live[rb + pos++] = w[k];
+        K += tot;
+        const int anyhit = __syncthreads_or(hit);
+        const int anystop = __syncthreads_or(stop);
+        lost |= anyhit != 0;
+        if (anyhit && !build && early) {
+            p = min(send - rb, quad_end(src, rb, q0 + WG));
+            break;
+        }
+        if (anystop) break;
+    }
+    int newlen = K;
+    if (!build) {
+        const int m = min(p - K, len - p);
+        for (int i = tid; i < m; i += WG) a.live[rb + K + i] = a.live[rb + len - m + i];
+        newlen = len - (p - K);
+    }
+    if (tid == 0) *lenp = newlen;
+    __syncthreads();
+    return lost;
+}
+
 // Wavefront bucket: metadata for 64 vertices at a time, then the wavefront scans the
 // lower part of one row at a time (256 arcs per step; for sorted rows the scan stops
 // at the first w >= v, and at the first conflict in any case).
@@ -770,13 +917,14 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
         for (int t0 = wlo; t0 < whi; t0 += 64) {
             const int nv = min(64, whi - t0);
             const int v_l = lane < nv ? list[t0 + lane] : -1;
-            int beg_l = 0, end_l = 0, cv_l = 0;
+            int beg_l = 0, end_l = 0, cv_l = 0, len_l = -1;
             bool lost_l = false;
             if (v_l >= 0) {
                 cv_l = tentative(a, v_l);
                 lost_l = hint_hit(a, v_l, cv_l);
                 beg_l = a.rowptr[v_l];
                 end_l = a.rowptr[v_l + 1];
+                if (a.live && !lost_l) len_l = a.llen[v_l];
             }
             unsigned long long todo = __ballot(v_l >= 0 && !lost_l);
             while (todo) {
@@ -786,6 +934,11 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
                 const int beg = __builtin_amdgcn_readlane(beg_l, j);
                 const int end = __builtin_amdgcn_readlane(end_l, j);
                 const int cv = __builtin_amdgcn_readlane(cv_l, j);
+                if (a.live) {
+                    const bool lost = live_test_wave(a, v, cv, beg, end, __builtin_amdgcn_readlane(len_l, j));
+                    if (lane == j) lost_l = lost;
+                    continue;
+                }
                 const int nq = ((end - beg) + 3 + 3) / 4 + 1;
                 bool lost = false;
                 for (int q0 = 0; q0 < nq; q0 += 64) {
@@ -824,16 +977,19 @@ __device__ __forceinline__ void detect_wg(const RoundArgs& a, const int* list, i
             const int i0 = atomicAdd(&a.ctl->dyn[1][5], 1);
             s.sh[0] = i0;
             s.sh[1] = i0 < cnt ? (int)hint_hit(a, list[i0], tentative(a, list[i0])) : 0;
+            s.sh[2] = (i0 < cnt && a.live) ? a.llen[list[i0]] : -1;
         }
         __syncthreads();
         const int i = s.sh[0];
         bool lost = s.sh[1] != 0;
+        const int len = s.sh[2];
         __syncthreads();
         if (i >= cnt) break;
         const int v = list[i];
         const int beg = a.rowptr[v], end = a.rowptr[v + 1];
         const int cv = tentative(a, v);
-        const int nq = lost ? 0 : ((end - beg) + 3 + 3) / 4 + 1;
+        if (a.live && !lost) lost = live_test_wg(a, v, cv, beg, end, len, &a.llen[v], true, s);
+        const int nq = (lost || a.live) ? 0 : ((end - beg) + 3 + 3) / 4 + 1;
         for (int q0 = 0; q0 < nq; q0 += WG) {
             int w[4];
             load_quad(a.colidx, a.nnz, beg, end, q0 + (int)threadIdx.x, w);
@@ -885,9 +1041,35 @@ __device__ __forceinline__ void detect_split(const RoundArgs& a, const int* list
         const int nch = split_chunks(re - rb);
         const int beg = rb + k * SPLIT_CH, end = min(beg + SPLIT_CH, re);
         const int cv = tentative(a, v);
+        bool hit = false;
+        if (a.live) {
+            // thread 0 decides for the block: hint, a sibling's verdict, the chunk's list
+            if (tid == 0) {
+                const bool h = hint_hit(a, v, cv);
+                const int ci = a.llen[v] + k;
+                int cl = a.clen[ci];
+                const bool sk = h || ld_agent(&a.hublost[p]) != 0;
+                if (!sk && cl < 0 && a.sorted && a.colidx[beg] >= v) {
+                    cl = 0;                    // a sorted chunk above v has no lower entries
+                    a.clen[ci] = 0;
+                }
+                s.lsh[0] = h;
+                s.lsh[1] = sk;
+                s.lsh[2] = cl;
+                s.lsh[3] = ci;
+            }
+            __syncthreads();
+            hit = s.lsh[0] != 0;
+            const bool sk = s.lsh[1] != 0;
+            const int cl = s.lsh[2];
+            const int ci = s.lsh[3];
+            __syncthreads();
+            if (!sk && cl != 0) hit = live_test_wg(a, v, cv, beg, end, cl, &a.clen[ci], false, s);
+        }
         // the remembered neighbour decides for every chunk of the hub at once
-        bool hit = hint_hit(a, v, cv);
-        const bool skip = hit || ld_agent(&a.hublost[p]) != 0 || (a.rule == 0 && a.sorted && a.colidx[beg] >= v);
+        if (!a.live) hit = hint_hit(a, v, cv);
+        const bool skip = a.live || hit || ld_agent(&a.hublost[p]) != 0 ||
+                          (a.rule == 0 && a.sorted && a.colidx[beg] >= v);
         if (!skip) {
             const int nq = ((end - beg) + 3 + 3) / 4 + 1;
             for (int q0 = 0; q0 < nq; q0 += WG) {

@@ -387,3 +387,26 @@ def test_conflict_hints_on_and_off(dev, hints, mode):
     for g in graphs:
         _assert_parity(g, dev, mode=mode, hints=hints)
         _assert_parity(g, dev, mode=mode, hints=hints, lane_detect=-1, t_wave=128, t_split=1024)
+
+
+@pytest.mark.parametrize("live", [-1, 1])
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_live_lists_on_and_off(dev, live, mode):
+    """Vertices of degree > 61 may test lists of their still-uncoloured lower neighbours
+    instead of their rows (wavefront, workgroup and split-row buckets); on or off, with
+    hints on or off, sorted or unsorted rows, the colouring is the oracle's."""
+    graphs = [gg.rmat(14, 16, 8), gg.complete(200), gg.complete(1100),
+              _degree_ladder([61, 62, 300, 1024, 1025, 2048, 2049, 5000, 9000], 6),
+              gg.star(3000, [i for i in range(6001) if i != 3000]),
+              gg.shuffle_rows(gg.rmat(13, 16, 4), 5)]
+    for g in graphs:
+        _assert_parity(g, dev, mode=mode, live_lists=live)
+        _assert_parity(g, dev, mode=mode, live_lists=live, hints=-1, t_wave=128, t_split=1024)
+
+
+def test_live_lists_workspace_reuse(dev):
+    """Consecutive runs reuse the live-list buffers: stale lists of an earlier graph
+    must never be read as built lists of the next one."""
+    seq = [gg.rmat(14, 16, 9), gg.rmat(14, 16, 10), gg.rmat(12, 8, 11), gg.rmat(14, 16, 9)]
+    for g in seq:
+        _assert_parity(g, dev)
