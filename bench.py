@@ -451,6 +451,7 @@ def main() -> int:
     ap.add_argument("--rule", type=int, default=0, help="conflict rule: 0 = higher id, 1 = smaller degree requeued")
     ap.add_argument("--hints", type=int, default=0, help="conflict hints: 0 = default (on), -1 = off")
     ap.add_argument("--live-lists", type=int, default=0, help="live lists: 0 = default (on), -1 = off")
+    ap.add_argument("--ordered", type=int, default=0, help="ordered worklist compaction: 0 = default (on), -1 = off")
     ap.add_argument("--jp-seed", type=int, default=1)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
@@ -499,7 +500,7 @@ def main() -> int:
     tuned = dict(mode=args.mode, lane_assign=args.lane_assign, lane_detect=args.lane_detect,
                  t_wave=args.t_wave, t_split=args.t_split, blocks_per_cu=args.blocks_per_cu,
                  sync_every=args.sync_every, firstfit=args.firstfit, rule=args.rule, hints=args.hints,
-                 live_lists=args.live_lists)
+                 live_lists=args.live_lists, ordered=args.ordered)
     algo = {"sgr": 0, "topo": 1, "jp": 2}[args.algo]
     if args.autotune and algo == 0:
         from paper_1606_06025_amd import tune

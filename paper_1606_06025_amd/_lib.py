@@ -45,7 +45,7 @@ class Opts(ctypes.Structure):
                 ("lane_detect", ctypes.c_int32), ("firstfit", ctypes.c_int32),
                 ("rule", ctypes.c_int32), ("algorithm", ctypes.c_int32), ("seed_lo", ctypes.c_uint32),
                 ("seed_hi", ctypes.c_uint32), ("hints", ctypes.c_int32),
-                ("live_lists", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("live_lists", ctypes.c_int32), ("ordered", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -36,6 +36,8 @@ struct Workspace {
     int* llen = nullptr;         // live-list lengths (or a split row's chunk-slot base)
     int* live = nullptr;         // live lists, same offsets as colidx
     size_t live_cap = 0;         // ints
+    unsigned long long* lb = nullptr;   // look-back status words of ordered compaction
+    size_t lb_cap = 0;
     Ctl* ctl = nullptr;          // device control block
     Ctl* ctl_h = nullptr;        // pinned host mirror
     int st_cap = 0;
@@ -195,6 +197,9 @@ void free_ws_arrays(Workspace* w) {
     if (w->live) (void)hipFree(w->live);
     w->live = nullptr;
     w->live_cap = 0;
+    if (w->lb) (void)hipFree(w->lb);
+    w->lb = nullptr;
+    w->lb_cap = 0;
     free_vertex_arrays(w);
 }
 
@@ -267,6 +272,18 @@ int ensure_live(Workspace* w, size_t ints) {
     return CSRCOLOR_OK;
 }
 
+int ensure_lb(Workspace* w, size_t words) {
+    if (words <= w->lb_cap) return CSRCOLOR_OK;
+    (void)hipStreamSynchronize(w->stream);
+    if (w->lb) (void)hipFree(w->lb);
+    w->lb = nullptr;
+    w->lb_cap = 0;
+    const size_t want = std::max(words, (size_t)16384);
+    if (hipMalloc(&w->lb, want * sizeof(unsigned long long)) != hipSuccess) return CSRCOLOR_ENOMEM;
+    w->lb_cap = want;
+    return CSRCOLOR_OK;
+}
+
 int read_ctl(Workspace* w) {
     HIP_TRY(hipMemcpyAsync(w->ctl_h, w->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, w->stream));
     HIP_TRY(hipStreamSynchronize(w->stream));
@@ -285,6 +302,7 @@ struct Options {
     int pushff = 1;           // push-mode FirstFit
     int hints = 1;            // conflict hints (id rule)
     int live = 1;             // live lists for degree > 61 (id rule)
+    int ordered = 1;          // order-preserving worklist compaction
     int rule = 0;             // conflict rule (csrcolor_rule)
     int algo = CSRCOLOR_ALGO_SGR;
     unsigned long long seed = 0;
@@ -296,7 +314,8 @@ bool opts_valid(const csrcolor_opts* o, bool single) {
     if (!o) return true;
     if (o->mode < 0 || o->mode > CSRCOLOR_MODE_GRAPH || o->validate < 0 || o->firstfit < 0 || o->firstfit > 2 ||
         o->rule < 0 || o->rule > 1 || o->algorithm < 0 || o->algorithm > CSRCOLOR_ALGO_JP || o->hints < -1 ||
-        o->hints > 1 || o->live_lists < -1 || o->live_lists > 1)
+        o->hints > 1 || o->live_lists < -1 || o->live_lists > 1 ||
+        o->ordered < -1 || o->ordered > 1)
         return false;
     if (o->algorithm != CSRCOLOR_ALGO_SGR && (o->mode == CSRCOLOR_MODE_PERSISTENT || o->mode == CSRCOLOR_MODE_GRAPH))
         return false;
@@ -319,6 +338,7 @@ Options parse_opts(const csrcolor_opts* o) {
     if (o->firstfit) r.pushff = o->firstfit != 1;
     if (o->hints) r.hints = o->hints > 0;
     if (o->live_lists) r.live = o->live_lists > 0;
+    if (o->ordered) r.ordered = o->ordered > 0;
     r.rule = o->rule;
     r.algo = o->algorithm;
     r.seed = ((unsigned long long)o->seed_hi << 32) | o->seed_lo;
@@ -345,6 +365,9 @@ void make_plan(const int ub[NB], int budget, int boff[NB + 1]) {
             nb = std::max(1, (int)(share * budget + 0.5));
             const int useful = (ub[b] + plan_units_per_block(b) - 1) / plan_units_per_block(b);
             nb = std::min(nb, std::max(useful, 1));
+            // buckets that flush per workgroup: at most SUB entries per block, so the
+            // conflict test can keep the worklist order
+            if (b <= NTILE) nb = std::max(nb, (ub[b] + SUB - 1) / SUB);
         }
         boff[b + 1] = boff[b] + nb;
     }
@@ -388,7 +411,7 @@ int drive_loop(Workspace* w, Job& J, RoundArgs& a, int ub[NB], int budget, KTime
             a.wl_out = w->wl[par ^ 1];
             if (jp) {
                 a.jpc = (int)launched + 1;    // colour of this JP round
-                T.run(1, [&] { k_jp_prep<<<1, 64, 0, st>>>(a.ctl, a.par_out); });
+                T.run(1, [&] { k_jp_prep<<<1, 256, 0, st>>>(a.ctl, a.par_out, a.lbs, grid); });
             } else {
                 T.run(1, [&] { k_assign<<<grid, WG, 0, st>>>(a); });
             }
@@ -587,11 +610,25 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     // conflict hints serve the id rule (the degree rule would need the neighbour's degree too)
     int* hint = (J.opt.hints && J.opt.rule == 0) ? w->hint : nullptr;
     const int r1blocks = (int)(((long long)n + 4 * WG - 1) / (4 * WG));
+    // ordered compaction: look-back status words, NB per round-1 block, then one per
+    // block of the largest round grid (cleared before each use)
+    const int budget = cus * J.opt.blocks_per_cu;
+    const size_t lb_round = (size_t)budget + 2 * NB + (size_t)n / SUB + 8;
+    unsigned long long* lb = nullptr;
+    if (J.opt.ordered) {
+        if ((rc = ensure_lb(w, std::max((size_t)NB * r1blocks, lb_round)))) return rc;
+        lb = w->lb;
+        const size_t ints = 2 * (size_t)NB * r1blocks;
+        T.run(0, [&] {
+            k_fill<<<(int)std::min<size_t>((ints + WG - 1) / WG, (size_t)cus * 8), WG, 0, st>>>(
+                reinterpret_cast<int*>(lb), (int)ints, 0);
+        });
+    }
     T.run(0, [&] {
         k_round1<<<r1blocks, WG, 0, st>>>(n, J.rowptr, J.colidx, w->X, J.colors_out, w->wl[1], w->ctl,
                                           J.sorted, twave, J.opt.tsplit, seg, cstart1, owner1, F,
                                           w->ctl_h->nnz, J.opt.rule, J.opt.algo == CSRCOLOR_ALGO_JP, hint,
-                                          use_live ? w->llen : nullptr, clen);
+                                          use_live ? w->llen : nullptr, clen, lb);
     });
     HIP_TRY(hipGetLastError());
 
@@ -621,6 +658,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     a.rule = J.opt.rule;
     a.seed = J.opt.seed;
     a.hint = hint;
+    a.lbs = lb;
     a.live = use_live ? w->live : nullptr;
     a.llen = use_live ? w->llen : nullptr;
     a.clen = clen;
@@ -633,7 +671,6 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
         HIP_TRY(hipMemsetAsync(w->st_arcs, 0, st_cap * sizeof(long long), st));
     }
 
-    const int budget = cus * J.opt.blocks_per_cu;
     if (J.opt.mode == CSRCOLOR_MODE_PERSISTENT) {
         rc = drive_persistent(w, J, a, budget, T);
     } else if (J.opt.mode == CSRCOLOR_MODE_GRAPH) {

@@ -107,7 +107,9 @@ struct Ctl {
     int hchunks;        // chunks over all split-bucket vertices
     int ccnt[2];        // chunks queued in the split bucket, by round parity
     int pdone;          // persistent mode: set when a round found every queue empty
-    int pad[4];
+    int tk[8];          // ordered compaction: conflict-test tickets per bucket (reset by FirstFit)
+    int tk1;            // ordered compaction: round-1 tickets
+    int pad[3];
     // device-wide barrier of the persistent mode, each counter on its own 128-byte line
     int bar[8][32];
     int bar_top[32];
@@ -155,6 +157,9 @@ struct RoundArgs {
     int* live;
     int* llen;
     int* clen;
+    // ordered compaction (nullptr = off): one look-back status word per block of the
+    // grid, cleared by the FirstFit launch of the round
+    unsigned long long* lbs;
     // JP (rule RULE_JP): this round's colour and the priority generator's seed
     int jpc;
     unsigned long long seed;

@@ -113,7 +113,8 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
                                                const int* __restrict__ colidx, int* X, int* out,
                                                int* wl1, Ctl* ctl, int sorted, int twave, int tsplit,
                                                Seg seg, int* cstart1, int* owner1, unsigned* F, int nnz,
-                                               int rule, int jp, int* hint, int* llen, int* clen) {
+                                               int rule, int jp, int* hint, int* llen, int* clen,
+                                               unsigned long long* lb1) {
     constexpr int ITER = 4;
     __shared__ int buf[WAVES][NB][ITER * 64];
     __shared__ int wcnt[WAVES][NB];
@@ -125,7 +126,14 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
     // an isolated vertex is alone in its neighbourhood and takes colour 1 here), and
     // the conflict-test launches count the rounds.
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->rounds = jp ? 0 : 1;
-    const long long chunk0 = (long long)blockIdx.x * (ITER * WG);
+    // ordered mode (lb1): the block works on the vertex range of its ticket, and each
+    // bucket's run is placed after the runs of the lower tickets (look-back), so every
+    // worklist segment starts in ascending id order
+    __shared__ int ticket;
+    if (threadIdx.x == 0) ticket = lb1 ? atomicAdd(&ctl->tk1, 1) : (int)blockIdx.x;
+    __syncthreads();
+    const int unit = ticket;
+    const long long chunk0 = (long long)unit * (ITER * WG);
     for (int it = 0; it < ITER; ++it) {
         // wavefront wv owns the 64*ITER consecutive vertices starting at chunk0 + wv*64*ITER,
         // so concatenating the per-wavefront buffers keeps ascending vertex order
@@ -199,7 +207,25 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
         for (int b = 0; b < NB; ++b) wcnt[wv][b] = cnt[b];
     }
     __syncthreads();
-    if (threadIdx.x < NB) {
+    if (lb1) {
+        // one wavefront per bucket runs its look-back (wavefront w: buckets w, w + WAVES);
+        // every count is published before any walk starts
+        for (int b = wv; b < NB; b += WAVES) {
+            int tot = 0;
+            for (int w = 0; w < WAVES; ++w) tot += wcnt[w][b];
+            lookback_publish(lb1 + (size_t)b * gridDim.x, unit, tot);
+        }
+        for (int b = wv; b < NB; b += WAVES) {
+            int tot = 0;
+            for (int w = 0; w < WAVES; ++w) tot += wcnt[w][b];
+            const int base = lookback_walk(lb1 + (size_t)b * gridDim.x, unit, tot);
+            if (lane == 0) {
+                if (tot) atomicAdd(&ctl->cnt[1][b], tot);
+                int bs = base;
+                for (int w = 0; w < WAVES; ++w) { wbase[w][b] = bs; bs += wcnt[w][b]; }
+            }
+        }
+    } else if (threadIdx.x < NB) {
         const int b = threadIdx.x;
         int tot = 0;
         for (int w = 0; w < WAVES; ++w) tot += wcnt[w][b];

@@ -463,6 +463,54 @@ __device__ __forceinline__ unsigned or_agent(unsigned* p, unsigned v) {
 __device__ __forceinline__ int add_agent(int* p, int v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ unsigned long long ld_agent(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Decoupled look-back (Merrill and Garland's single-pass prefix scan), run by one
+// whole wavefront: unit u publishes its count c, then reads the status words of the
+// 64 units before it at once and adds up counts back to the nearest unit that has
+// published its inclusive prefix (further windows of 64 if none has), and publishes
+// its own.  Status words: high half 0 = nothing yet, 1 = count, 2 = inclusive prefix;
+// low half the value.  Units are numbered in the order their blocks took a ticket, so
+// every unit waited on belongs to a block that is already running and publishes its
+// count without waiting: the walk always ends.  Returns the exclusive prefix of u in
+// every lane.
+__device__ __forceinline__ void lookback_publish(unsigned long long* st, int u, int c) {
+    if (__lane_id() == 0) st_agent(&st[u], ((u == 0 ? 2ull : 1ull) << 32) | (unsigned)c);
+}
+__device__ __forceinline__ int lookback_walk(unsigned long long* st, int u, int c) {
+    const int lane = __lane_id();
+    if (u == 0) return 0;
+    int excl = 0;
+    for (int base = u - 1;;) {
+        const int k = base - lane;
+        const unsigned long long x = k >= 0 ? ld_agent(&st[k]) : (2ull << 32);   // before unit 0: prefix 0
+        const unsigned kind = (unsigned)(x >> 32);
+        const unsigned long long incl = __ballot(kind == 2);
+        const unsigned long long notready = __ballot(kind == 0);
+        // the lanes up to the nearest inclusive prefix (or all 64) must have published
+        const int stop = incl ? __ffsll((long long)incl) - 1 : 63;
+        const unsigned long long need = (2ull << stop) - 1ull;
+        if (notready & need) continue;
+        int v = lane <= stop ? (int)(unsigned)x : 0;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        excl += v;
+        if (incl) break;
+        base -= 64;
+    }
+    if (lane == 0) st_agent(&st[u], (2ull << 32) | (unsigned)(excl + c));
+    return excl;
+}
+__device__ __forceinline__ int lookback(unsigned long long* st, int u, int c) {
+    lookback_publish(st, u, c);
+    return lookback_walk(st, u, c);
+}
+
 // Makes the wavefront wait until `v` (the result of an atomic) has arrived, and keeps
 // later memory operations after that point.
 __device__ __forceinline__ void wait_on(unsigned v) { asm volatile("" ::"v"(v) : "memory"); }
@@ -537,9 +585,12 @@ __device__ __forceinline__ void assign_phase(const RoundArgs& a, RoundLds& s, in
         for (int k = 0; k < NB; ++k) {
             a.ctl->cnt[a.par_out][k] = 0;
             a.ctl->dyn[1][k] = 0;
+            st_agent(&a.ctl->tk[k], 0);
         }
         a.ctl->ccnt[a.par_out] = 0;
     }
+    // the conflict test of this round uses one look-back status word per block
+    if (a.lbs && threadIdx.x == 0) st_agent(&a.lbs[bid], 0ull);
     if (bid >= boff[NB]) return;
     const int cnt = a.ctl->cnt[a.par_in][b];
     const int* list = a.wl_in + a.seg[b];
@@ -609,18 +660,33 @@ __device__ __forceinline__ void settle(const RoundArgs& a, int v, int cv, int& c
 }
 
 // Writes the per-wavefront loser buffers to the global worklist with one atomic per
-// workgroup.  `wc` is the calling wavefront's count (uniform).  Buffers hold
+// workgroup; in ordered mode (unit_st) at the position a look-back gives, so the
+// worklist keeps ascending id order from round to round.  `wc` is the calling wavefront's count (uniform).  Buffers hold
 // ascending worklist positions and wavefronts own ascending slices, so each flush
 // is one run in worklist order.
-__device__ __forceinline__ void flush_losers(RoundLds& s, int wc, int* outl, int* cnt_out) {
+__device__ __forceinline__ void flush_losers(RoundLds& s, int wc, int* outl, int* cnt_out,
+                                             unsigned long long* unit_st, int unit) {
     const int lane = __lane_id();
     const int wv = threadIdx.x >> 6;
     if (lane == 0) s.wcnt[wv] = wc;
     __syncthreads();
+    int lbase = 0;
+    if (unit_st && wv == 0) {
+        // ordered: this block's run goes right after the runs of the blocks before it
+        int tot = 0;
+        for (int w = 0; w < WAVES; ++w) tot += s.wcnt[w];
+        lbase = lookback(unit_st, unit, tot);
+    }
     if (threadIdx.x == 0) {
         int tot = 0;
         for (int w = 0; w < WAVES; ++w) tot += s.wcnt[w];
-        int base = tot ? atomicAdd(cnt_out, tot) : 0;
+        int base;
+        if (unit_st) {
+            base = lbase;
+            if (tot) atomicAdd(cnt_out, tot);
+        } else {
+            base = tot ? atomicAdd(cnt_out, tot) : 0;
+        }
         for (int w = 0; w < WAVES; ++w) {
             s.wbase[w] = base;
             base += s.wcnt[w];
@@ -643,7 +709,7 @@ __device__ __forceinline__ void push_losers(int v_l, bool lost_l, int* mybuf, in
 
 template <int L>
 __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list, int lo, int hi, RoundLds& s,
-                                             int* outl, int* cnt_out, int& cmax) {
+                                             int* outl, int* cnt_out, int& cmax, unsigned long long* ust, int unit) {
     constexpr int V = 64 / L;
     const int lane = __lane_id();
     const int wv = threadIdx.x >> 6;
@@ -695,7 +761,7 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
             if (a.pushff) push_rows_wave(a, v_l >= 0 && !lost_l, v_l, cv_l, beg_l, end_l);
             push_losers(v_l, lost_l, mybuf, wc);
         }
-        flush_losers(s, wc, outl, cnt_out);
+        flush_losers(s, wc, outl, cnt_out, ust, unit);
     }
 }
 
@@ -703,7 +769,7 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
 // of its own row quad by quad and stops at its first conflict (or, for sorted rows,
 // at its first w >= v); the wavefront moves on when all its lanes have stopped.
 __device__ __forceinline__ void detect_lanes(const RoundArgs& a, const int* list, int lo, int hi, RoundLds& s,
-                                             int* outl, int* cnt_out, int& cmax) {
+                                             int* outl, int* cnt_out, int& cmax, unsigned long long* ust, int unit) {
     const int lane = __lane_id();
     const int wv = threadIdx.x >> 6;
     int* mybuf = s.lbuf + wv * WAVE_CAP;
@@ -752,7 +818,7 @@ __device__ __forceinline__ void detect_lanes(const RoundArgs& a, const int* list
             if (a.pushff) push_rows_wave(a, v_l >= 0 && !lost, v_l, cv, beg, end);
             push_losers(v_l, lost, mybuf, wc);
         }
-        flush_losers(s, wc, outl, cnt_out);
+        flush_losers(s, wc, outl, cnt_out, ust, unit);
     }
 }
 
@@ -819,10 +885,15 @@ __device__ __forceinline__ bool live_test_wave(const RoundArgs& a, int v, int cv
         bool hit = false, stop = false;
         live_step(a, src, rb, send, q0 + lane, v, cv, build, w, keep, hit, stop);
         int tot;
-        int pos = K + wave_excl(__popc(keep), tot);
+        int pos = rb + K + wave_excl(__popc(keep), tot);
+        const int qs = rb + quad_end(src, rb, q0 + lane);   // position of w[0] in src
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (keep >> k & 1) a.live[rb + pos++] = w[k];
+        for (int k = 0; k < 4; ++k) {
+            if (keep >> k & 1) {
+                if (build || pos != qs + k) a.live[pos] = w[k];   // an entry already in place stays
+                ++pos;
+            }
+        }
         K += tot;
         const bool anyhit = __ballot(hit) != 0;
         lost |= anyhit;
@@ -876,10 +947,15 @@ __device__ __forceinline__ bool live_test_wg(const RoundArgs& a, int v, int cv, 
             before += k < wv ? s.lpre[k] : 0;
             tot += s.lpre[k];
         }
-        int pos = K + before + wex;
+        int pos = rb + K + before + wex;
+        const int qs = rb + quad_end(src, rb, q0 + tid);
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (keep >> k & 1) a.live[rb + pos++] = w[k];
+        for (int k = 0; k < 4; ++k) {
+            if (keep >> k & 1) {
+                if (build || pos != qs + k) a.live[pos] = w[k];
+                ++pos;
+            }
+        }
         K += tot;
         const int anyhit = __syncthreads_or(hit);
         const int anystop = __syncthreads_or(stop);
@@ -905,7 +981,7 @@ __device__ __forceinline__ bool live_test_wg(const RoundArgs& a, int v, int cv, 
 // lower part of one row at a time (256 arcs per step; for sorted rows the scan stops
 // at the first w >= v, and at the first conflict in any case).
 __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list, int lo, int hi, RoundLds& s,
-                                            int* outl, int* cnt_out, int& cmax) {
+                                            int* outl, int* cnt_out, int& cmax, unsigned long long* ust, int unit) {
     const int lane = __lane_id();
     const int wv = threadIdx.x >> 6;
     int* mybuf = s.lbuf + wv * WAVE_CAP;
@@ -964,7 +1040,7 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
             if (a.pushff) push_rows_wave(a, v_l >= 0 && !lost_l, v_l, cv_l, beg_l, end_l);
             push_losers(v_l, lost_l, mybuf, wc);
         }
-        flush_losers(s, wc, outl, cnt_out);
+        flush_losers(s, wc, outl, cnt_out, ust, unit);
     }
 }
 
@@ -1138,17 +1214,33 @@ __device__ __forceinline__ void detect_phase(const RoundArgs& a, RoundLds& s, in
     const int* list = a.wl_in + a.seg[b];
     int* outl = a.wl_out + a.seg[b];
     int* cnt_out = &a.ctl->cnt[a.par_out][b];
+    // Ordered compaction for the buckets that flush per workgroup, when every block's
+    // range fits one flush: the block takes a ticket, works on the ticket's range and
+    // writes its losers after those of the lower tickets.
+    unsigned long long* ust = nullptr;
+    if (a.lbs && b <= NTILE && (long long)cnt <= (long long)SUB * nbk) {
+        if (threadIdx.x == 0) s.lsh[0] = atomicAdd(&a.ctl->tk[b], 1);
+        __syncthreads();
+        j = s.lsh[0];
+        __syncthreads();
+        ust = a.lbs + boff[b];
+    }
     const int lo = (int)((long long)j * cnt / nbk);
     const int hi = (int)((long long)(j + 1) * cnt / nbk);
+    if (ust && lo >= hi) {
+        // an empty range still publishes its (zero) count for the blocks after it
+        if (threadIdx.x < 64) lookback(ust, j, 0);
+        return;
+    }
     if (b < NTILE && (a.lane_mode_detect >> b & 1)) {
-        detect_lanes(a, list, lo, hi, s, outl, cnt_out, cmax);
+        detect_lanes(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j);
     } else {
         switch (b) {
-            case 0: detect_tiles<2>(a, list, lo, hi, s, outl, cnt_out, cmax); break;
-            case 1: detect_tiles<4>(a, list, lo, hi, s, outl, cnt_out, cmax); break;
-            case 2: detect_tiles<8>(a, list, lo, hi, s, outl, cnt_out, cmax); break;
-            case 3: detect_tiles<16>(a, list, lo, hi, s, outl, cnt_out, cmax); break;
-            case 4: detect_wave(a, list, lo, hi, s, outl, cnt_out, cmax); break;
+            case 0: detect_tiles<2>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j); break;
+            case 1: detect_tiles<4>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j); break;
+            case 2: detect_tiles<8>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j); break;
+            case 3: detect_tiles<16>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j); break;
+            case 4: detect_wave(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j); break;
             case 5: detect_wg(a, list, cnt, s, outl, cnt_out, cmax); break;
             default: detect_split(a, list, a.ctl->ccnt[a.par_in], j, nbk, s, outl, cnt_out, cmax); break;
         }
@@ -1157,13 +1249,16 @@ __device__ __forceinline__ void detect_phase(const RoundArgs& a, RoundLds& s, in
 
 // JP rounds have no FirstFit phase, whose first block otherwise clears the output
 // queue counters and the conflict-test work counters of the round.
-__global__ void k_jp_prep(Ctl* ctl, int par_out) {
+__global__ void k_jp_prep(Ctl* ctl, int par_out, unsigned long long* lbs, int nlbs) {
     const int k = threadIdx.x;
     if (k < NB) {
         ctl->cnt[par_out][k] = 0;
         ctl->dyn[1][k] = 0;
+        ctl->tk[k] = 0;
     }
     if (k == 0) ctl->ccnt[par_out] = 0;
+    if (lbs)
+        for (int i = k; i < nlbs; i += blockDim.x) lbs[i] = 0;
 }
 
 __global__ __launch_bounds__(WG) void k_detect(RoundArgs a) {

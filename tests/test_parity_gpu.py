@@ -410,3 +410,19 @@ def test_live_lists_workspace_reuse(dev):
     seq = [gg.rmat(14, 16, 9), gg.rmat(14, 16, 10), gg.rmat(12, 8, 11), gg.rmat(14, 16, 9)]
     for g in seq:
         _assert_parity(g, dev)
+
+
+@pytest.mark.parametrize("ordered", [-1, 1])
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_ordered_compaction_on_and_off(dev, ordered, mode):
+    """Blocks may take tickets and place their losers after those of lower tickets
+    (look-back prefix) so the worklist keeps id order; on or off, in every drive mode
+    and with more blocks than fit on the device at once, the colouring is the oracle's."""
+    graphs = [gg.stencil27(64, 64, 64), gg.rmat(16, 16, 12), gg.erdos_renyi(300000, 2400000, 13),
+              _degree_ladder([5, 13, 29, 61, 300, 1500, 2500], 7), gg.edgeless(5000)]
+    for g in graphs:
+        _assert_parity(g, dev, mode=mode, ordered=ordered)
+    if mode == 1:
+        for kw in (dict(blocks_per_cu=1), dict(blocks_per_cu=32), dict(sync_every=1, blocks_per_cu=2)):
+            _assert_parity(graphs[0], dev, ordered=ordered, **kw)
+            _assert_parity(graphs[1], dev, ordered=ordered, **kw)
