@@ -98,7 +98,8 @@ struct Ctl {
     int dyn[2][8];      // dynamic work counters for workgroup-per-vertex buckets (per phase)
     int hist[8];        // vertices per degree bucket (deg >= 1)
     int maxcolor;       // largest settled colour
-    int err;            // bit 0: rowptr, bit 1: colidx range, bit 2: asymmetric, bit 3: internal
+    int err;            // bit 0: rowptr, bit 1: colidx range, bit 2: asymmetric, bit 3: internal,
+                        // bit 4: a look-back walk gave up
     int desc_total;     // positions e >= 1 with colidx[e] < colidx[e-1]
     int desc_bound;     // such positions that start a non-empty row
     int maxdeg;

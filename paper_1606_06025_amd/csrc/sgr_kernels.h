@@ -218,10 +218,10 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
         for (int b = wv; b < NB; b += WAVES) {
             int tot = 0;
             for (int w = 0; w < WAVES; ++w) tot += wcnt[w][b];
-            const int base = lookback_walk(lb1 + (size_t)b * gridDim.x, unit, tot);
+            const int base = lookback_walk(lb1 + (size_t)b * gridDim.x, unit, tot, &ctl->err);
             if (lane == 0) {
-                if (tot) atomicAdd(&ctl->cnt[1][b], tot);
-                int bs = base;
+                const int pos = tot ? atomicAdd(&ctl->cnt[1][b], tot) : 0;
+                int bs = base >= 0 ? base : pos;   // a walk that gave up takes the unordered slot
                 for (int w = 0; w < WAVES; ++w) { wbase[w][b] = bs; bs += wcnt[w][b]; }
             }
         }

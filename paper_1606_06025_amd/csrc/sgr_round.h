@@ -478,15 +478,22 @@ __device__ __forceinline__ void st_agent(unsigned long long* p, unsigned long lo
 // low half the value.  Units are numbered in the order their blocks took a ticket, so
 // every unit waited on belongs to a block that is already running and publishes its
 // count without waiting: the walk always ends.  Returns the exclusive prefix of u in
-// every lane.
+// every lane (-1 if the walk gave up; the caller then takes an unordered position).
 __device__ __forceinline__ void lookback_publish(unsigned long long* st, int u, int c) {
     if (__lane_id() == 0) st_agent(&st[u], ((u == 0 ? 2ull : 1ull) << 32) | (unsigned)c);
 }
-__device__ __forceinline__ int lookback_walk(unsigned long long* st, int u, int c) {
+__device__ __forceinline__ int lookback_walk(unsigned long long* st, int u, int c, int* err) {
     const int lane = __lane_id();
     if (u == 0) return 0;
     int excl = 0;
+    int spins = 0;
     for (int base = u - 1;;) {
+        // safety net: a unit that never publishes would be a bug; flag it (the host
+        // then fails the call) rather than spin forever
+        if (++spins > (1 << 22)) {
+            if (lane == 0) atomicOr(err, 16);
+            return -1;
+        }
         const int k = base - lane;
         const unsigned long long x = k >= 0 ? ld_agent(&st[k]) : (2ull << 32);   // before unit 0: prefix 0
         const unsigned kind = (unsigned)(x >> 32);
@@ -506,9 +513,9 @@ __device__ __forceinline__ int lookback_walk(unsigned long long* st, int u, int 
     if (lane == 0) st_agent(&st[u], (2ull << 32) | (unsigned)(excl + c));
     return excl;
 }
-__device__ __forceinline__ int lookback(unsigned long long* st, int u, int c) {
+__device__ __forceinline__ int lookback(unsigned long long* st, int u, int c, int* err) {
     lookback_publish(st, u, c);
-    return lookback_walk(st, u, c);
+    return lookback_walk(st, u, c, err);
 }
 
 // Makes the wavefront wait until `v` (the result of an atomic) has arrived, and keeps
@@ -665,7 +672,7 @@ __device__ __forceinline__ void settle(const RoundArgs& a, int v, int cv, int& c
 // ascending worklist positions and wavefronts own ascending slices, so each flush
 // is one run in worklist order.
 __device__ __forceinline__ void flush_losers(RoundLds& s, int wc, int* outl, int* cnt_out,
-                                             unsigned long long* unit_st, int unit) {
+                                             unsigned long long* unit_st, int unit, int* err) {
     const int lane = __lane_id();
     const int wv = threadIdx.x >> 6;
     if (lane == 0) s.wcnt[wv] = wc;
@@ -675,13 +682,13 @@ __device__ __forceinline__ void flush_losers(RoundLds& s, int wc, int* outl, int
         // ordered: this block's run goes right after the runs of the blocks before it
         int tot = 0;
         for (int w = 0; w < WAVES; ++w) tot += s.wcnt[w];
-        lbase = lookback(unit_st, unit, tot);
+        lbase = lookback(unit_st, unit, tot, err);
     }
     if (threadIdx.x == 0) {
         int tot = 0;
         for (int w = 0; w < WAVES; ++w) tot += s.wcnt[w];
         int base;
-        if (unit_st) {
+        if (unit_st && lbase >= 0) {
             base = lbase;
             if (tot) atomicAdd(cnt_out, tot);
         } else {
@@ -761,7 +768,7 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
             if (a.pushff) push_rows_wave(a, v_l >= 0 && !lost_l, v_l, cv_l, beg_l, end_l);
             push_losers(v_l, lost_l, mybuf, wc);
         }
-        flush_losers(s, wc, outl, cnt_out, ust, unit);
+        flush_losers(s, wc, outl, cnt_out, ust, unit, &a.ctl->err);
     }
 }
 
@@ -818,7 +825,7 @@ __device__ __forceinline__ void detect_lanes(const RoundArgs& a, const int* list
             if (a.pushff) push_rows_wave(a, v_l >= 0 && !lost, v_l, cv, beg, end);
             push_losers(v_l, lost, mybuf, wc);
         }
-        flush_losers(s, wc, outl, cnt_out, ust, unit);
+        flush_losers(s, wc, outl, cnt_out, ust, unit, &a.ctl->err);
     }
 }
 
@@ -1040,7 +1047,7 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
             if (a.pushff) push_rows_wave(a, v_l >= 0 && !lost_l, v_l, cv_l, beg_l, end_l);
             push_losers(v_l, lost_l, mybuf, wc);
         }
-        flush_losers(s, wc, outl, cnt_out, ust, unit);
+        flush_losers(s, wc, outl, cnt_out, ust, unit, &a.ctl->err);
     }
 }
 
@@ -1229,7 +1236,7 @@ __device__ __forceinline__ void detect_phase(const RoundArgs& a, RoundLds& s, in
     const int hi = (int)((long long)(j + 1) * cnt / nbk);
     if (ust && lo >= hi) {
         // an empty range still publishes its (zero) count for the blocks after it
-        if (threadIdx.x < 64) lookback(ust, j, 0);
+        if (threadIdx.x < 64) lookback(ust, j, 0, &a.ctl->err);
         return;
     }
     if (b < NTILE && (a.lane_mode_detect >> b & 1)) {
