@@ -119,7 +119,7 @@ typedef struct {
     int32_t live_lists;     /* 0: default (on); 1: on; -1: off.  Live lists (id rule): a vertex of degree > 61
                                tests a list of its lower neighbours that were still uncoloured when last seen,
                                shrunk as they settle, instead of its row (same colouring) */
-    int32_t ordered;        /* 0: default (on); 1: on; -1: off.  Order-preserving worklist compaction: blocks
+    int32_t ordered;        /* 0: default (off); 1: on; -1: off.  Order-preserving worklist compaction: blocks
                                take tickets and place their losers after those of lower tickets (look-back
                                prefix), so every worklist keeps ascending id order (same colouring) */
 } csrcolor_opts;

@@ -302,7 +302,7 @@ struct Options {
     int pushff = 1;           // push-mode FirstFit
     int hints = 1;            // conflict hints (id rule)
     int live = 1;             // live lists for degree > 61 (id rule)
-    int ordered = 1;          // order-preserving worklist compaction
+    int ordered = 0;          // order-preserving worklist compaction (measured slower on the stencil)
     int rule = 0;             // conflict rule (csrcolor_rule)
     int algo = CSRCOLOR_ALGO_SGR;
     unsigned long long seed = 0;
