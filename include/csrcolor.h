@@ -106,9 +106,10 @@ typedef struct {
     int32_t lane_assign;    /* bit b (b < 4): low-degree bucket b runs FirstFit one lane per vertex;
                                0 = default; -1 = none (all use 2/4/8/16 lanes per vertex) */
     int32_t lane_detect;    /* the same for the conflict test */
-    int32_t firstfit;       /* 0: default (push); 1: rescan: every FirstFit gathers all neighbour colours
-                               (as printed in the paper); 2: push: a vertex that settles marks its colour in
-                               a per-neighbour bitmap and FirstFit reads that bitmap (same colouring) */
+    int32_t firstfit;       /* 0: default (push, bit flags); 1: rescan: every FirstFit gathers all neighbour
+                               colours (as printed in the paper); 2: push: a vertex that settles marks its
+                               colour in per-neighbour flags (bits, set by atomic OR) and FirstFit reads its
+                               own flags; 3: push with byte flags (plain stores).  Same colouring */
     int32_t rule;           /* conflict rule, csrcolor_rule; CHANGES the colouring (each rule is exact) */
     int32_t algorithm;      /* csrcolor_algorithm (default CSRCOLOR_ALGO_SGR) */
     uint32_t seed_lo;       /* JP: low and high 32 bits of the 64-bit priority seed */

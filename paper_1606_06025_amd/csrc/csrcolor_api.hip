@@ -299,7 +299,7 @@ struct Options {
     int tsplit = 2048;
     int lane_assign = 0;      // tile buckets run with 2/4/8/16 lanes per vertex
     int lane_detect = 0xF;    // lane-per-vertex conflict test (early exit) in every tile bucket
-    int pushff = 1;           // push-mode FirstFit
+    int pushff = 1;           // FirstFit: 0 rescan, 1 push with bit flags, 2 push with byte flags
     int hints = 1;            // conflict hints (id rule)
     int live = 1;             // live lists for degree > 61 (id rule)
     int ordered = 0;          // order-preserving worklist compaction (measured slower on the stencil)
@@ -312,7 +312,7 @@ struct Options {
 // multi-graph calls, which do not take JP (its priorities depend on global ids).
 bool opts_valid(const csrcolor_opts* o, bool single) {
     if (!o) return true;
-    if (o->mode < 0 || o->mode > CSRCOLOR_MODE_GRAPH || o->validate < 0 || o->firstfit < 0 || o->firstfit > 2 ||
+    if (o->mode < 0 || o->mode > CSRCOLOR_MODE_GRAPH || o->validate < 0 || o->firstfit < 0 || o->firstfit > 3 ||
         o->rule < 0 || o->rule > 1 || o->algorithm < 0 || o->algorithm > CSRCOLOR_ALGO_JP || o->hints < -1 ||
         o->hints > 1 || o->live_lists < -1 || o->live_lists > 1 ||
         o->ordered < -1 || o->ordered > 1)
@@ -335,7 +335,7 @@ Options parse_opts(const csrcolor_opts* o) {
     r.tsplit = std::max(r.tsplit, r.twave);
     if (o->lane_assign) r.lane_assign = o->lane_assign < 0 ? 0 : (o->lane_assign & 0xF);
     if (o->lane_detect) r.lane_detect = o->lane_detect < 0 ? 0 : (o->lane_detect & 0xF);
-    if (o->firstfit) r.pushff = o->firstfit != 1;
+    if (o->firstfit) r.pushff = o->firstfit - 1;
     if (o->hints) r.hints = o->hints > 0;
     if (o->live_lists) r.live = o->live_lists > 0;
     if (o->ordered) r.ordered = o->ordered > 0;
@@ -598,7 +598,9 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     // push mode: deg(v)+1 bits per vertex, zeroed
     unsigned* F = nullptr;
     if (J.opt.pushff) {
-        const size_t words = ((size_t)w->ctl_h->nnz + (size_t)n) / 32 + 2;
+        // one flag per (vertex, colour <= deg+1): bits, or bytes
+        const size_t flags = (size_t)w->ctl_h->nnz + (size_t)n;
+        const size_t words = J.opt.pushff == 2 ? flags / 4 + 4 : flags / 32 + 2;
         if ((rc = ensure_F(w, words))) return rc;
         F = w->F;
         T.run(0, [&] {
@@ -628,7 +630,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
         k_round1<<<r1blocks, WG, 0, st>>>(n, J.rowptr, J.colidx, w->X, J.colors_out, w->wl[1], w->ctl,
                                           J.sorted, twave, J.opt.tsplit, seg, cstart1, owner1, F,
                                           w->ctl_h->nnz, J.opt.rule, J.opt.algo == CSRCOLOR_ALGO_JP, hint,
-                                          use_live ? w->llen : nullptr, clen, lb);
+                                          use_live ? w->llen : nullptr, clen, lb, J.opt.pushff == 2);
     });
     HIP_TRY(hipGetLastError());
 

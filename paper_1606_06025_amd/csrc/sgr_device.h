@@ -62,14 +62,23 @@ __device__ __forceinline__ bool conflict(int rule, const int* __restrict__ rowpt
     return (X[w] & 0x7fffffff) == cv && beats(1, rowptr, w, v, dv);
 }
 
-// Marks colour c in the forbidden bitmap of neighbour u (push-mode FirstFit).  Only
-// colours <= deg(u)+1 can change u's smallest free colour, and only they have a bit.
-__device__ __forceinline__ void push_colour(unsigned* F, const int* __restrict__ rowptr, int u, int c) {
+// Marks colour c among the forbidden colours of neighbour u (push-mode FirstFit).
+// Only colours <= deg(u)+1 can change u's smallest free colour, and only they have a
+// flag: flag c-1 of u sits at position rowptr[u]+u+c-1, one bit of F (set with an
+// atomic OR, several neighbours may share a word) or, with `bytes`, one byte (a plain
+// store: concurrent writers of one byte all write 1, and distinct bytes of a line are
+// merged by the caches).
+__device__ __forceinline__ void push_colour(unsigned* F, const int* __restrict__ rowptr, int u, int c,
+                                            bool bytes) {
     const int ub = rowptr[u];
     const int du = rowptr[u + 1] - ub;
     if (c - 1 <= du) {
-        const long long bit = (long long)ub + u + c - 1;
-        atomicOr(&F[bit >> 5], 1u << (bit & 31));
+        const long long pos = (long long)ub + u + c - 1;
+        if (bytes) {
+            reinterpret_cast<unsigned char*>(F)[pos] = 1;
+        } else {
+            atomicOr(&F[pos >> 5], 1u << (pos & 31));
+        }
     }
 }
 
@@ -142,7 +151,7 @@ struct RoundArgs {
     int dev_plan;          // 1: every block derives the bucket partition from the device queue sizes
     // push mode: F holds, for every vertex v, deg(v)+1 bits starting at bit rowptr[v]+v;
     // bit c-1 set <=> a neighbour settled with colour c in an earlier round
-    int pushff;
+    int pushff;         // 0: rescan FirstFit; 1: push, bit flags; 2: push, byte flags
     unsigned* F;
     // conflict rule: 0 = the higher id is requeued; 1 = the smaller degree (row
     // length) is requeued, the higher id on equal degree (heuristic of Sec. 3.2)

@@ -140,19 +140,19 @@ __device__ __forceinline__ void wave_slice(int lo, int hi, int& wlo, int& whi) {
 // `nthr` threads (thread index t) push colour c of v over row [beg, end) together.
 __device__ __forceinline__ void push_row_coop(unsigned* F, const int* __restrict__ rowptr,
                                               const int* __restrict__ colidx, int nnz, int v, int c, int beg,
-                                              int end, int t, int nthr) {
+                                              int end, int t, int nthr, bool bytes) {
     const int nq = ((end - beg) + 3 + 3) / 4 + 1;
     for (int q0 = 0; q0 < nq; q0 += nthr) {
         int w[4];
         load_quad(colidx, nnz, beg, end, q0 + t, w);
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (w[k] >= 0 && w[k] != v) push_colour(F, rowptr, w[k], c);
+            if (w[k] >= 0 && w[k] != v) push_colour(F, rowptr, w[k], c, bytes);
     }
 }
 __device__ __forceinline__ void push_row_coop(const RoundArgs& a, int v, int c, int beg, int end, int t,
                                               int nthr) {
-    push_row_coop(a.F, a.rowptr, a.colidx, a.nnz, v, c, beg, end, t, nthr);
+    push_row_coop(a.F, a.rowptr, a.colidx, a.nnz, v, c, beg, end, t, nthr, a.pushff == 2);
 }
 
 // The whole wavefront pushes the colours of its winners: lane l contributes the row
@@ -162,7 +162,7 @@ __device__ __forceinline__ void push_row_coop(const RoundArgs& a, int v, int c, 
 // or a few short winner rows does not serialise on one lane.  Every lane must call.
 __device__ __forceinline__ void push_rows_wave(unsigned* F, const int* __restrict__ rowptr,
                                                const int* __restrict__ colidx, int nnz, bool win, int v, int c,
-                                               int beg, int end) {
+                                               int beg, int end, bool bytes) {
     const int lane = __lane_id();
     const int mis = (int)((reinterpret_cast<uintptr_t>(colidx) >> 2) & 3);
     const int nq = win && end > beg ? (((end - 1 + mis) >> 2) - ((beg + mis) >> 2) + 1) : 0;
@@ -191,12 +191,12 @@ __device__ __forceinline__ void push_rows_wave(unsigned* F, const int* __restric
             load_quad(colidx, nnz, bj, ej, q, w);
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                if (w[k] >= 0 && w[k] != vj) push_colour(F, rowptr, w[k], cj);
+                if (w[k] >= 0 && w[k] != vj) push_colour(F, rowptr, w[k], cj, bytes);
         }
     }
 }
 __device__ __forceinline__ void push_rows_wave(const RoundArgs& a, bool win, int v, int c, int beg, int end) {
-    push_rows_wave(a.F, a.rowptr, a.colidx, a.nnz, win, v, c, beg, end);
+    push_rows_wave(a.F, a.rowptr, a.colidx, a.nnz, win, v, c, beg, end, a.pushff == 2);
 }
 
 // Push-mode FirstFit for any bucket: one lane per vertex finds the first clear bit
@@ -212,10 +212,24 @@ __device__ __forceinline__ void assign_push(const RoundArgs& a, const int* list,
             const int v = list[t0 + lane];
             const int beg = a.rowptr[v];
             const long long bit = (long long)beg + v;
-            long long wi = bit >> 5;
-            unsigned wd = a.F[wi] | ((1u << (bit & 31)) - 1u);
-            while (wd == 0xffffffffu) wd = a.F[++wi];
-            const long long pos = wi * 32 + __ffs(~wd) - 1;
+            long long pos;
+            if (a.pushff == 2) {
+                // byte flags: the first zero byte at or after `bit`, four bytes per load
+                // (bytes before `bit` count as set)
+                long long wi = bit >> 2;
+                unsigned wd = a.F[wi] | ((1u << (8 * (bit & 3))) - 1u);
+                unsigned z = (wd - 0x01010101u) & ~wd & 0x80808080u;
+                while (z == 0) {
+                    wd = a.F[++wi];
+                    z = (wd - 0x01010101u) & ~wd & 0x80808080u;
+                }
+                pos = wi * 4 + (__ffs(z) - 1) / 8;
+            } else {
+                long long wi = bit >> 5;
+                unsigned wd = a.F[wi] | ((1u << (bit & 31)) - 1u);
+                while (wd == 0xffffffffu) wd = a.F[++wi];
+                pos = wi * 32 + __ffs(~wd) - 1;
+            }
             a.X[v] = FLAG | (int)(pos - bit + 1);
             arcs += a.rowptr[v + 1] - beg;
         }

@@ -76,7 +76,7 @@ def test_algorithm_option_errors_without_device_work(lib):
     assert ex(opts(algorithm=3)) == L.EINVAL
     assert ex(opts(algorithm=-1)) == L.EINVAL
     assert ex(opts(rule=2)) == L.EINVAL
-    assert ex(opts(firstfit=3)) == L.EINVAL
+    assert ex(opts(firstfit=4)) == L.EINVAL
     assert ex(opts(hints=2)) == L.EINVAL
     assert ex(opts(hints=-2)) == L.EINVAL
     assert ex(opts(live_lists=2)) == L.EINVAL

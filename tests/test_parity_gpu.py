@@ -335,7 +335,7 @@ def test_drive_modes_repeat_and_shrink(dev, mode):
         _assert_parity(g, dev, mode=mode)
 
 
-@pytest.mark.parametrize("firstfit", [1, 2])
+@pytest.mark.parametrize("firstfit", [1, 2, 3])
 @pytest.mark.parametrize("mode", [1, 2, 3])
 def test_firstfit_variants_match_oracle(dev, firstfit, mode):
     """FirstFit by rescanning neighbour colours every round (1) and by per-vertex
@@ -348,7 +348,7 @@ def test_firstfit_variants_match_oracle(dev, firstfit, mode):
         _assert_parity(g, dev, mode=mode, firstfit=firstfit)
 
 
-@pytest.mark.parametrize("firstfit", [1, 2])
+@pytest.mark.parametrize("firstfit", [1, 2, 3])
 def test_firstfit_variants_split_heavy(dev, firstfit):
     g = gg.rmat(16, 16, 11)
     _assert_parity(g, dev, firstfit=firstfit, t_split=1024, t_wave=61)
