@@ -21,6 +21,7 @@ struct RoundLds {
         unsigned bm[BMW];             // assign, workgroup bucket: colour window bitmap
     };
     int res[WAVES * 64];              // per-wavefront staging of per-vertex results
+    int idx[WAVES * 64];              // per-wavefront list of the lanes still to be tested
     int wcnt[WAVES];
     int wbase[WAVES];
     int red[WAVES];
@@ -758,12 +759,22 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
                     end_l = a.rowptr[v_l + 1];
                 }
             }
-            const int nsub = (nv + V - 1) / V;
+            // only the vertices the hint did not decide are tested: their lanes are
+            // listed in idx, V of them per sub-step
+            const unsigned long long todo = __ballot(v_l >= 0 && !hinted_l);
+            int* ids = s.idx + wv * 64;
+            res[lane] = 0;
+            if (todo >> lane & 1) ids[__popcll(todo & lanemask_lt())] = lane;
+            __builtin_amdgcn_wave_barrier();
+            const int nt = __popcll(todo);
+            const int nsub = (nt + V - 1) / V;
             for (int sstep = 0; sstep < nsub; ++sstep) {
-                const int j = sstep * V + jsub;
+                const int jj = sstep * V + jsub;
+                const int j = jj < nt ? ids[jj] : lane;      // spare groups repeat their own lane, idle
+                const bool real = jj < nt;
                 const int v = __shfl(v_l, j, 64);
-                const int beg = __shfl(beg_l, j, 64);
-                const int end = __shfl(end_l, j, 64);
+                const int beg = real ? __shfl(beg_l, j, 64) : 0;
+                const int end = real ? __shfl(end_l, j, 64) : 0;
                 const int cv = __shfl(cv_l, j, 64);
                 int w[4];
                 load_quad(a.colidx, a.nnz, beg, end, q, w);
@@ -773,7 +784,7 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
                     if (loses_to(a, w[k], v, cv, end - beg)) found = w[k];
                 if (found >= 0 && a.hint) a.hint[v] = found;    // any conflicting neighbour will do
                 const bool lost = ((__ballot(found >= 0) >> gshift) & gmask) != 0;
-                if (q == 0) res[j] = lost;
+                if (q == 0 && real) res[j] = lost;
             }
             __builtin_amdgcn_wave_barrier();
             const bool lost_l = hinted_l || res[lane] != 0;
