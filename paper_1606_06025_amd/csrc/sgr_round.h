@@ -64,7 +64,7 @@ __host__ __device__ inline int plan_cost(int b) {
     return c[b];
 }
 __host__ __device__ inline int plan_units_per_block(int b) {
-    constexpr int u[NB] = {WG, WG, WG, WG, WAVES, 1, 1};
+    constexpr int u[NB] = {WG, WG, WG, WG, WAVES, WAVES, WAVES};
     return u[b];
 }
 
@@ -900,8 +900,9 @@ __device__ __forceinline__ int quad_end(const int* src, int beg, int q) {
 
 // The whole wavefront runs the conflict test of v (tentative colour cv, row
 // [rb, re)) on its live list of length len (-1: build it from the row).  Updates the
-// list and llen[v]; returns whether v is requeued.  Every lane must call.
-__device__ __forceinline__ bool live_test_wave(const RoundArgs& a, int v, int cv, int rb, int re, int len) {
+// list and its length *lenp; returns whether v is requeued.  Every lane must call.
+__device__ __forceinline__ bool live_test_wave(const RoundArgs& a, int v, int cv, int rb, int re, int len,
+                                               int* lenp) {
     const int lane = __lane_id();
     const bool build = len < 0;
     const int* src = build ? a.colidx : a.live;
@@ -942,7 +943,7 @@ __device__ __forceinline__ bool live_test_wave(const RoundArgs& a, int v, int cv
         for (int i = lane; i < m; i += 64) a.live[rb + K + i] = a.live[rb + len - m + i];
         newlen = len - (p - K);
     }
-    if (lane == 0) a.llen[v] = newlen;
+    if (lane == 0) *lenp = newlen;
     return lost;
 }
 
@@ -1043,7 +1044,8 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
                 const int end = __builtin_amdgcn_readlane(end_l, j);
                 const int cv = __builtin_amdgcn_readlane(cv_l, j);
                 if (a.live) {
-                    const bool lost = live_test_wave(a, v, cv, beg, end, __builtin_amdgcn_readlane(len_l, j));
+                    const bool lost = live_test_wave(a, v, cv, beg, end, __builtin_amdgcn_readlane(len_l, j),
+                                                     &a.llen[v]);
                     if (lane == j) lost_l = lost;
                     continue;
                 }
@@ -1225,6 +1227,73 @@ __device__ __forceinline__ void detect_split(const RoundArgs& a, const int* list
     }
 }
 
+// Split bucket with live lists: the lists of a hub's chunks shrink quickly, so one
+// wavefront (not a workgroup) handles a chunk, four chunks per block at a time.  The
+// merge of the verdicts is that of detect_split, done by lane 0.
+__device__ __forceinline__ void detect_split_wave(const RoundArgs& a, const int* list, int nchunks, int j,
+                                                  int nbk, int* outl, int* cnt_out, int& cmax) {
+    const int* cstart = a.cstart[a.par_in];
+    const int* owner = a.owner[a.par_in];
+    int* cstart_out = a.cstart[a.par_out];
+    int* owner_out = a.owner[a.par_out];
+    const int lane = __lane_id();
+    const int wv = threadIdx.x >> 6;
+    for (int t = j * WAVES + wv; t < nchunks; t += nbk * WAVES) {
+        const int p = owner[t];
+        const int v = list[p];
+        const int k = t - cstart[p];
+        const int rb = a.rowptr[v], re = a.rowptr[v + 1];
+        const int nch = split_chunks(re - rb);
+        const int beg = rb + k * SPLIT_CH, end = min(beg + SPLIT_CH, re);
+        const int cv = tentative(a, v);
+        const int ci = a.llen[v] + k;
+        int h = 0, sk = 0, cl = 0;
+        if (lane == 0) {
+            h = hint_hit(a, v, cv);
+            cl = a.clen[ci];
+            sk = h || ld_agent(&a.hublost[p]) != 0;
+            if (!sk && cl < 0 && a.sorted && a.colidx[beg] >= v) {
+                cl = 0;                        // a sorted chunk above v has no lower entries
+                a.clen[ci] = 0;
+            }
+        }
+        h = __builtin_amdgcn_readfirstlane(h);
+        sk = __builtin_amdgcn_readfirstlane(sk);
+        cl = __builtin_amdgcn_readfirstlane(cl);
+        bool hit = h != 0;
+        if (!sk && cl != 0) hit = live_test_wave(a, v, cv, beg, end, cl, &a.clen[ci]);
+        int decide = 0;
+        if (lane == 0) {
+            unsigned old = 0;
+            if (hit) old = or_agent(reinterpret_cast<unsigned*>(&a.hublost[p]), 1u);
+            wait_on(old);
+            decide = add_agent(&a.hubdone[p], 1) == nch - 1;
+        }
+        decide = __builtin_amdgcn_readfirstlane(decide);
+        if (decide) {
+            // the last chunk to finish settles the hub or requeues it with fresh chunks
+            int qn = -1, cs = 0;
+            if (lane == 0) {
+                const bool lost = ld_agent(&a.hublost[p]) != 0;
+                st_agent(&a.hublost[p], 0);
+                st_agent(&a.hubdone[p], 0);
+                if (lost) {
+                    qn = atomicAdd(cnt_out, 1);
+                    cs = atomicAdd(&a.ctl->ccnt[a.par_out], nch);
+                    outl[qn] = v;
+                    cstart_out[qn] = cs;
+                } else {
+                    settle(a, v, cv, cmax);
+                }
+            }
+            qn = __builtin_amdgcn_readfirstlane(qn);
+            cs = __builtin_amdgcn_readfirstlane(cs);
+            if (qn >= 0)
+                for (int i = lane; i < nch; i += 64) owner_out[cs + i] = qn;
+        }
+    }
+}
+
 // One conflict-test phase for the block `bid` of a grid partitioned by boff.
 __device__ __forceinline__ void detect_phase(const RoundArgs& a, RoundLds& s, int bid, const int* boff, int& cmax) {
     int b, j, nbk;
@@ -1273,8 +1342,15 @@ __device__ __forceinline__ void detect_phase(const RoundArgs& a, RoundLds& s, in
             case 2: detect_tiles<8>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j); break;
             case 3: detect_tiles<16>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j); break;
             case 4: detect_wave(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j); break;
-            case 5: detect_wg(a, list, cnt, s, outl, cnt_out, cmax); break;
-            default: detect_split(a, list, a.ctl->ccnt[a.par_in], j, nbk, s, outl, cnt_out, cmax); break;
+            case 5:
+                // with live lists a wavefront per vertex does (the lists shrink quickly)
+                if (a.live) detect_wave(a, list, lo, hi, s, outl, cnt_out, cmax, nullptr, 0);
+                else detect_wg(a, list, cnt, s, outl, cnt_out, cmax);
+                break;
+            default:
+                if (a.live) detect_split_wave(a, list, a.ctl->ccnt[a.par_in], j, nbk, outl, cnt_out, cmax);
+                else detect_split(a, list, a.ctl->ccnt[a.par_in], j, nbk, s, outl, cnt_out, cmax);
+                break;
         }
     }
 }
