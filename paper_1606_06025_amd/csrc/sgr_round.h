@@ -772,10 +772,13 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
                 const int jj = sstep * V + jsub;
                 const int j = jj < nt ? ids[jj] : lane;      // spare groups repeat their own lane, idle
                 const bool real = jj < nt;
+                // every lane takes part in the cross-lane reads (a read from a lane
+                // that skipped the instruction would return 0); spare groups then idle
                 const int v = __shfl(v_l, j, 64);
-                const int beg = real ? __shfl(beg_l, j, 64) : 0;
-                const int end = real ? __shfl(end_l, j, 64) : 0;
+                int beg = __shfl(beg_l, j, 64);
+                int end = __shfl(end_l, j, 64);
                 const int cv = __shfl(cv_l, j, 64);
+                if (!real) beg = end = 0;
                 int w[4];
                 load_quad(a.colidx, a.nnz, beg, end, q, w);
                 int found = -1;
