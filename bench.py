@@ -59,15 +59,16 @@ def assign_bytes(wsize, arcs, push: bool) -> int:
     return sum(16 * int(w) + 8 * int(a) for w, a in zip(wsize[1:], arcs[1:]))
 
 
-def detect_bytes(wsize, arcs_cr, pushed_arcs: int, push: bool) -> int:
+def detect_bytes(wsize, arcs_cr, pushed_arcs: int, push: bool, byte_flags: bool = True) -> int:
     """Algorithmic bytes of all conflict-test launches (rounds 2..R): per worklist
     vertex 20 B (id, rowptr pair, own colour, colour/output write) + 8 B per examined
-    lower arc (colidx + colour) + 4 B per requeued vertex; in the push variant also
-    20 B per arc pushed by a winner (colidx, the neighbour's rowptr pair, the bitmap
-    word read and written)."""
+    lower arc (colidx + colour) + 4 B per requeued vertex; in the push variant also,
+    per arc pushed by a winner, the colidx entry and the neighbour's rowptr pair (12 B)
+    plus the flag: a 1-byte store (byte flags) or a 4-byte word read and written (bit
+    flags, 8 B)."""
     w = [int(x) for x in wsize] + [0]
     b = sum(20 * w[r] + 8 * int(arcs_cr[r]) + 4 * w[r + 1] for r in range(1, len(wsize)))
-    return b + (20 * pushed_arcs if push else 0)
+    return b + ((13 if byte_flags else 20) * pushed_arcs if push else 0)
 
 
 def kernel_source_digest() -> str:
@@ -576,6 +577,7 @@ def main() -> int:
             na += s2.n_assign
             nd += s2.n_detect
         push = args.firstfit != 1
+        byte_flags = args.firstfit in (0, 3)
         ows, ocr, ff_colors = oracle_stats(g, args.workload)
         if [int(x) for x in ows] != st.wsize:
             raise SystemExit("worklist sizes differ from the oracle's")
@@ -583,7 +585,7 @@ def main() -> int:
         # round-1 winners' rows are pushed by the round-1 kernel)
         pushed = int(st.arcs[1]) if len(st.arcs) > 1 else 0
         kb = {"k_assign": (assign_bytes(st.wsize, st.arcs, push), tot_a, na),
-              "k_detect": (detect_bytes(st.wsize, ocr, pushed, push), tot_d, nd)}
+              "k_detect": (detect_bytes(st.wsize, ocr, pushed, push, byte_flags), tot_d, nd)}
         dom = max(kb, key=lambda k: kb[k][1])
         byts, tms, nl = kb[dom]
         launches_per_step = nl / args.steps

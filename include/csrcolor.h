@@ -101,12 +101,13 @@ typedef struct {
     int32_t validate;       /* 1: also check symmetry (sorted rows only; costs one search per arc) */
     int32_t t_wave;         /* max degree handled by one wavefront per vertex (61..1024; default 1024) */
     int32_t t_split;        /* rows longer than this are split over several workgroups (>= 1024; default 2048) */
-    int32_t blocks_per_cu;  /* workgroups per compute unit for the round kernels (default 8) */
+    int32_t blocks_per_cu;  /* workgroups per compute unit for the round kernels (default 4) */
     int32_t sync_every;     /* LOOP/GRAPH: rounds enqueued between worklist-size read-backs (default 8) */
     int32_t lane_assign;    /* bit b (b < 4): low-degree bucket b runs FirstFit one lane per vertex;
                                0 = default; -1 = none (all use 2/4/8/16 lanes per vertex) */
-    int32_t lane_detect;    /* the same for the conflict test */
-    int32_t firstfit;       /* 0: default (push, bit flags); 1: rescan: every FirstFit gathers all neighbour
+    int32_t lane_detect;    /* the same for the conflict test; by default none: L lanes per vertex, over
+                               only the vertices their conflict hint did not decide */
+    int32_t firstfit;       /* 0: default (push, byte flags); 1: rescan: every FirstFit gathers all neighbour
                                colours (as printed in the paper); 2: push: a vertex that settles marks its
                                colour in per-neighbour flags (bits, set by atomic OR) and FirstFit reads its
                                own flags; 3: push with byte flags (plain stores).  Same colouring */

@@ -294,12 +294,12 @@ struct Options {
     int mode = CSRCOLOR_MODE_LOOP;
     int validate = 0;
     int twave = 1024;
-    int blocks_per_cu = 8;
+    int blocks_per_cu = 4;
     int sync_every = 8;
     int tsplit = 2048;
     int lane_assign = 0;      // tile buckets run with 2/4/8/16 lanes per vertex
-    int lane_detect = 0xF;    // lane-per-vertex conflict test (early exit) in every tile bucket
-    int pushff = 1;           // FirstFit: 0 rescan, 1 push with bit flags, 2 push with byte flags
+    int lane_detect = 0;      // tiled conflict test (L lanes per untested vertex) in every tile bucket
+    int pushff = 2;           // FirstFit: 0 rescan, 1 push with bit flags, 2 push with byte flags
     int hints = 1;            // conflict hints (id rule)
     int live = 1;             // live lists for degree > 61 (id rule)
     int ordered = 0;          // order-preserving worklist compaction (measured slower on the stencil)

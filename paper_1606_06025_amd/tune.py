@@ -24,12 +24,12 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "csrcolor", "tun
 
 # knob -> values tried (0 = library default)
 KNOBS: List[Tuple[str, Sequence[int]]] = [
-    ("firstfit", (2, 1)),
+    ("firstfit", (3, 2, 1)),
     ("mode", (1, 3)),
     ("t_wave", (1024, 256, 128)),
     ("t_split", (2048, 8192, 1024)),
-    ("blocks_per_cu", (8, 4, 16)),
-    ("lane_detect", (15, -1)),
+    ("blocks_per_cu", (4, 2, 6, 8)),
+    ("lane_detect", (-1, 15)),
     ("sync_every", (8, 16, 32)),
 ]
 

@@ -22,7 +22,8 @@ def test_bytes_models():
     assert bench.assign_bytes([10, 4, 2], [100, 40, 20], push=False) == 16 * 6 + 8 * 60
     # detect: 20 B/vertex + 8 B/examined arc + 4 B per requeued vertex (+ 20 B per pushed arc)
     assert bench.detect_bytes([10, 4, 2], [0, 7, 3], 50, push=False) == 20 * 4 + 56 + 8 + 20 * 2 + 24 + 0
-    assert bench.detect_bytes([10, 4, 2], [0, 7, 3], 50, push=True) == 20 * 4 + 56 + 8 + 20 * 2 + 24 + 1000
+    assert bench.detect_bytes([10, 4, 2], [0, 7, 3], 50, push=True, byte_flags=False) == 20 * 4 + 56 + 8 + 20 * 2 + 24 + 1000
+    assert bench.detect_bytes([10, 4, 2], [0, 7, 3], 50, push=True) == 20 * 4 + 56 + 8 + 20 * 2 + 24 + 650
 
 
 def test_digest_and_traffic_summary(tmp_path, monkeypatch, capsys):
