@@ -170,7 +170,8 @@ def traffic_summary(workload: str, fetch_dir: str, write_dir: str, cfetch_dir: s
         name = name or next((k for k in ks if "neg" in k.lower() and counter in ks[k]), None)
         if name is None:
             raise SystemExit(f"no copy kernel with {counter} in {d}")
-        return ks[name][counter]["per_dispatch"] * 1024.0 / probe, name
+        # the probe's copies are its largest dispatches (the runtime may add small ones)
+        return ks[name][counter]["max_dispatch"] * 1024.0 / probe, name
 
     ff, fname = factor(cfetch_dir, "FETCH_SIZE")
     wf, wname = factor(cwrite_dir, "WRITE_SIZE")
@@ -208,11 +209,11 @@ def digest_pmc(path: str) -> int:
                 k = row["Kernel_Name"].split("(")[0].split("<")[0].strip()
                 k = k.replace("void ", "").split("::")[-1]
                 c = row["Counter_Name"]
-                e = tab.setdefault(k, {}).setdefault(c, {"sum": 0.0, "dispatches": set()})
-                e["sum"] += float(row["Counter_Value"])
-                e["dispatches"].add(row.get("Dispatch_Id") or row.get("Correlation_Id"))
-    out = {k: {c: {"sum": e["sum"], "dispatches": len(e["dispatches"]),
-                   "per_dispatch": e["sum"] / max(len(e["dispatches"]), 1)} for c, e in v.items()}
+                e = tab.setdefault(k, {}).setdefault(c, {})
+                d = row.get("Dispatch_Id") or row.get("Correlation_Id")
+                e[d] = e.get(d, 0.0) + float(row["Counter_Value"])
+    out = {k: {c: {"sum": sum(e.values()), "dispatches": len(e), "per_dispatch": sum(e.values()) / max(len(e), 1),
+                   "max_dispatch": max(e.values()) if e else 0.0} for c, e in v.items()}
            for k, v in tab.items()}
     print(json.dumps({"files": len(files), "kernels": out}, indent=1, sort_keys=True), flush=True)
     return 0 if files else 1

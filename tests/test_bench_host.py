@@ -35,7 +35,8 @@ def test_digest_and_traffic_summary(tmp_path, monkeypatch, capsys):
                         ("void csrcolor::k_detect(csrcolor::RoundArgs)", "WRITE_SIZE", 50.0),
                         ("csrcolor::k_assign(csrcolor::RoundArgs)", "WRITE_SIZE", 4.0)])
     # copy probe of 1 MiB reading 2048 KiB and writing 1024 KiB per dispatch -> factors 2 and 1
-    _write_counters(cf, [("void at::native::copy_kernel(int)", "FETCH_SIZE", 2048.0)])
+    _write_counters(cf, [("void at::native::copy_kernel(int)", "FETCH_SIZE", 2048.0),
+                         ("void at::native::copy_kernel(int)", "FETCH_SIZE", 3.0)])     # a small extra dispatch
     _write_counters(cw, [("void at::native::copy_kernel(int)", "WRITE_SIZE", 1024.0)])
     assert bench.digest_pmc(f) == 0
     dig = json.loads(capsys.readouterr().out)
