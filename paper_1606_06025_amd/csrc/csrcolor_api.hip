@@ -34,6 +34,7 @@ struct Workspace {
     int* wl[2] = {nullptr, nullptr};
     int* hint = nullptr;         // conflict hints: a neighbour that beat the vertex
     int* llen = nullptr;         // live-list lengths (or a split row's chunk-slot base)
+    unsigned char* dirty = nullptr;   // push FirstFit: flags changed since the last FirstFit
     int* live = nullptr;         // live lists, same offsets as colidx
     size_t live_cap = 0;         // ints
     unsigned long long* lb = nullptr;   // look-back status words of ordered compaction
@@ -181,7 +182,9 @@ void free_vertex_arrays(Workspace* w) {
     if (w->wl[1]) (void)hipFree(w->wl[1]);
     if (w->hint) (void)hipFree(w->hint);
     if (w->llen) (void)hipFree(w->llen);
+    if (w->dirty) (void)hipFree(w->dirty);
     w->X = w->wl[0] = w->wl[1] = w->hint = w->llen = nullptr;
+    w->dirty = nullptr;
     w->cap_n = 0;
 }
 
@@ -216,7 +219,8 @@ int ensure_capacity(Workspace* w, size_t n, int st_cap) {
             hipMalloc(&w->wl[0], want * sizeof(int)) != hipSuccess ||
             hipMalloc(&w->wl[1], want * sizeof(int)) != hipSuccess ||
             hipMalloc(&w->hint, want * sizeof(int)) != hipSuccess ||
-            hipMalloc(&w->llen, want * sizeof(int)) != hipSuccess) {
+            hipMalloc(&w->llen, want * sizeof(int)) != hipSuccess ||
+            hipMalloc(&w->dirty, want + 16) != hipSuccess) {
             free_vertex_arrays(w);
             return CSRCOLOR_ENOMEM;
         }
@@ -607,6 +611,11 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
             k_fill<<<(int)std::min<size_t>((words + WG - 1) / WG, (size_t)cus * 8), WG, 0, st>>>(
                 reinterpret_cast<int*>(F), (int)words, 0);
         });
+        const int dwords = n / 4 + 1;
+        T.run(0, [&] {
+            k_fill<<<std::min((dwords + WG - 1) / WG, cus * 8), WG, 0, st>>>(reinterpret_cast<int*>(w->dirty),
+                                                                                dwords, 0);
+        });
     }
 
     // conflict hints serve the id rule (the degree rule would need the neighbour's degree too)
@@ -630,7 +639,8 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
         k_round1<<<r1blocks, WG, 0, st>>>(n, J.rowptr, J.colidx, w->X, J.colors_out, w->wl[1], w->ctl,
                                           J.sorted, twave, J.opt.tsplit, seg, cstart1, owner1, F,
                                           w->ctl_h->nnz, J.opt.rule, J.opt.algo == CSRCOLOR_ALGO_JP, hint,
-                                          use_live ? w->llen : nullptr, clen, lb, J.opt.pushff == 2);
+                                          use_live ? w->llen : nullptr, clen, lb, J.opt.pushff == 2,
+                                          F ? w->dirty : nullptr);
     });
     HIP_TRY(hipGetLastError());
 
@@ -657,6 +667,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     a.hublost = a.hubdone + nhub;
     a.pushff = J.opt.pushff;
     a.F = F;
+    a.dirty = F ? w->dirty : nullptr;
     a.rule = J.opt.rule;
     a.seed = J.opt.seed;
     a.hint = hint;

@@ -68,8 +68,10 @@ __device__ __forceinline__ bool conflict(int rule, const int* __restrict__ rowpt
 // atomic OR, several neighbours may share a word) or, with `bytes`, one byte (a plain
 // store: concurrent writers of one byte all write 1, and distinct bytes of a line are
 // merged by the caches).
+// With `dirty`, u is also marked for its next FirstFit (a vertex whose flags did not
+// change keeps its tentative colour, and FirstFit skips it).
 __device__ __forceinline__ void push_colour(unsigned* F, const int* __restrict__ rowptr, int u, int c,
-                                            bool bytes) {
+                                            bool bytes, unsigned char* dirty) {
     const int ub = rowptr[u];
     const int du = rowptr[u + 1] - ub;
     if (c - 1 <= du) {
@@ -79,6 +81,7 @@ __device__ __forceinline__ void push_colour(unsigned* F, const int* __restrict__
         } else {
             atomicOr(&F[pos >> 5], 1u << (pos & 31));
         }
+        if (dirty) dirty[u] = 1;
     }
 }
 
@@ -153,6 +156,8 @@ struct RoundArgs {
     // bit c-1 set <=> a neighbour settled with colour c in an earlier round
     int pushff;         // 0: rescan FirstFit; 1: push, bit flags; 2: push, byte flags
     unsigned* F;
+    // push mode: dirty[v] = 1 when a flag of v was set since its last FirstFit
+    unsigned char* dirty;
     // conflict rule: 0 = the higher id is requeued; 1 = the smaller degree (row
     // length) is requeued, the higher id on equal degree (heuristic of Sec. 3.2)
     int rule;

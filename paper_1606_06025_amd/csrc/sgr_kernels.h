@@ -114,7 +114,7 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
                                                int* wl1, Ctl* ctl, int sorted, int twave, int tsplit,
                                                Seg seg, int* cstart1, int* owner1, unsigned* F, int nnz,
                                                int rule, int jp, int* hint, int* llen, int* clen,
-                                               unsigned long long* lb1, int fbytes) {
+                                               unsigned long long* lb1, int fbytes, unsigned char* dirty) {
     constexpr int ITER = 4;
     __shared__ int buf[WAVES][NB][ITER * 64];
     __shared__ int wcnt[WAVES][NB];
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
             }
         }
         // round-1 winners push colour 1, the whole wavefront over their concatenated rows
-        if (F != nullptr) push_rows_wave(F, rowptr, colidx, nnz, winpush, (int)vv, 1, wbeg, wend, fbytes != 0);
+        if (F != nullptr) push_rows_wave(F, rowptr, colidx, nnz, winpush, (int)vv, 1, wbeg, wend, fbytes != 0, dirty);
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const unsigned long long m = __ballot(bkt == b);

@@ -141,19 +141,19 @@ __device__ __forceinline__ void wave_slice(int lo, int hi, int& wlo, int& whi) {
 // `nthr` threads (thread index t) push colour c of v over row [beg, end) together.
 __device__ __forceinline__ void push_row_coop(unsigned* F, const int* __restrict__ rowptr,
                                               const int* __restrict__ colidx, int nnz, int v, int c, int beg,
-                                              int end, int t, int nthr, bool bytes) {
+                                              int end, int t, int nthr, bool bytes, unsigned char* dirty) {
     const int nq = ((end - beg) + 3 + 3) / 4 + 1;
     for (int q0 = 0; q0 < nq; q0 += nthr) {
         int w[4];
         load_quad(colidx, nnz, beg, end, q0 + t, w);
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (w[k] >= 0 && w[k] != v) push_colour(F, rowptr, w[k], c, bytes);
+            if (w[k] >= 0 && w[k] != v) push_colour(F, rowptr, w[k], c, bytes, dirty);
     }
 }
 __device__ __forceinline__ void push_row_coop(const RoundArgs& a, int v, int c, int beg, int end, int t,
                                               int nthr) {
-    push_row_coop(a.F, a.rowptr, a.colidx, a.nnz, v, c, beg, end, t, nthr, a.pushff == 2);
+    push_row_coop(a.F, a.rowptr, a.colidx, a.nnz, v, c, beg, end, t, nthr, a.pushff == 2, a.dirty);
 }
 
 // The whole wavefront pushes the colours of its winners: lane l contributes the row
@@ -163,7 +163,7 @@ __device__ __forceinline__ void push_row_coop(const RoundArgs& a, int v, int c, 
 // or a few short winner rows does not serialise on one lane.  Every lane must call.
 __device__ __forceinline__ void push_rows_wave(unsigned* F, const int* __restrict__ rowptr,
                                                const int* __restrict__ colidx, int nnz, bool win, int v, int c,
-                                               int beg, int end, bool bytes) {
+                                               int beg, int end, bool bytes, unsigned char* dirty) {
     const int lane = __lane_id();
     const int mis = (int)((reinterpret_cast<uintptr_t>(colidx) >> 2) & 3);
     const int nq = win && end > beg ? (((end - 1 + mis) >> 2) - ((beg + mis) >> 2) + 1) : 0;
@@ -192,12 +192,12 @@ __device__ __forceinline__ void push_rows_wave(unsigned* F, const int* __restric
             load_quad(colidx, nnz, bj, ej, q, w);
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                if (w[k] >= 0 && w[k] != vj) push_colour(F, rowptr, w[k], cj, bytes);
+                if (w[k] >= 0 && w[k] != vj) push_colour(F, rowptr, w[k], cj, bytes, dirty);
         }
     }
 }
 __device__ __forceinline__ void push_rows_wave(const RoundArgs& a, bool win, int v, int c, int beg, int end) {
-    push_rows_wave(a.F, a.rowptr, a.colidx, a.nnz, win, v, c, beg, end, a.pushff == 2);
+    push_rows_wave(a.F, a.rowptr, a.colidx, a.nnz, win, v, c, beg, end, a.pushff == 2, a.dirty);
 }
 
 // Push-mode FirstFit for any bucket: one lane per vertex finds the first clear bit
@@ -211,6 +211,14 @@ __device__ __forceinline__ void assign_push(const RoundArgs& a, const int* list,
         const int nv = min(64, whi - t0);
         if (lane < nv) {
             const int v = list[t0 + lane];
+            if (a.dirty) {
+                // no flag of v changed since its last FirstFit: its tentative colour stands
+                if (!a.dirty[v]) {
+                    if (a.st_arcs) arcs += a.rowptr[v + 1] - a.rowptr[v];
+                    continue;
+                }
+                a.dirty[v] = 0;
+            }
             const int beg = a.rowptr[v];
             const long long bit = (long long)beg + v;
             long long pos;
