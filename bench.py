@@ -390,6 +390,12 @@ def bench_serve(args, dev) -> int:
     sat_arcs = total_arcs / wall
     sat_qps = len(pairs) / wall
     log(f"saturation: {wall * 1e3:.1f} ms, {sat_arcs / 1e9:.3f} G arcs/s, {sat_qps:.1f} req/s")
+    # where a request's time goes: admission + upload, waiting for a slot, its batch
+    phases = {"admit_upload_ms": float(np.mean([r.admitted - r.arrival for r in rr]) * 1e3),
+              "wait_slot_ms": float(np.mean([r.started - r.admitted for r in rr]) * 1e3),
+              "batch_ms": float(np.mean([r.done_time - r.started for r in rr]) * 1e3),
+              "mean_batch_size": float(np.mean([r.batch_size for r in rr]))}
+    log(f"saturation phases (means): {phases}")
     unit_arrivals = np.array([r.arrival_s for r in reqs])   # Poisson at 1 req/s
     loads = {}
     for frac in (0.5, 0.9):
@@ -427,7 +433,7 @@ def bench_serve(args, dev) -> int:
         "dtype": "int32", "data": "synthetic",
         "config": {"workload": f"serve_{len(pairs)}_requests", "requests": len(pairs), "total_arcs": total_arcs,
                    "slots": args.slots, "hbm_budget_gb": args.hbm_budget_gb, "peak_admitted_bytes": peak,
-                   "saturation_qps": sat_qps, "loads": loads,
+                   "saturation_qps": sat_qps, "saturation_phases": phases, "loads": loads,
                    "one_graph_per_launch_with_transfers_arcs_per_s": total_arcs / single_path,
                    "one_graph_per_launch_resident_arcs_per_s": total_arcs / single,
                    "served_vs_one_graph_per_launch": (total_arcs / wall) / (total_arcs / single_path)},

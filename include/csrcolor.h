@@ -101,7 +101,7 @@ typedef struct {
     int32_t validate;       /* 1: also check symmetry (sorted rows only; costs one search per arc) */
     int32_t t_wave;         /* max degree handled by one wavefront per vertex (61..1024; default 1024) */
     int32_t t_split;        /* rows longer than this are split over several workgroups (>= 1024; default 2048) */
-    int32_t blocks_per_cu;  /* workgroups per compute unit for the round kernels (default 4) */
+    int32_t blocks_per_cu;  /* workgroups per compute unit for the round kernels (default 6) */
     int32_t sync_every;     /* LOOP/GRAPH: rounds enqueued between worklist-size read-backs (default 8) */
     int32_t lane_assign;    /* bit b (b < 4): low-degree bucket b runs FirstFit one lane per vertex;
                                0 = default; -1 = none (all use 2/4/8/16 lanes per vertex) */

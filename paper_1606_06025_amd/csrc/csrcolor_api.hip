@@ -298,7 +298,7 @@ struct Options {
     int mode = CSRCOLOR_MODE_LOOP;
     int validate = 0;
     int twave = 1024;
-    int blocks_per_cu = 4;
+    int blocks_per_cu = 6;
     int sync_every = 8;
     int tsplit = 2048;
     int lane_assign = 0;      // tile buckets run with 2/4/8/16 lanes per vertex

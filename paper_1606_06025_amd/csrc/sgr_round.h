@@ -21,7 +21,8 @@ struct RoundLds {
         unsigned bm[BMW];             // assign, workgroup bucket: colour window bitmap
     };
     int res[WAVES * 64];              // per-wavefront staging of per-vertex results
-    int idx[WAVES * 64];              // per-wavefront list of the lanes still to be tested
+    int idx[WAVES * 128];             // detect tiles: per-wavefront list of the entries still to be tested
+    int res2[WAVES * 128];            // detect tiles: their verdicts
     int wcnt[WAVES];
     int wbase[WAVES];
     int red[WAVES];
@@ -204,43 +205,63 @@ __device__ __forceinline__ void push_rows_wave(const RoundArgs& a, bool win, int
 // of the vertex's bitmap (bits below its start count as set); the scan stops at the
 // first clear bit, which exists within deg(v)+1 bits.
 __device__ __forceinline__ void assign_push(const RoundArgs& a, const int* list, int lo, int hi, long long& arcs) {
+    // four worklist entries per lane at a time, each step's loads issued together so
+    // their latencies overlap
+    constexpr int U = 4;
     const int lane = __lane_id();
+    const bool bytes = a.pushff == 2;
     int wlo, whi;
     wave_slice(lo, hi, wlo, whi);
-    for (int t0 = wlo; t0 < whi; t0 += 64) {
-        const int nv = min(64, whi - t0);
-        if (lane < nv) {
-            const int v = list[t0 + lane];
-            if (a.dirty) {
-                // no flag of v changed since its last FirstFit: its tentative colour stands
-                if (!a.dirty[v]) {
-                    if (a.st_arcs) arcs += a.rowptr[v + 1] - a.rowptr[v];
-                    continue;
-                }
-                a.dirty[v] = 0;
-            }
-            const int beg = a.rowptr[v];
-            const long long bit = (long long)beg + v;
+    for (int t0 = wlo; t0 < whi; t0 += 64 * U) {
+        int v[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            const int t = t0 + 64 * i + lane;
+            v[i] = t < whi ? list[t] : -1;
+        }
+        // a vertex none of whose flags changed since its last FirstFit keeps its colour
+        bool need[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) need[i] = v[i] >= 0 && (!a.dirty || a.dirty[v[i]] != 0);
+        int beg[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) beg[i] = need[i] ? a.rowptr[v[i]] : 0;
+        long long wi[U];
+        unsigned wd[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            const long long bit = (long long)beg[i] + v[i];
+            wi[i] = bytes ? bit >> 2 : bit >> 5;
+            wd[i] = need[i] ? a.F[wi[i]] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            if (!need[i]) continue;
+            const long long bit = (long long)beg[i] + v[i];
             long long pos;
-            if (a.pushff == 2) {
-                // byte flags: the first zero byte at or after `bit`, four bytes per load
-                // (bytes before `bit` count as set)
-                long long wi = bit >> 2;
-                unsigned wd = a.F[wi] | ((1u << (8 * (bit & 3))) - 1u);
-                unsigned z = (wd - 0x01010101u) & ~wd & 0x80808080u;
+            if (bytes) {
+                // byte flags: the first zero byte at or after `bit` (bytes before it count as set)
+                unsigned w = wd[i] | ((1u << (8 * (bit & 3))) - 1u);
+                unsigned z = (w - 0x01010101u) & ~w & 0x80808080u;
+                long long k = wi[i];
                 while (z == 0) {
-                    wd = a.F[++wi];
-                    z = (wd - 0x01010101u) & ~wd & 0x80808080u;
+                    w = a.F[++k];
+                    z = (w - 0x01010101u) & ~w & 0x80808080u;
                 }
-                pos = wi * 4 + (__ffs(z) - 1) / 8;
+                pos = k * 4 + (__ffs(z) - 1) / 8;
             } else {
-                long long wi = bit >> 5;
-                unsigned wd = a.F[wi] | ((1u << (bit & 31)) - 1u);
-                while (wd == 0xffffffffu) wd = a.F[++wi];
-                pos = wi * 32 + __ffs(~wd) - 1;
+                unsigned w = wd[i] | ((1u << (bit & 31)) - 1u);
+                long long k = wi[i];
+                while (w == 0xffffffffu) w = a.F[++k];
+                pos = k * 32 + __ffs(~w) - 1;
             }
-            a.X[v] = FLAG | (int)(pos - bit + 1);
-            arcs += a.rowptr[v + 1] - beg;
+            if (a.dirty) a.dirty[v[i]] = 0;
+            a.X[v[i]] = FLAG | (int)(pos - bit + 1);
+        }
+        if (a.st_arcs) {
+#pragma unroll
+            for (int i = 0; i < U; ++i)
+                if (v[i] >= 0) arcs += a.rowptr[v[i] + 1] - a.rowptr[v[i]];
         }
     }
 }
@@ -748,44 +769,71 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
     const unsigned long long gmask = (L == 64) ? ~0ull : ((1ull << L) - 1ull);
     const int gshift = lane & ~(L - 1);
     int* mybuf = s.lbuf + wv * WAVE_CAP;
-    int* res = s.res + wv * 64;
     for (int s0 = lo; s0 < hi; s0 += SUB) {
         const int s1 = min(s0 + SUB, hi);
         int wlo, whi;
         wave_slice(s0, s1, wlo, whi);      // <= WAVE_CAP entries per wavefront
         int wc = 0;
-        for (int t0 = wlo; t0 < whi; t0 += 64) {
-            const int nv = min(64, whi - t0);
-            const int v_l = lane < nv ? list[t0 + lane] : -1;
-            int beg_l = 0, end_l = 0, cv_l = 0;
-            bool hinted_l = false;
-            if (v_l >= 0) {
-                cv_l = tentative(a, v_l);
-                hinted_l = hint_hit(a, v_l, cv_l);
-                if (!hinted_l) {
-                    beg_l = a.rowptr[v_l];
-                    end_l = a.rowptr[v_l + 1];
+        // two 64-entry batches per step (entry u * 64 + lane), each stage's loads for
+        // both issued together so their latencies overlap
+        int* ids = s.idx + wv * 128;
+        int* res2 = s.res2 + wv * 128;
+        for (int t0 = wlo; t0 < whi; t0 += 128) {
+            int v_l[2], beg_l[2] = {0, 0}, end_l[2] = {0, 0}, cv_l[2] = {0, 0}, h_l[2] = {-1, -1};
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int t = t0 + 64 * u + lane;
+                v_l[u] = t < whi ? list[t] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (v_l[u] >= 0) {
+                    cv_l[u] = tentative(a, v_l[u]);
+                    if (a.hint) h_l[u] = a.hint[v_l[u]];
                 }
             }
-            // only the vertices the hint did not decide are tested: their lanes are
-            // listed in idx, V of them per sub-step
-            const unsigned long long todo = __ballot(v_l >= 0 && !hinted_l);
-            int* ids = s.idx + wv * 64;
-            res[lane] = 0;
-            if (todo >> lane & 1) ids[__popcll(todo & lanemask_lt())] = lane;
+            bool hinted_l[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                // the remembered neighbour still requeues v (see hint_hit)
+                const int h = h_l[u];
+                hinted_l[u] = h >= 0 && h < v_l[u] && (a.X[h] & CMASK) == cv_l[u];
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (v_l[u] >= 0 && !hinted_l[u]) {
+                    beg_l[u] = a.rowptr[v_l[u]];
+                    end_l[u] = a.rowptr[v_l[u] + 1];
+                }
+            }
+            // only the vertices the hint did not decide are tested: their entries are
+            // listed in ids, V of them per sub-step
+            const unsigned long long todo0 = __ballot(v_l[0] >= 0 && !hinted_l[0]);
+            const unsigned long long todo1 = __ballot(v_l[1] >= 0 && !hinted_l[1]);
+            const int nt0 = __popcll(todo0);
+            const int nt = nt0 + __popcll(todo1);
+            res2[lane] = 0;
+            res2[64 + lane] = 0;
+            if (todo0 >> lane & 1) ids[__popcll(todo0 & lanemask_lt())] = lane;
+            if (todo1 >> lane & 1) ids[nt0 + __popcll(todo1 & lanemask_lt())] = 64 + lane;
             __builtin_amdgcn_wave_barrier();
-            const int nt = __popcll(todo);
             const int nsub = (nt + V - 1) / V;
             for (int sstep = 0; sstep < nsub; ++sstep) {
                 const int jj = sstep * V + jsub;
-                const int j = jj < nt ? ids[jj] : lane;      // spare groups repeat their own lane, idle
                 const bool real = jj < nt;
-                // every lane takes part in the cross-lane reads (a read from a lane
-                // that skipped the instruction would return 0); spare groups then idle
-                const int v = __shfl(v_l, j, 64);
-                int beg = __shfl(beg_l, j, 64);
-                int end = __shfl(end_l, j, 64);
-                const int cv = __shfl(cv_l, j, 64);
+                const int e = real ? ids[jj] : lane;      // spare groups repeat their own lane, idle
+                const int l = e & 63;
+                const bool hi1 = e >= 64;
+                // every lane takes part in the cross-lane reads (a read from a lane that
+                // skipped the instruction would return 0); spare groups then idle
+                const int va = __shfl(v_l[0], l, 64), vb = __shfl(v_l[1], l, 64);
+                const int ba = __shfl(beg_l[0], l, 64), bb = __shfl(beg_l[1], l, 64);
+                const int ea = __shfl(end_l[0], l, 64), eb = __shfl(end_l[1], l, 64);
+                const int ca = __shfl(cv_l[0], l, 64), cb = __shfl(cv_l[1], l, 64);
+                const int v = hi1 ? vb : va;
+                const int cv = hi1 ? cb : ca;
+                int beg = hi1 ? bb : ba;
+                int end = hi1 ? eb : ea;
                 if (!real) beg = end = 0;
                 int w[4];
                 load_quad(a.colidx, a.nnz, beg, end, q, w);
@@ -795,14 +843,19 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
                     if (loses_to(a, w[k], v, cv, end - beg)) found = w[k];
                 if (found >= 0 && a.hint) a.hint[v] = found;    // any conflicting neighbour will do
                 const bool lost = ((__ballot(found >= 0) >> gshift) & gmask) != 0;
-                if (q == 0 && real) res[j] = lost;
+                if (q == 0 && real) res2[e] = lost;
             }
             __builtin_amdgcn_wave_barrier();
-            const bool lost_l = hinted_l || res[lane] != 0;
+            bool lost_l[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) lost_l[u] = hinted_l[u] || res2[64 * u + lane] != 0;
             __builtin_amdgcn_wave_barrier();
-            if (v_l >= 0 && !lost_l) settle(a, v_l, cv_l, cmax);
-            if (a.pushff) push_rows_wave(a, v_l >= 0 && !lost_l, v_l, cv_l, beg_l, end_l);
-            push_losers(v_l, lost_l, mybuf, wc);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (v_l[u] >= 0 && !lost_l[u]) settle(a, v_l[u], cv_l[u], cmax);
+                if (a.pushff) push_rows_wave(a, v_l[u] >= 0 && !lost_l[u], v_l[u], cv_l[u], beg_l[u], end_l[u]);
+                push_losers(v_l[u], lost_l[u], mybuf, wc);
+            }
         }
         flush_losers(s, wc, outl, cnt_out, ust, unit, &a.ctl->err);
     }
@@ -1380,7 +1433,7 @@ __global__ void k_jp_prep(Ctl* ctl, int par_out, unsigned long long* lbs, int nl
         for (int i = k; i < nlbs; i += blockDim.x) lbs[i] = 0;
 }
 
-__global__ __launch_bounds__(WG) void k_detect(RoundArgs a) {
+__global__ __launch_bounds__(WG, 6) void k_detect(RoundArgs a) {
     __shared__ RoundLds s;
     __shared__ int boff[NB + 1];
     if (threadIdx.x == 0) {

@@ -28,7 +28,7 @@ KNOBS: List[Tuple[str, Sequence[int]]] = [
     ("mode", (1, 3)),
     ("t_wave", (1024, 256, 128)),
     ("t_split", (2048, 8192, 1024)),
-    ("blocks_per_cu", (4, 2, 6, 8)),
+    ("blocks_per_cu", (6, 4, 8)),
     ("lane_detect", (-1, 15)),
     ("sync_every", (8, 16, 32)),
 ]
