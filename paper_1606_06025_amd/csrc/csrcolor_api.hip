@@ -585,7 +585,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     const bool use_live = J.opt.live && J.opt.rule == 0 && J.opt.algo == CSRCOLOR_ALGO_SGR &&
                           hist[NTILE] + hist[NTILE + 1] + hist[BSPLIT] > 0;
     const size_t split_ints = 2 * (size_t)nhub + 2 * (size_t)nchunk + (size_t)nhub * (HW + 2) +
-                              (use_live ? (size_t)nchunk : 0);
+                              (use_live ? (size_t)nchunk : 0) + (size_t)nhub;
     if ((rc = ensure_split(w, split_ints))) return rc;
     int* cstart0 = w->split;
     int* cstart1 = cstart0 + nhub;
@@ -597,6 +597,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
         k_fill<<<std::min((cnt + WG - 1) / WG, cus * 4), WG, 0, st>>>(hubflags, cnt, 0);
     }
     int* clen = use_live ? hubflags + (size_t)nhub * (HW + 2) : nullptr;   // per-chunk live lengths
+    int* settled = hubflags + (size_t)nhub * (HW + 2) + (use_live ? (size_t)nchunk : 0);
     if (use_live && (rc = ensure_live(w, std::max<size_t>((size_t)w->ctl_h->nnz, 1)))) return rc;
 
     // push mode: deg(v)+1 bits per vertex, zeroed
@@ -665,6 +666,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     a.hubbm = reinterpret_cast<unsigned*>(hubflags);
     a.hubdone = hubflags + (size_t)nhub * HW;
     a.hublost = a.hubdone + nhub;
+    a.settled = (J.opt.pushff && nhub > 0) ? settled : nullptr;
     a.pushff = J.opt.pushff;
     a.F = F;
     a.dirty = F ? w->dirty : nullptr;

@@ -639,6 +639,7 @@ __device__ __forceinline__ void assign_phase(const RoundArgs& a, RoundLds& s, in
             st_agent(&a.ctl->tk[k], 0);
         }
         a.ctl->ccnt[a.par_out] = 0;
+        a.ctl->nsettled = 0;
     }
     // the conflict test of this round uses one look-back status word per block
     if (a.lbs && threadIdx.x == 0) st_agent(&a.lbs[bid], 0ull);
@@ -1281,6 +1282,7 @@ __device__ __forceinline__ void detect_split(const RoundArgs& a, const int* list
                     s.sh[3] = cs;
                 } else {
                     settle(a, v, cv, cmax);
+                    if (a.settled) a.settled[atomicAdd(&a.ctl->nsettled, 1)] = p;
                 }
             }
             __syncthreads();
@@ -1348,6 +1350,7 @@ __device__ __forceinline__ void detect_split_wave(const RoundArgs& a, const int*
                     cstart_out[qn] = cs;
                 } else {
                     settle(a, v, cv, cmax);
+                    if (a.settled) a.settled[atomicAdd(&a.ctl->nsettled, 1)] = p;
                 }
             }
             qn = __builtin_amdgcn_readfirstlane(qn);
@@ -1455,8 +1458,24 @@ __global__ __launch_bounds__(WG, 6) void k_detect(RoundArgs a) {
 // Push phase for the split bucket (push mode): every chunk of a hub that settled this
 // round pushes the hub's colour over the chunk's part of the row.
 __device__ __forceinline__ void push_split_phase(const RoundArgs& a, int j, int nbk) {
-    const int nchunks = a.ctl->ccnt[a.par_in];
     const int* list = a.wl_in + a.seg[BSPLIT];
+    if (a.settled) {
+        // only the rows that settled this round, listed by the conflict test; every
+        // block takes its share of each row's chunks
+        const int ns = a.ctl->nsettled;
+        for (int i = 0; i < ns; ++i) {
+            const int v = list[a.settled[i]];
+            const int x = a.X[v];
+            const int rb = a.rowptr[v], re = a.rowptr[v + 1];
+            const int nch = split_chunks(re - rb);
+            for (int k = j; k < nch; k += nbk) {
+                const int beg = rb + k * SPLIT_CH, end = min(beg + SPLIT_CH, re);
+                push_row_coop(a, v, x, beg, end, threadIdx.x, WG);
+            }
+        }
+        return;
+    }
+    const int nchunks = a.ctl->ccnt[a.par_in];
     const int* cstart = a.cstart[a.par_in];
     const int* owner = a.owner[a.par_in];
     for (int t = j; t < nchunks; t += nbk) {
