@@ -408,6 +408,13 @@ int drive_loop(Workspace* w, Job& J, RoundArgs& a, int ub[NB], int budget, KTime
         if (tot == 0) break;
         make_plan(ub, budget, a.boff);
         const int grid = a.boff[NB];
+        a.lbs_n = grid;
+        // push-mode FirstFit does little per entry (mostly a dirty-byte check), so it runs
+        // on a smaller grid: fewer blocks to dispatch, more entries in flight per wavefront
+        int aboff[NB + 1];
+        for (int b = 0; b <= NB; ++b) aboff[b] = a.boff[b];
+        if (a.pushff) make_plan(ub, std::max(budget / 3, 1), aboff);
+        const int agrid = aboff[NB];
         for (int i = 0; i < k; ++i) {
             a.par_in = par;
             a.par_out = par ^ 1;
@@ -417,7 +424,9 @@ int drive_loop(Workspace* w, Job& J, RoundArgs& a, int ub[NB], int budget, KTime
                 a.jpc = (int)launched + 1;    // colour of this JP round
                 T.run(1, [&] { k_jp_prep<<<1, 256, 0, st>>>(a.ctl, a.par_out, a.lbs, grid); });
             } else {
-                T.run(1, [&] { k_assign<<<grid, WG, 0, st>>>(a); });
+                RoundArgs aa = a;
+                for (int b = 0; b <= NB; ++b) aa.boff[b] = aboff[b];
+                T.run(1, [&] { k_assign<<<agrid, WG, 0, st>>>(aa); });
             }
             T.run(2, [&] { k_detect<<<grid, WG, 0, st>>>(a); });
             if (a.pushff && ub[BSPLIT] > 0) {
@@ -448,6 +457,7 @@ int drive_persistent(Workspace* w, Job& J, RoundArgs& a, int budget, KTimer& T) 
     const int cus = num_cus(w->device);
     const int grid = std::min(std::max(per_cu, 1) * cus, budget);
     a.dev_plan = 1;
+    a.lbs_n = grid;
     // round index 1 (the second round) reads parity 1; odd rounds 1 -> 0, even rounds 0 -> 1
     RoundArgs a_odd = a, a_even = a;
     a_odd.par_in = 1;
@@ -479,6 +489,7 @@ int drive_persistent(Workspace* w, Job& J, RoundArgs& a, int budget, KTimer& T) 
 // same (same arrays, sizes and options).
 int drive_graph(Workspace* w, Job& J, RoundArgs& a, int budget) {
     a.dev_plan = 1;
+    a.lbs_n = budget;
     if (!w->gstream) {
         HIP_TRY(hipStreamCreateWithFlags(&w->gstream, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&w->gev, hipEventDisableTiming));

@@ -176,6 +176,7 @@ struct RoundArgs {
     // ordered compaction (nullptr = off): one look-back status word per block of the
     // grid, cleared by the FirstFit launch of the round
     unsigned long long* lbs;
+    int lbs_n;          // status words to clear: the conflict-test grid size
     // JP (rule RULE_JP): this round's colour and the priority generator's seed
     int jpc;
     unsigned long long seed;

@@ -641,8 +641,10 @@ __device__ __forceinline__ void assign_phase(const RoundArgs& a, RoundLds& s, in
         a.ctl->ccnt[a.par_out] = 0;
         a.ctl->nsettled = 0;
     }
-    // the conflict test of this round uses one look-back status word per block
-    if (a.lbs && threadIdx.x == 0) st_agent(&a.lbs[bid], 0ull);
+    // the conflict test of this round uses one look-back status word per block of its
+    // grid (the FirstFit grid may be smaller)
+    if (a.lbs && threadIdx.x == 0)
+        for (int i = bid; i < a.lbs_n; i += gridDim.x) st_agent(&a.lbs[i], 0ull);
     if (bid >= boff[NB]) return;
     const int cnt = a.ctl->cnt[a.par_in][b];
     const int* list = a.wl_in + a.seg[b];
