@@ -596,7 +596,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     const bool use_live = J.opt.live && J.opt.rule == 0 && J.opt.algo == CSRCOLOR_ALGO_SGR &&
                           hist[NTILE] + hist[NTILE + 1] + hist[BSPLIT] > 0;
     const size_t split_ints = 2 * (size_t)nhub + 2 * (size_t)nchunk + (size_t)nhub * (HW + 2) +
-                              (use_live ? (size_t)nchunk : 0) + (size_t)nhub;
+                              (use_live ? (size_t)nchunk : 0) + 2 * (size_t)nchunk;
     if ((rc = ensure_split(w, split_ints))) return rc;
     int* cstart0 = w->split;
     int* cstart1 = cstart0 + nhub;
@@ -678,6 +678,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     a.hubdone = hubflags + (size_t)nhub * HW;
     a.hublost = a.hubdone + nhub;
     a.settled = (J.opt.pushff && nhub > 0) ? settled : nullptr;
+    a.settled_k = settled + nchunk;
     a.pushff = J.opt.pushff;
     a.F = F;
     a.dirty = F ? w->dirty : nullptr;

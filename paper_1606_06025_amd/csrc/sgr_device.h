@@ -122,7 +122,7 @@ struct Ctl {
     int pdone;          // persistent mode: set when a round found every queue empty
     int tk[8];          // ordered compaction: conflict-test tickets per bucket (reset by FirstFit)
     int tk1;            // ordered compaction: round-1 tickets
-    int nsettled;       // split rows that settled this round (their queue entries in `settled`)
+    int nsettled;       // push tasks (split row, chunk) of the rows that settled this round
     int pad[2];
     // device-wide barrier of the persistent mode, each counter on its own 128-byte line
     int bar[8][32];
@@ -187,7 +187,8 @@ struct RoundArgs {
     unsigned* hubbm;
     int* hubdone;
     int* hublost;
-    int* settled;       // queue entries of the split rows that settled this round
+    int* settled;       // push tasks of the split rows that settled this round: queue entry
+    int* settled_k;     // and chunk index
     int st_cap;
     long long* st_wsize;
     long long* st_arcs;

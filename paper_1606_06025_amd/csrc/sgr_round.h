@@ -1284,12 +1284,19 @@ __device__ __forceinline__ void detect_split(const RoundArgs& a, const int* list
                     s.sh[3] = cs;
                 } else {
                     settle(a, v, cv, cmax);
-                    if (a.settled) a.settled[atomicAdd(&a.ctl->nsettled, 1)] = p;
+                    s.sh[3] = a.settled ? atomicAdd(&a.ctl->nsettled, nch) : 0;
                 }
             }
             __syncthreads();
-            if (s.sh[2] >= 0)
+            if (s.sh[2] >= 0) {
                 for (int i = tid; i < nch; i += WG) owner_out[s.sh[3] + i] = s.sh[2];
+            } else if (a.settled) {
+                // one push task per chunk of the settled row
+                for (int i = tid; i < nch; i += WG) {
+                    a.settled[s.sh[3] + i] = p;
+                    a.settled_k[s.sh[3] + i] = i;
+                }
+            }
         }
         __syncthreads();
     }
@@ -1352,13 +1359,20 @@ __device__ __forceinline__ void detect_split_wave(const RoundArgs& a, const int*
                     cstart_out[qn] = cs;
                 } else {
                     settle(a, v, cv, cmax);
-                    if (a.settled) a.settled[atomicAdd(&a.ctl->nsettled, 1)] = p;
+                    cs = a.settled ? atomicAdd(&a.ctl->nsettled, nch) : 0;
                 }
             }
             qn = __builtin_amdgcn_readfirstlane(qn);
             cs = __builtin_amdgcn_readfirstlane(cs);
-            if (qn >= 0)
+            if (qn >= 0) {
                 for (int i = lane; i < nch; i += 64) owner_out[cs + i] = qn;
+            } else if (a.settled) {
+                // one push task per chunk of the settled row
+                for (int i = lane; i < nch; i += 64) {
+                    a.settled[cs + i] = p;
+                    a.settled_k[cs + i] = i;
+                }
+            }
         }
     }
 }
@@ -1462,18 +1476,15 @@ __global__ __launch_bounds__(WG, 6) void k_detect(RoundArgs a) {
 __device__ __forceinline__ void push_split_phase(const RoundArgs& a, int j, int nbk) {
     const int* list = a.wl_in + a.seg[BSPLIT];
     if (a.settled) {
-        // only the rows that settled this round, listed by the conflict test; every
-        // block takes its share of each row's chunks
+        // only the chunks of the rows that settled this round, listed by the conflict test
         const int ns = a.ctl->nsettled;
-        for (int i = 0; i < ns; ++i) {
-            const int v = list[a.settled[i]];
+        for (int t = j; t < ns; t += nbk) {
+            const int v = list[a.settled[t]];
+            const int k = a.settled_k[t];
             const int x = a.X[v];
             const int rb = a.rowptr[v], re = a.rowptr[v + 1];
-            const int nch = split_chunks(re - rb);
-            for (int k = j; k < nch; k += nbk) {
-                const int beg = rb + k * SPLIT_CH, end = min(beg + SPLIT_CH, re);
-                push_row_coop(a, v, x, beg, end, threadIdx.x, WG);
-            }
+            const int beg = rb + k * SPLIT_CH, end = min(beg + SPLIT_CH, re);
+            push_row_coop(a, v, x, beg, end, threadIdx.x, WG);
         }
         return;
     }
