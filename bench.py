@@ -474,6 +474,7 @@ def main() -> int:
     ap.add_argument("--rule", type=int, default=0, help="conflict rule: 0 = higher id, 1 = smaller degree requeued")
     ap.add_argument("--hints", type=int, default=0, help="conflict hints: 0 = default (on), -1 = off")
     ap.add_argument("--live-lists", type=int, default=0, help="live lists: 0 = default (on), -1 = off")
+    ap.add_argument("--wake", type=int, default=0, help="wake lists: 0 = default (on), -1 = off")
     ap.add_argument("--ordered", type=int, default=0, help="ordered worklist compaction: 0 = default (off), 1 = on")
     ap.add_argument("--jp-seed", type=int, default=1)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -523,7 +524,7 @@ def main() -> int:
     tuned = dict(mode=args.mode, lane_assign=args.lane_assign, lane_detect=args.lane_detect,
                  t_wave=args.t_wave, t_split=args.t_split, blocks_per_cu=args.blocks_per_cu,
                  sync_every=args.sync_every, firstfit=args.firstfit, rule=args.rule, hints=args.hints,
-                 live_lists=args.live_lists, ordered=args.ordered)
+                 live_lists=args.live_lists, ordered=args.ordered, wake=args.wake)
     algo = {"sgr": 0, "topo": 1, "jp": 2}[args.algo]
     if args.autotune and algo == 0:
         from paper_1606_06025_amd import tune
@@ -588,23 +589,29 @@ def main() -> int:
         ows, ocr, ff_colors = oracle_stats(g, args.workload)
         if [int(x) for x in ows] != st.wsize:
             raise SystemExit("worklist sizes differ from the oracle's")
-        # arcs pushed by winners of rounds >= 2 (every vertex pushes its row once; the
-        # round-1 winners' rows are pushed by the round-1 kernel)
-        pushed = int(st.arcs[1]) if len(st.arcs) > 1 else 0
-        kb = {"k_assign": (assign_bytes(st.wsize, st.arcs, push), tot_a, na),
-              "k_detect": (detect_bytes(st.wsize, ocr, pushed, push, byte_flags), tot_d, nd)}
+        # with wake flags the kernels count the bytes they move (a separate, slower pass)
+        _, _, sc = api.color(rp, ci, out=out, opts=opts, stats=True, stats_cap=1 << 16, count_bytes=True)
+        if sc.kernel_bytes and any(sc.kernel_bytes):
+            kb = {"k_wassign": (sc.kernel_bytes[0] * args.steps, tot_a, na),
+                  "k_detect_flags": (sc.kernel_bytes[1] * args.steps, tot_d, nd)}
+        else:
+            # arcs pushed by winners of rounds >= 2 (every vertex pushes its row once; the
+            # round-1 winners' rows are pushed by the round-1 kernel)
+            pushed = int(st.arcs[1]) if len(st.arcs) > 1 else 0
+            kb = {"k_assign": (assign_bytes(st.wsize, st.arcs, push) * args.steps, tot_a, na),
+                  "k_detect": (detect_bytes(st.wsize, ocr, pushed, push, byte_flags) * args.steps, tot_d, nd)}
         dom = max(kb, key=lambda k: kb[k][1])
         byts, tms, nl = kb[dom]
         launches_per_step = nl / args.steps
         avg_launch_ms = tms / nl if nl else float("nan")
-        bytes_per_launch = byts / launches_per_step if launches_per_step else 0.0
+        bytes_per_launch = byts / nl if nl else 0.0
         achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if nl else 0.0
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": measured_traffic(args.workload, dom), "bytes_per_launch": round(bytes_per_launch),
                     "avg_launch_us": round(avg_launch_ms * 1e3, 2),
                     "launches_per_step": launches_per_step,
-                    "other_kernels_gbs": {k: round(v[0] * args.steps / (v[1] * 1e-3) / 1e9, 1)
+                    "other_kernels_gbs": {k: round(v[0] / (v[1] * 1e-3) / 1e9, 1)
                                           for k, v in kb.items() if k != dom and v[1] > 0}}
         kern = {"ms_assign_per_step": round(tot_a / args.steps, 3),
                 "ms_detect_per_step": round(tot_d / args.steps, 3),

@@ -124,6 +124,10 @@ typedef struct {
     int32_t ordered;        /* 0: default (off); 1: on; -1: off.  Order-preserving worklist compaction: blocks
                                take tickets and place their losers after those of lower tickets (look-back
                                prefix), so every worklist keeps ascending id order (same colouring) */
+    int32_t wake;           /* 0: default (on); 1: on; -1: off.  Wake lists (id rule, push FirstFit, hints on,
+                               LOOP mode, unordered compaction): a requeued vertex is tested again only once its
+                               tentative colour or that of the neighbour that requeued it has changed; every
+                               other one loses again without being read (same colouring and rounds) */
 } csrcolor_opts;
 
 /* Optional run statistics (HOST struct).  Set `cap`, `time_kernels` and the array
@@ -146,6 +150,10 @@ typedef struct {
     double ms_detect;       /* out (time_kernels): all conflict-test kernel launches */
     int32_t n_assign;       /* out (time_kernels): FirstFit launches */
     int32_t n_detect;       /* out (time_kernels): conflict-test launches */
+    int64_t *kernel_bytes;  /* in: NULL, or a HOST array of 2 filled on return: the bytes moved (each element
+                               read or written counted once, at its size) by all recolouring FirstFit launches
+                               and all flag-scanning conflict-test launches of a run with wake flags (0 for
+                               other runs).  Counting runs slower kernels: request it apart from timing */
 } csrcolor_stats;
 
 /* Colour one graph (Sec. 3.1, Algorithm Data-GC).

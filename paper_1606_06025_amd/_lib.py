@@ -45,7 +45,8 @@ class Opts(ctypes.Structure):
                 ("lane_detect", ctypes.c_int32), ("firstfit", ctypes.c_int32),
                 ("rule", ctypes.c_int32), ("algorithm", ctypes.c_int32), ("seed_lo", ctypes.c_uint32),
                 ("seed_hi", ctypes.c_uint32), ("hints", ctypes.c_int32),
-                ("live_lists", ctypes.c_int32), ("ordered", ctypes.c_int32)]
+                ("live_lists", ctypes.c_int32), ("ordered", ctypes.c_int32),
+                ("wake", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -54,7 +55,8 @@ class Stats(ctypes.Structure):
                 ("time_kernels", ctypes.c_int32), ("wsize", ctypes.POINTER(ctypes.c_int64)),
                 ("arcs", ctypes.POINTER(ctypes.c_int64)), ("ms_setup", ctypes.c_double),
                 ("ms_assign", ctypes.c_double), ("ms_detect", ctypes.c_double),
-                ("n_assign", ctypes.c_int32), ("n_detect", ctypes.c_int32)]
+                ("n_assign", ctypes.c_int32), ("n_detect", ctypes.c_int32),
+                ("kernel_bytes", ctypes.POINTER(ctypes.c_int64))]
 
 
 class CsrColorError(RuntimeError):

@@ -24,12 +24,14 @@ class ColorStats:
     ms_detect: float = 0.0
     n_assign: int = 0
     n_detect: int = 0
+    kernel_bytes: Optional[List[int]] = None   # [recolouring FirstFit, flag-scanning test] bytes moved
 
 
 def make_opts(mode: int = 0, validate: int = 0, t_wave: int = 0, t_split: int = 0,
               blocks_per_cu: int = 0, sync_every: int = 0, lane_assign: int = 0,
               lane_detect: int = 0, firstfit: int = 0, rule: int = 0, algorithm: int = 0,
-              seed: int = 0, hints: int = 0, live_lists: int = 0, ordered: int = 0) -> L.Opts:
+              seed: int = 0, hints: int = 0, live_lists: int = 0, ordered: int = 0,
+              wake: int = 0) -> L.Opts:
     o = L.Opts()
     o.mode, o.validate, o.t_wave, o.t_split = mode, validate, t_wave, t_split
     o.blocks_per_cu, o.sync_every = blocks_per_cu, sync_every
@@ -38,6 +40,7 @@ def make_opts(mode: int = 0, validate: int = 0, t_wave: int = 0, t_split: int = 
     o.hints = hints
     o.live_lists = live_lists
     o.ordered = ordered
+    o.wake = wake
     seed &= (1 << 64) - 1
     o.seed_lo, o.seed_hi = seed & 0xFFFFFFFF, seed >> 32
     return o
@@ -62,9 +65,11 @@ def _check_csr(rowptr: torch.Tensor, colidx: torch.Tensor) -> int:
 
 def color(rowptr: torch.Tensor, colidx: torch.Tensor, out: Optional[torch.Tensor] = None,
           opts: Optional[L.Opts] = None, stats: bool = False, stats_cap: int = 4096,
-          time_kernels: bool = False,
+          time_kernels: bool = False, count_bytes: bool = False,
           stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, int, Optional[ColorStats]]:
-    """Colour one graph.  Returns (colors int32[n] on the device, ncolors, stats)."""
+    """Colour one graph.  Returns (colors int32[n] on the device, ncolors, stats).
+    count_bytes: also count the bytes moved by the wake-flag kernels (slower kernels;
+    ColorStats.kernel_bytes)."""
     lib = L.load()
     n = _check_csr(rowptr, colidx)
     if out is None:
@@ -73,8 +78,8 @@ def color(rowptr: torch.Tensor, colidx: torch.Tensor, out: Optional[torch.Tensor
         raise ValueError("out must be an int32 device tensor with n entries")
     nc = ctypes.c_int32(0)
     st = None
-    wbuf = abuf = None
-    if stats or time_kernels:
+    wbuf = abuf = kbuf = None
+    if stats or time_kernels or count_bytes:
         st = L.Stats()
         st.time_kernels = 1 if time_kernels else 0
         wbuf = (ctypes.c_int64 * stats_cap)()
@@ -82,6 +87,9 @@ def color(rowptr: torch.Tensor, colidx: torch.Tensor, out: Optional[torch.Tensor
         st.cap = stats_cap
         st.wsize = ctypes.cast(wbuf, ctypes.POINTER(ctypes.c_int64))
         st.arcs = ctypes.cast(abuf, ctypes.POINTER(ctypes.c_int64))
+        if count_bytes:
+            kbuf = (ctypes.c_int64 * 2)()
+            st.kernel_bytes = ctypes.cast(kbuf, ctypes.POINTER(ctypes.c_int64))
     rc = lib.csrcolor_color_ex(n, rowptr.data_ptr(), colidx.data_ptr(), out.data_ptr(), ctypes.byref(nc),
                                ctypes.byref(opts) if opts is not None else None,
                                ctypes.byref(st) if st is not None else None, _stream_ptr(stream))
@@ -91,7 +99,7 @@ def color(rowptr: torch.Tensor, colidx: torch.Tensor, out: Optional[torch.Tensor
         k = min(st.rounds, stats_cap)
         cs = ColorStats(st.rounds, st.ncolors, bool(st.rows_sorted), st.max_degree, st.nnz,
                         list(wbuf[:k]), list(abuf[:k]), st.ms_setup, st.ms_assign, st.ms_detect,
-                        st.n_assign, st.n_detect)
+                        st.n_assign, st.n_detect, list(kbuf) if kbuf is not None else None)
     return out[:n], int(nc.value), cs
 
 

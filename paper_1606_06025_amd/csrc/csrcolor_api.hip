@@ -35,6 +35,10 @@ struct Workspace {
     int* hint = nullptr;         // conflict hints: a neighbour that beat the vertex
     int* llen = nullptr;         // live-list lengths (or a split row's chunk-slot base)
     unsigned char* dirty = nullptr;   // push FirstFit: flags changed since the last FirstFit
+    unsigned char* rflag = nullptr;   // wake flags: recolour this round (padded to whole scans)
+    unsigned char* aflag = nullptr;   // wake flags: test this round (padded likewise)
+    int* srnd = nullptr;              // wake flags: settling round per vertex
+    unsigned long long* ubytes = nullptr;   // wake flags: bytes moved by the two kernels (on request)
     int* live = nullptr;         // live lists, same offsets as colidx
     size_t live_cap = 0;         // ints
     unsigned long long* lb = nullptr;   // look-back status words of ordered compaction
@@ -183,6 +187,11 @@ void free_vertex_arrays(Workspace* w) {
     if (w->hint) (void)hipFree(w->hint);
     if (w->llen) (void)hipFree(w->llen);
     if (w->dirty) (void)hipFree(w->dirty);
+    if (w->rflag) (void)hipFree(w->rflag);
+    if (w->aflag) (void)hipFree(w->aflag);
+    if (w->srnd) (void)hipFree(w->srnd);
+    w->rflag = w->aflag = nullptr;
+    w->srnd = nullptr;
     w->X = w->wl[0] = w->wl[1] = w->hint = w->llen = nullptr;
     w->dirty = nullptr;
     w->cap_n = 0;
@@ -206,9 +215,13 @@ void free_ws_arrays(Workspace* w) {
     free_vertex_arrays(w);
 }
 
+// Bytes of a wake-flag array for n vertices: whole scans of VPW vertices, zero padded.
+size_t flag_bytes(size_t n) { return (n + VPW - 1) / VPW * VPW + VPW; }
+
 int ensure_capacity(Workspace* w, size_t n, int st_cap) {
     if (!w->ctl) {
         HIP_TRY(hipMalloc(&w->ctl, sizeof(Ctl)));
+        HIP_TRY(hipMalloc(&w->ubytes, 2 * sizeof(unsigned long long)));
         if (hipHostMalloc(&w->ctl_h, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return CSRCOLOR_ENOMEM;
     }
     if (n > w->cap_n) {
@@ -220,6 +233,9 @@ int ensure_capacity(Workspace* w, size_t n, int st_cap) {
             hipMalloc(&w->wl[1], want * sizeof(int)) != hipSuccess ||
             hipMalloc(&w->hint, want * sizeof(int)) != hipSuccess ||
             hipMalloc(&w->llen, want * sizeof(int)) != hipSuccess ||
+            hipMalloc(&w->rflag, flag_bytes(want)) != hipSuccess ||
+            hipMalloc(&w->aflag, flag_bytes(want)) != hipSuccess ||
+            hipMalloc(&w->srnd, want * sizeof(int)) != hipSuccess ||
             hipMalloc(&w->dirty, want + 16) != hipSuccess) {
             free_vertex_arrays(w);
             return CSRCOLOR_ENOMEM;
@@ -307,6 +323,7 @@ struct Options {
     int hints = 1;            // conflict hints (id rule)
     int live = 1;             // live lists for degree > 61 (id rule)
     int ordered = 0;          // order-preserving worklist compaction (measured slower on the stencil)
+    int wake = 1;             // wake lists (id rule, push FirstFit, hints, LOOP mode, unordered)
     int rule = 0;             // conflict rule (csrcolor_rule)
     int algo = CSRCOLOR_ALGO_SGR;
     unsigned long long seed = 0;
@@ -319,7 +336,7 @@ bool opts_valid(const csrcolor_opts* o, bool single) {
     if (o->mode < 0 || o->mode > CSRCOLOR_MODE_GRAPH || o->validate < 0 || o->firstfit < 0 || o->firstfit > 3 ||
         o->rule < 0 || o->rule > 1 || o->algorithm < 0 || o->algorithm > CSRCOLOR_ALGO_JP || o->hints < -1 ||
         o->hints > 1 || o->live_lists < -1 || o->live_lists > 1 ||
-        o->ordered < -1 || o->ordered > 1)
+        o->ordered < -1 || o->ordered > 1 || o->wake < -1 || o->wake > 1)
         return false;
     if (o->algorithm != CSRCOLOR_ALGO_SGR && (o->mode == CSRCOLOR_MODE_PERSISTENT || o->mode == CSRCOLOR_MODE_GRAPH))
         return false;
@@ -343,6 +360,7 @@ Options parse_opts(const csrcolor_opts* o) {
     if (o->hints) r.hints = o->hints > 0;
     if (o->live_lists) r.live = o->live_lists > 0;
     if (o->ordered) r.ordered = o->ordered > 0;
+    if (o->wake) r.wake = o->wake > 0;
     r.rule = o->rule;
     r.algo = o->algorithm;
     r.seed = ((unsigned long long)o->seed_hi << 32) | o->seed_lo;
@@ -388,6 +406,7 @@ struct Job {
     int ncolors = 0;
     int rounds = 0;
     int sorted = 1;
+    bool wake = false;       // the rounds ran with wake flags (statistics from settling rounds)
     int maxdeg = 0;
     long long nnz = 0;
 };
@@ -428,10 +447,10 @@ int drive_loop(Workspace* w, Job& J, RoundArgs& a, int ub[NB], int budget, KTime
                 for (int b = 0; b <= NB; ++b) aa.boff[b] = aboff[b];
                 T.run(1, [&] { k_assign<<<agrid, WG, 0, st>>>(aa); });
             }
-            T.run(2, [&] { k_detect<<<grid, WG, 0, st>>>(a); });
+            T.run(2, [&] { k_detect<false><<<grid, WG, 0, st>>>(a); });
             if (a.pushff && ub[BSPLIT] > 0) {
                 const int pg = std::min(ub[BSPLIT], budget);
-                T.run(2, [&] { k_push<<<pg, WG, 0, st>>>(a); });
+                T.run(2, [&] { k_push<false><<<pg, WG, 0, st>>>(a); });
             }
             par ^= 1;
             ++launched;
@@ -444,6 +463,61 @@ int drive_loop(Workspace* w, Job& J, RoundArgs& a, int ub[NB], int budget, KTime
         for (int b = 0; b < NB; ++b) left += (ub[b] = w->ctl_h->cnt[par][b]);
         ub[BSPLIT] = w->ctl_h->ccnt[par];
         if (left > 0 && launched > (long long)J.n + 2) return CSRCOLOR_ELIMIT;   // rounds <= n
+        k = std::min(k * 2, J.opt.sync_every);
+    }
+    return CSRCOLOR_OK;
+}
+
+// Host loop with wake flags: per round the recolouring FirstFit and the conflict test,
+// both scanning the flag bytes of every vertex (plus the worklists of the long rows,
+// device-side partition) and, when split rows exist, their push phase.  The conflict
+// test stores the round number when it tests a vertex; a round that tests none means
+// every vertex is settled (the lowest uncoloured vertex is always tested).  That is
+// read back every few rounds; rounds launched past the end do nothing.
+int drive_wake(Workspace* w, Job& J, RoundArgs& a, int budget, bool big, int nhub, int nchunk, KTimer& T) {
+    hipStream_t st = w->stream;
+    a.dev_plan = 1;
+    // enough wavefronts to fill the chip (about 4096) even for smaller graphs
+    a.vpw = J.n >= 4096 * 256 ? 256 : J.n >= 4096 * 128 ? 128 : 64;
+    const long long scans = ((long long)J.n + (long long)a.vpw * WAVES - 1) / ((long long)a.vpw * WAVES);
+    a.gdense = (int)std::max<long long>(1, std::min<long long>(scans, 4LL * budget));
+    const int pgrid = std::max(std::min(nchunk, budget), 1);
+    int par = 1;             // parity of the worklists of the next round
+    long long r = 2;         // next round (round 1 was k_round1)
+    int k = 2;
+    for (;;) {
+        for (int i = 0; i < k; ++i) {
+            a.par_in = par;
+            a.par_out = par ^ 1;
+            a.wl_in = w->wl[par];
+            a.wl_out = w->wl[par ^ 1];
+            a.wround = (int)r;
+            if (a.ubytes) T.run(1, [&] { k_wassign<true><<<a.gdense, WG, 0, st>>>(a); });
+            else T.run(1, [&] { k_wassign<false><<<a.gdense, WG, 0, st>>>(a); });
+            if (big && a.ubytes) {
+                // counting: the flag scan on its own, then the worklists of the long rows
+                RoundArgs al = a;
+                al.gdense = 0;
+                T.run(2, [&] { k_detect_flags<true><<<a.gdense, WG, 0, st>>>(a); });
+                T.run(2, [&] { k_detect<true><<<budget, WG, 0, st>>>(al); });
+            } else if (big) {
+                // one launch: flag scan in the first gdense blocks, worklists of the long rows after
+                T.run(2, [&] { k_detect<true><<<a.gdense + budget, WG, 0, st>>>(a); });
+            } else if (a.ubytes) {
+                T.run(2, [&] { k_detect_flags<true><<<a.gdense, WG, 0, st>>>(a); });
+            } else {
+                T.run(2, [&] { k_detect_flags<false><<<a.gdense, WG, 0, st>>>(a); });
+            }
+            if (nhub > 0) T.run(2, [&] { k_push<true><<<pgrid, WG, 0, st>>>(a); });
+            par ^= 1;
+            ++r;
+        }
+        HIP_TRY(hipGetLastError());
+        int rc = read_ctl(w);
+        if (rc) return rc;
+        if (w->ctl_h->err) return CSRCOLOR_EHIP;
+        if (w->ctl_h->rounds < r - 1) break;
+        if (r > (long long)J.n + 2) return CSRCOLOR_ELIMIT;
         k = std::min(k * 2, J.opt.sync_every);
     }
     return CSRCOLOR_OK;
@@ -507,8 +581,8 @@ int drive_graph(Workspace* w, Job& J, RoundArgs& a, int budget) {
             r.wl_in = w->wl[par];
             r.wl_out = w->wl[par ^ 1];
             k_assign<<<budget, WG, 0, w->gstream>>>(r);
-            k_detect<<<budget, WG, 0, w->gstream>>>(r);
-            if (r.pushff && r.cstart[1] != r.cstart[0]) k_push<<<budget, WG, 0, w->gstream>>>(r);  // split hubs exist
+            k_detect<false><<<budget, WG, 0, w->gstream>>>(r);
+            if (r.pushff && r.cstart[1] != r.cstart[0]) k_push<false><<<budget, WG, 0, w->gstream>>>(r);  // split hubs exist
         }
         hipError_t ce = hipStreamEndCapture(w->gstream, &g);
         if (ce != hipSuccess) return CSRCOLOR_EHIP;
@@ -611,6 +685,21 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     int* settled = hubflags + (size_t)nhub * (HW + 2) + (use_live ? (size_t)nchunk : 0);
     if (use_live && (rc = ensure_live(w, std::max<size_t>((size_t)w->ctl_h->nnz, 1)))) return rc;
 
+    // conflict hints serve the id rule (the degree rule would need the neighbour's degree too)
+    int* hint = (J.opt.hints && J.opt.rule == 0) ? w->hint : nullptr;
+    // wake flags need the id rule's hints, push FirstFit and the host loop; ordered
+    // compaction is a property of the full worklists they replace
+    const bool use_wake = J.opt.wake && hint && J.opt.pushff && J.opt.algo == CSRCOLOR_ALGO_SGR &&
+                          J.opt.mode == CSRCOLOR_MODE_LOOP && !J.opt.ordered;
+    J.wake = use_wake;
+    if (use_wake) {
+        const int fw = (int)(flag_bytes((size_t)n) / 4);
+        T.run(0, [&] {
+            k_fill<<<std::min((fw + WG - 1) / WG, cus * 8), WG, 0, st>>>(reinterpret_cast<int*>(w->rflag), fw, 0);
+            k_fill<<<std::min((fw + WG - 1) / WG, cus * 8), WG, 0, st>>>(reinterpret_cast<int*>(w->aflag), fw, 0);
+        });
+    }
+
     // push mode: deg(v)+1 bits per vertex, zeroed
     unsigned* F = nullptr;
     if (J.opt.pushff) {
@@ -624,14 +713,13 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
                 reinterpret_cast<int*>(F), (int)words, 0);
         });
         const int dwords = n / 4 + 1;
-        T.run(0, [&] {
-            k_fill<<<std::min((dwords + WG - 1) / WG, cus * 8), WG, 0, st>>>(reinterpret_cast<int*>(w->dirty),
-                                                                                dwords, 0);
-        });
+        if (!use_wake) {
+            T.run(0, [&] {
+                k_fill<<<std::min((dwords + WG - 1) / WG, cus * 8), WG, 0, st>>>(reinterpret_cast<int*>(w->dirty),
+                                                                                    dwords, 0);
+            });
+        }
     }
-
-    // conflict hints serve the id rule (the degree rule would need the neighbour's degree too)
-    int* hint = (J.opt.hints && J.opt.rule == 0) ? w->hint : nullptr;
     const int r1blocks = (int)(((long long)n + 4 * WG - 1) / (4 * WG));
     // ordered compaction: look-back status words, NB per round-1 block, then one per
     // block of the largest round grid (cleared before each use)
@@ -652,7 +740,8 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
                                           J.sorted, twave, J.opt.tsplit, seg, cstart1, owner1, F,
                                           w->ctl_h->nnz, J.opt.rule, J.opt.algo == CSRCOLOR_ALGO_JP, hint,
                                           use_live ? w->llen : nullptr, clen, lb, J.opt.pushff == 2,
-                                          F ? w->dirty : nullptr);
+                                          (F && !use_wake) ? w->dirty : nullptr,
+                                          use_wake ? w->rflag : nullptr, w->aflag, use_wake ? w->srnd : nullptr);
     });
     HIP_TRY(hipGetLastError());
 
@@ -681,7 +770,16 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     a.settled_k = settled + nchunk;
     a.pushff = J.opt.pushff;
     a.F = F;
-    a.dirty = F ? w->dirty : nullptr;
+    a.dirty = (F && !use_wake) ? w->dirty : nullptr;
+    if (use_wake) {
+        a.rflag = w->rflag;
+        a.aflag = w->aflag;
+        a.srnd = w->srnd;
+        if (J.stats && J.stats->kernel_bytes) {
+            k_fill<<<1, 64, 0, st>>>(reinterpret_cast<int*>(w->ubytes), 4, 0);
+            a.ubytes = w->ubytes;
+        }
+    }
     a.rule = J.opt.rule;
     a.seed = J.opt.seed;
     a.hint = hint;
@@ -702,6 +800,8 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
         rc = drive_persistent(w, J, a, budget, T);
     } else if (J.opt.mode == CSRCOLOR_MODE_GRAPH) {
         rc = drive_graph(w, J, a, budget);
+    } else if (use_wake) {
+        rc = drive_wake(w, J, a, budget, hist[NTILE] + hist[NTILE + 1] + hist[BSPLIT] > 0, nhub, nchunk, T);
     } else {
         int ub[NB];
         for (int b = 0; b < NB; ++b) ub[b] = hist[b];
@@ -759,6 +859,11 @@ int run_job(Workspace* w, Job& J, const long long* voff, int G) {
         rc = run_rounds(w, J, hist, seg, st_cap, T);
     }
     if (rc) return rc;
+    if (J.wake && st_cap) {
+        // per-round settle counts and their arcs, from the settling rounds
+        k_round_hist<<<std::max(vblocks, 1), WG, 0, st>>>(n, J.rowptr, w->srnd, w->st_wsize, w->st_arcs, st_cap);
+        HIP_TRY(hipGetLastError());
+    }
     if ((rc = read_ctl(w))) return rc;
     // Vertex 0 has no lower neighbour, so it always settles in round 1 with colour 1
     // (round-1 winners do not touch the device maximum).
@@ -775,6 +880,16 @@ int run_job(Workspace* w, Job& J, const long long* voff, int G) {
             J.stats->ms_setup = J.stats->ms_assign = J.stats->ms_detect = 0;
             J.stats->n_assign = J.stats->n_detect = 0;
         }
+        if (J.stats->kernel_bytes) {
+            J.stats->kernel_bytes[0] = J.stats->kernel_bytes[1] = 0;
+            if (J.wake) {
+                unsigned long long kb[2];
+                HIP_TRY(hipMemcpyAsync(kb, w->ubytes, sizeof(kb), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                J.stats->kernel_bytes[0] = (int64_t)kb[0];
+                J.stats->kernel_bytes[1] = (int64_t)kb[1];
+            }
+        }
         J.stats->rounds = J.rounds;
         J.stats->ncolors = J.ncolors;
         J.stats->rows_sorted = J.sorted;
@@ -785,13 +900,30 @@ int run_job(Workspace* w, Job& J, const long long* voff, int G) {
             if (J.stats->wsize) {
                 HIP_TRY(hipMemcpyAsync(tmp.data(), w->st_wsize, m * sizeof(long long), hipMemcpyDeviceToHost, st));
                 HIP_TRY(hipStreamSynchronize(st));
-                for (int r = 0; r < m; ++r) J.stats->wsize[r] = tmp[r];
+                if (J.wake) {
+                    // tmp[r]: vertices settled in round r+1; W_1 = V
+                    long long left = n;
+                    for (int r = 0; r < m; ++r) {
+                        J.stats->wsize[r] = left;
+                        left -= tmp[r];
+                    }
+                } else {
+                    for (int r = 0; r < m; ++r) J.stats->wsize[r] = tmp[r];
+                }
                 J.stats->wsize[0] = n;
             }
             if (J.stats->arcs) {
                 HIP_TRY(hipMemcpyAsync(tmp.data(), w->st_arcs, m * sizeof(long long), hipMemcpyDeviceToHost, st));
                 HIP_TRY(hipStreamSynchronize(st));
-                for (int r = 0; r < m; ++r) J.stats->arcs[r] = tmp[r];
+                if (J.wake) {
+                    long long left = w->ctl_h->nnz;
+                    for (int r = 0; r < m; ++r) {
+                        J.stats->arcs[r] = left;
+                        left -= tmp[r];
+                    }
+                } else {
+                    for (int r = 0; r < m; ++r) J.stats->arcs[r] = tmp[r];
+                }
                 J.stats->arcs[0] = w->ctl_h->nnz;
             }
         }
@@ -984,6 +1116,7 @@ void csrcolor_release_workspace(void) {
         (void)hipStreamSynchronize(w->stream);
         free_ws_arrays(w);
         if (w->ctl) (void)hipFree(w->ctl);
+        if (w->ubytes) (void)hipFree(w->ubytes);
         if (w->ctl_h) (void)hipHostFree(w->ctl_h);
         if (w->st_wsize) (void)hipFree(w->st_wsize);
         if (w->st_arcs) (void)hipFree(w->st_arcs);

@@ -62,6 +62,22 @@ __device__ __forceinline__ bool conflict(int rule, const int* __restrict__ rowpt
     return (X[w] & 0x7fffffff) == cv && beats(1, rowptr, w, v, dv);
 }
 
+// Where a settling vertex pushes its colour (push-mode FirstFit).
+struct PushCtx {
+    unsigned* F;                  // forbidden-colour flags (bits, or bytes when `bytes`)
+    const int* rowptr;
+    const int* colidx;
+    int nnz;
+    bool bytes;
+    unsigned char* dirty;         // nullptr, or per-vertex "flags changed" bytes
+    // wake flags (rflag == nullptr: off): a neighbour whose tentative colour is the
+    // pushed colour must take a new one next round, so its recolour flag is set
+    const int* X;
+    unsigned char* rflag;
+    bool all_tentative;           // round 1: every neighbour of a winner holds colour 1
+    long long* nbytes;            // nullptr, or the calling thread's count of bytes moved
+};
+
 // Marks colour c among the forbidden colours of neighbour u (push-mode FirstFit).
 // Only colours <= deg(u)+1 can change u's smallest free colour, and only they have a
 // flag: flag c-1 of u sits at position rowptr[u]+u+c-1, one bit of F (set with an
@@ -70,19 +86,26 @@ __device__ __forceinline__ bool conflict(int rule, const int* __restrict__ rowpt
 // merged by the caches).
 // With `dirty`, u is also marked for its next FirstFit (a vertex whose flags did not
 // change keeps its tentative colour, and FirstFit skips it).
-__device__ __forceinline__ void push_colour(unsigned* F, const int* __restrict__ rowptr, int u, int c,
-                                            bool bytes, unsigned char* dirty) {
-    const int ub = rowptr[u];
-    const int du = rowptr[u + 1] - ub;
-    if (c - 1 <= du) {
+// With wake flags a settled neighbour is skipped (its flags are never read again), and
+// a neighbour holding tentative colour c gets its recolour flag (its smallest free
+// colour moves); concurrent writers all store 1.
+__device__ __forceinline__ void push_colour(const PushCtx& P, int u, int c) {
+    const int ub = P.rowptr[u];
+    const int ue = P.rowptr[u + 1];
+    const int xu = (P.rflag && !P.all_tentative) ? P.X[u] : (FLAG | c);
+    if (P.nbytes) *P.nbytes += 12 + (P.rflag && !P.all_tentative ? 4 : 0);   // colidx entry, rowptr pair, colour
+    if (xu > 0) return;
+    if (P.nbytes) *P.nbytes += (c - 1 <= ue - ub ? 1 : 0) + (P.rflag && xu == (FLAG | c) ? 1 : 0);
+    if (c - 1 <= ue - ub) {
         const long long pos = (long long)ub + u + c - 1;
-        if (bytes) {
-            reinterpret_cast<unsigned char*>(F)[pos] = 1;
+        if (P.bytes) {
+            reinterpret_cast<unsigned char*>(P.F)[pos] = 1;
         } else {
-            atomicOr(&F[pos >> 5], 1u << (pos & 31));
+            atomicOr(&P.F[pos >> 5], 1u << (pos & 31));
         }
-        if (dirty) dirty[u] = 1;
+        if (P.dirty) P.dirty[u] = 1;
     }
+    if (P.rflag && xu == (FLAG | c)) P.rflag[u] = 1;
 }
 
 // Internal rule number of the Jones-Plassmann independent-set colouring (Sec. 2.2,
@@ -115,7 +138,8 @@ struct Ctl {
     int desc_total;     // positions e >= 1 with colidx[e] < colidx[e-1]
     int desc_bound;     // such positions that start a non-empty row
     int maxdeg;
-    int rounds;         // number of non-empty rounds so far
+    int rounds;         // number of non-empty rounds so far (wake flags: the last round
+                        // whose conflict test found a vertex to test)
     int nnz;            // rowptr[n]
     int hchunks;        // chunks over all split-bucket vertices
     int ccnt[2];        // chunks queued in the split bucket, by round parity
@@ -189,12 +213,32 @@ struct RoundArgs {
     int* hublost;
     int* settled;       // push tasks of the split rows that settled this round: queue entry
     int* settled_k;     // and chunk index
+    // wake flags (rflag != nullptr): a requeued vertex of at most WAKE_DEG arcs is
+    // tested again only when its tentative colour or that of the neighbour that beat it
+    // (its hint) has changed, or every round while awake; longer ones stay on the
+    // worklists.  rflag[v]: recolour v this round (set by pushes); aflag[v]: test v
+    // this round (set by recolouring, kept by an awake loser); srnd[v]: the round v
+    // settled in; wround: this round's number
+    int wround;
+    unsigned char* rflag;
+    unsigned char* aflag;
+    int* srnd;
+    int gdense;         // blocks of the flag-scanning grids
+    int vpw;            // vertices per wavefront in the flag scans (64, 128 or 256)
+    // nullptr, or bytes moved (algorithmic, each element at its size) by the recolouring
+    // and the flag-scanning test launches: [0] and [1], summed over the run
+    unsigned long long* ubytes;
     int st_cap;
     long long* st_wsize;
     long long* st_arcs;
     int seg[NB + 1];    // bucket segment offsets inside the worklist arrays
     int boff[NB + 1];   // block offsets of each bucket inside the grid
 };
+
+// Wake flags: a vertex sleeps only when it and the neighbour that beat it have at most
+// WAKE_DEG arcs (the tile buckets), so waking the sleepers of a recoloured vertex reads
+// a short row; every other requeued vertex is awake (tested every round).
+constexpr int WAKE_DEG = 61;
 
 // Tentative colour of worklist vertex v: the FirstFit result in X, or under JP the
 // colour of the round.
@@ -206,10 +250,12 @@ __device__ __forceinline__ int tentative(const RoundArgs& a, int v) {
 // that settled in an earlier round cannot hold v's tentative colour (FirstFit excluded
 // it), so an equal colour part means a worklist neighbour of this round that beats v:
 // the same verdict the full scan would reach.
+// With wake flags the hint of a vertex of at most WAKE_DEG arcs carries FLAG when the
+// neighbour has more arcs (no hint is -1).
 __device__ __forceinline__ bool hint_hit(const RoundArgs& a, int v, int cv) {
     if (!a.hint) return false;
     const int h = a.hint[v];
-    return h >= 0 && h < v && (a.X[h] & CMASK) == cv;
+    return h != -1 && (h & CMASK) < v && (a.X[h & CMASK] & CMASK) == cv;
 }
 
 // Is worklist vertex v (tentative colour cv, degree dv) requeued because of row entry

@@ -1,9 +1,10 @@
-// Kernels of one speculative-greedy colouring: validation, the round-1 shortcut,
-// FirstFit (assign) and conflict test + compaction (detect) per degree bucket.
+// Kernels of one speculative-greedy colouring: validation, the round-1 shortcut and
+// the conflict-test launches (worklists per degree bucket; flag scans with wake flags).
 #pragma once
 
 #include "sgr_device.h"
 #include "sgr_round.h"
+#include "sgr_wake.h"
 
 namespace csrcolor {
 
@@ -114,7 +115,8 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
                                                int* wl1, Ctl* ctl, int sorted, int twave, int tsplit,
                                                Seg seg, int* cstart1, int* owner1, unsigned* F, int nnz,
                                                int rule, int jp, int* hint, int* llen, int* clen,
-                                               unsigned long long* lb1, int fbytes, unsigned char* dirty) {
+                                               unsigned long long* lb1, int fbytes, unsigned char* dirty,
+                                               unsigned char* rflag, unsigned char* aflag, int* srnd) {
     constexpr int ITER = 4;
     __shared__ int buf[WAVES][NB][ITER * 64];
     __shared__ int wcnt[WAVES][NB];
@@ -122,6 +124,20 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
     const int lane = __lane_id();
     const int wv = threadIdx.x >> 6;
     int cnt[NB] = {};
+    // wake flags (rflag): a loser of at most WAKE_DEG arcs is not listed but sleeps, or
+    // keeps its test flag when its hint is longer; every neighbour of a winner (a loser
+    // holding colour 1) gets its recolour flag; winners record their settling round
+    PushCtx P;
+    P.F = F;
+    P.rowptr = rowptr;
+    P.colidx = colidx;
+    P.nnz = nnz;
+    P.bytes = fbytes != 0;
+    P.dirty = dirty;
+    P.X = X;
+    P.rflag = rflag;
+    P.all_tentative = true;
+    P.nbytes = nullptr;
     // SGR: this is round 1.  JP: this only builds W_1 (every vertex with a neighbour;
     // an isolated vertex is alone in its neighbourhood and takes colour 1 here), and
     // the conflict-test launches count the rounds.
@@ -164,10 +180,19 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
                     }
                 }
             }
-            if (lose && hint) hint[v] = by;
+            if (lose && hint) {
+                if (rflag && end - beg <= WAKE_DEG) {
+                    const bool big = rowptr[by + 1] - rowptr[by] > WAKE_DEG;
+                    hint[v] = big ? (by | FLAG) : by;
+                    aflag[v] = big;
+                } else {
+                    hint[v] = by;
+                }
+            }
             if (lose) {
                 X[v] = jp ? 0 : (FLAG | 1);
                 bkt = bucket_of(end - beg, twave, tsplit);
+                if (rflag && bkt < NTILE) bkt = -1;      // wake flags: not listed
                 if (llen && bkt >= NTILE && bkt < BSPLIT) llen[v] = -1;   // live list not built yet
                 if (bkt == BSPLIT) {
                     // split rows are few: one queue slot and one chunk range per vertex
@@ -188,13 +213,14 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
             } else {
                 X[v] = 1;
                 out[v] = 0;
+                if (srnd) srnd[v] = 1;
                 winpush = F != nullptr && end > beg;
                 wbeg = beg;
                 wend = end;
             }
         }
         // round-1 winners push colour 1, the whole wavefront over their concatenated rows
-        if (F != nullptr) push_rows_wave(F, rowptr, colidx, nnz, winpush, (int)vv, 1, wbeg, wend, fbytes != 0, dirty);
+        if (F != nullptr) push_rows_wave(P, winpush, (int)vv, 1, wbeg, wend);
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const unsigned long long m = __ballot(bkt == b);
@@ -240,6 +266,80 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
     }
 }
 
+
+// Flag-scanning conflict test of the vertices of at most WAKE_DEG arcs for the
+// wavefronts of blocks [0, nblk): every wavefront scans the test flags of its vpw
+// vertices and tests the flagged ones.  A wavefront that tests a vertex stores the
+// round number (every writer stores the same).
+template <bool C>
+__device__ __forceinline__ void detect_flags_phase(const RoundArgs& a, int* ids, int* slot, int nblk, int& cmax,
+                                                   long long* red64) {
+    long long nb = 0;          // bytes moved (counted only on request)
+    bool any = false;
+    const long long nwv = (long long)nblk * WAVES;
+    const int k = a.vpw / 64;
+    for (long long wid = (long long)blockIdx.x * WAVES + (threadIdx.x >> 6); wid * a.vpw < a.n; wid += nwv) {
+        const long long v0 = wid * a.vpw;
+        const int cnt = flag_compact(load_flags(a.aflag, v0, k), (int)v0, k, ids);
+        if (C) nb += k;
+        if (cnt) {
+            any = true;
+            test_flagged<C>(a, ids, cnt, slot, cmax, nb);
+        }
+    }
+    if (any && __lane_id() == 0) a.ctl->rounds = a.wround;
+    if (C) {
+        const long long t = block_sum64(nb, red64);
+        if (threadIdx.x == 0 && t) atomicAdd(&a.ubytes[1], (unsigned long long)t);
+    }
+}
+
+// Conflict test of a round (Sec. 3, ConflictResolve; see detect_phase), one launch for
+// every degree bucket.  With wake flags (W) the first gdense blocks run the flag scan
+// of the vertices of at most WAKE_DEG arcs and the others the worklists of the longer
+// ones (k_detect_flags alone serves graphs without longer rows).
+template <bool W>
+__global__ __launch_bounds__(WG, W ? 5 : 6) void k_detect(RoundArgs a) {
+    __shared__ RoundLds s;
+    __shared__ int boff[NB + 1];
+    int cmax = 0;
+    if (W && (int)blockIdx.x < a.gdense) {
+        const int wv = threadIdx.x >> 6;
+        detect_flags_phase<false>(a, s.lbuf + wv * WAVE_CAP, s.res + wv * 64, a.gdense, cmax, s.red64);
+    } else {
+        const int bid = W ? (int)blockIdx.x - a.gdense : (int)blockIdx.x;
+        const int nblk = W ? (int)gridDim.x - a.gdense : (int)gridDim.x;
+        if (threadIdx.x == 0) {
+            if (a.dev_plan) {
+                int cnt[NB];
+                queue_sizes(a.ctl, a.par_in, cnt);
+                device_plan(cnt, nblk, boff);
+            } else {
+                for (int k = 0; k <= NB; ++k) boff[k] = a.boff[k];
+            }
+        }
+        __syncthreads();
+        detect_phase<W>(a, s, bid, boff, cmax);
+    }
+    cmax = block_max(cmax, s.red);
+    // with wake flags a colour at or below the current maximum needs no device atomic
+    if (threadIdx.x == 0 && cmax > 0 && (!W || cmax > ld_agent(&a.ctl->maxcolor)))
+        atomicMax(&a.ctl->maxcolor, cmax);
+}
+
+// Flag-scanning conflict test alone (wake flags, no row longer than WAKE_DEG).
+template <bool C>
+__global__ __launch_bounds__(WG) void k_detect_flags(RoundArgs a) {
+    __shared__ int ids[WAVES][VPW];
+    __shared__ int slot[WAVES][64];
+    __shared__ int red[WAVES];
+    __shared__ long long red64[WAVES];
+    const int wv = threadIdx.x >> 6;
+    int cmax = 0;
+    detect_flags_phase<C>(a, ids[wv], slot[wv], gridDim.x, cmax, red64);
+    cmax = block_max(cmax, red);
+    if (threadIdx.x == 0 && cmax > ld_agent(&a.ctl->maxcolor)) atomicMax(&a.ctl->maxcolor, cmax);
+}
 
 // Per-graph colour count of a batched run: ncolors[g] = 1 + max colour in graph g.
 __global__ __launch_bounds__(WG) void k_segmented_max(int G, const long long* __restrict__ voff,

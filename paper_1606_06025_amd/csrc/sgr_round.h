@@ -1,5 +1,6 @@
-// Round kernels: FirstFit (k_assign) and conflict test + clearing + compaction
-// (k_detect), one launch each per round, every degree bucket in the same grid.
+// Round phases: FirstFit (k_assign) and conflict test + clearing + compaction (the
+// phase run by k_detect), one launch each per round, every degree bucket in the same
+// grid.
 //
 // Cost model that shapes them: on gfx950 a wave64 vector-memory instruction costs
 // the compute unit's address unit about the same whatever its lanes do, so the
@@ -140,21 +141,15 @@ __device__ __forceinline__ void wave_slice(int lo, int hi, int& wlo, int& whi) {
 // ---------------------------------------------------------------------------
 
 // `nthr` threads (thread index t) push colour c of v over row [beg, end) together.
-__device__ __forceinline__ void push_row_coop(unsigned* F, const int* __restrict__ rowptr,
-                                              const int* __restrict__ colidx, int nnz, int v, int c, int beg,
-                                              int end, int t, int nthr, bool bytes, unsigned char* dirty) {
+__device__ __forceinline__ void push_row_coop(const PushCtx& P, int v, int c, int beg, int end, int t, int nthr) {
     const int nq = ((end - beg) + 3 + 3) / 4 + 1;
     for (int q0 = 0; q0 < nq; q0 += nthr) {
         int w[4];
-        load_quad(colidx, nnz, beg, end, q0 + t, w);
+        load_quad(P.colidx, P.nnz, beg, end, q0 + t, w);
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (w[k] >= 0 && w[k] != v) push_colour(F, rowptr, w[k], c, bytes, dirty);
+            if (w[k] >= 0 && w[k] != v) push_colour(P, w[k], c);
     }
-}
-__device__ __forceinline__ void push_row_coop(const RoundArgs& a, int v, int c, int beg, int end, int t,
-                                              int nthr) {
-    push_row_coop(a.F, a.rowptr, a.colidx, a.nnz, v, c, beg, end, t, nthr, a.pushff == 2, a.dirty);
 }
 
 // The whole wavefront pushes the colours of its winners: lane l contributes the row
@@ -162,11 +157,9 @@ __device__ __forceinline__ void push_row_coop(const RoundArgs& a, int v, int c, 
 // quad (a prefix sum over the lanes) and the 64 lanes walk the concatenation, each
 // finding its row by a binary search over the prefix, so a wavefront with one long
 // or a few short winner rows does not serialise on one lane.  Every lane must call.
-__device__ __forceinline__ void push_rows_wave(unsigned* F, const int* __restrict__ rowptr,
-                                               const int* __restrict__ colidx, int nnz, bool win, int v, int c,
-                                               int beg, int end, bool bytes, unsigned char* dirty) {
+__device__ __forceinline__ void push_rows_wave(const PushCtx& P, bool win, int v, int c, int beg, int end) {
     const int lane = __lane_id();
-    const int mis = (int)((reinterpret_cast<uintptr_t>(colidx) >> 2) & 3);
+    const int mis = (int)((reinterpret_cast<uintptr_t>(P.colidx) >> 2) & 3);
     const int nq = win && end > beg ? (((end - 1 + mis) >> 2) - ((beg + mis) >> 2) + 1) : 0;
     int incl = nq;
 #pragma unroll
@@ -190,15 +183,38 @@ __device__ __forceinline__ void push_rows_wave(unsigned* F, const int* __restric
         const int ej = __shfl(end, j, 64);
         if (item < total) {
             int w[4];
-            load_quad(colidx, nnz, bj, ej, q, w);
+            load_quad(P.colidx, P.nnz, bj, ej, q, w);
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                if (w[k] >= 0 && w[k] != vj) push_colour(F, rowptr, w[k], cj, bytes, dirty);
+                if (w[k] >= 0 && w[k] != vj) push_colour(P, w[k], cj);
         }
     }
 }
+
+// Push context of a round (W: with wake flags).
+template <bool W>
+__device__ __forceinline__ PushCtx push_ctx(const RoundArgs& a) {
+    PushCtx P;
+    P.F = a.F;
+    P.rowptr = a.rowptr;
+    P.colidx = a.colidx;
+    P.nnz = a.nnz;
+    P.bytes = a.pushff == 2;
+    P.dirty = a.dirty;
+    P.X = a.X;
+    P.rflag = W ? a.rflag : nullptr;
+    P.all_tentative = false;
+    P.nbytes = nullptr;
+    return P;
+}
+template <bool W>
+__device__ __forceinline__ void push_row_coop(const RoundArgs& a, int v, int c, int beg, int end, int t,
+                                              int nthr) {
+    push_row_coop(push_ctx<W>(a), v, c, beg, end, t, nthr);
+}
+template <bool W>
 __device__ __forceinline__ void push_rows_wave(const RoundArgs& a, bool win, int v, int c, int beg, int end) {
-    push_rows_wave(a.F, a.rowptr, a.colidx, a.nnz, win, v, c, beg, end, a.pushff == 2, a.dirty);
+    push_rows_wave(push_ctx<W>(a), win, v, c, beg, end);
 }
 
 // Push-mode FirstFit for any bucket: one lane per vertex finds the first clear bit
@@ -707,9 +723,11 @@ __global__ __launch_bounds__(WG) void k_assign(RoundArgs a) {
 // the next FirstFit) and its id goes to the next worklist.
 // ---------------------------------------------------------------------------
 
+template <bool W>
 __device__ __forceinline__ void settle(const RoundArgs& a, int v, int cv, int& cmax) {
     a.X[v] = cv;
     a.out[v] = cv - 1;
+    if (W) a.srnd[v] = a.wround;           // wake flags: the settling round, for the statistics
     cmax = max(cmax, cv);
 }
 
@@ -761,7 +779,7 @@ __device__ __forceinline__ void push_losers(int v_l, bool lost_l, int* mybuf, in
     wc += __popcll(lm);
 }
 
-template <int L>
+template <int L, bool W>
 __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list, int lo, int hi, RoundLds& s,
                                              int* outl, int* cnt_out, int& cmax, unsigned long long* ust, int unit) {
     constexpr int V = 64 / L;
@@ -855,8 +873,8 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                if (v_l[u] >= 0 && !lost_l[u]) settle(a, v_l[u], cv_l[u], cmax);
-                if (a.pushff) push_rows_wave(a, v_l[u] >= 0 && !lost_l[u], v_l[u], cv_l[u], beg_l[u], end_l[u]);
+                if (v_l[u] >= 0 && !lost_l[u]) settle<W>(a, v_l[u], cv_l[u], cmax);
+                if (a.pushff) push_rows_wave<W>(a, v_l[u] >= 0 && !lost_l[u], v_l[u], cv_l[u], beg_l[u], end_l[u]);
                 push_losers(v_l[u], lost_l[u], mybuf, wc);
             }
         }
@@ -867,6 +885,7 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
 // Lane-per-vertex conflict test for the tile buckets: every lane walks the lower part
 // of its own row quad by quad and stops at its first conflict (or, for sorted rows,
 // at its first w >= v); the wavefront moves on when all its lanes have stopped.
+template <bool W>
 __device__ __forceinline__ void detect_lanes(const RoundArgs& a, const int* list, int lo, int hi, RoundLds& s,
                                              int* outl, int* cnt_out, int& cmax, unsigned long long* ust, int unit) {
     const int lane = __lane_id();
@@ -913,8 +932,8 @@ __device__ __forceinline__ void detect_lanes(const RoundArgs& a, const int* list
                 lost = true;
                 if (a.hint) a.hint[v_l] = found;
             }
-            if (v_l >= 0 && !lost) settle(a, v_l, cv, cmax);
-            if (a.pushff) push_rows_wave(a, v_l >= 0 && !lost, v_l, cv, beg, end);
+            if (v_l >= 0 && !lost) settle<W>(a, v_l, cv, cmax);
+            if (a.pushff) push_rows_wave<W>(a, v_l >= 0 && !lost, v_l, cv, beg, end);
             push_losers(v_l, lost, mybuf, wc);
         }
         flush_losers(s, wc, outl, cnt_out, ust, unit, &a.ctl->err);
@@ -1080,6 +1099,7 @@ __device__ __forceinline__ bool live_test_wg(const RoundArgs& a, int v, int cv, 
 // Wavefront bucket: metadata for 64 vertices at a time, then the wavefront scans the
 // lower part of one row at a time (256 arcs per step; for sorted rows the scan stops
 // at the first w >= v, and at the first conflict in any case).
+template <bool W>
 __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list, int lo, int hi, RoundLds& s,
                                             int* outl, int* cnt_out, int& cmax, unsigned long long* ust, int unit) {
     const int lane = __lane_id();
@@ -1137,14 +1157,15 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
                 }
                 if (lane == j) lost_l = lost;
             }
-            if (v_l >= 0 && !lost_l) settle(a, v_l, cv_l, cmax);
-            if (a.pushff) push_rows_wave(a, v_l >= 0 && !lost_l, v_l, cv_l, beg_l, end_l);
+            if (v_l >= 0 && !lost_l) settle<W>(a, v_l, cv_l, cmax);
+            if (a.pushff) push_rows_wave<W>(a, v_l >= 0 && !lost_l, v_l, cv_l, beg_l, end_l);
             push_losers(v_l, lost_l, mybuf, wc);
         }
         flush_losers(s, wc, outl, cnt_out, ust, unit, &a.ctl->err);
     }
 }
 
+template <bool W>
 __device__ __forceinline__ void detect_wg(const RoundArgs& a, const int* list, int cnt, RoundLds& s,
                                           int* outl, int* cnt_out, int& cmax) {
     for (;;) {
@@ -1192,10 +1213,10 @@ __device__ __forceinline__ void detect_wg(const RoundArgs& a, const int* list, i
                 const int p = atomicAdd(cnt_out, 1);
                 outl[p] = v;
             } else {
-                settle(a, v, cv, cmax);
+                settle<W>(a, v, cv, cmax);
             }
         }
-        if (a.pushff && !lost) push_row_coop(a, v, cv, beg, end, threadIdx.x, WG);
+        if (a.pushff && !lost) push_row_coop<W>(a, v, cv, beg, end, threadIdx.x, WG);
     }
 }
 
@@ -1203,6 +1224,7 @@ __device__ __forceinline__ void detect_wg(const RoundArgs& a, const int* list, i
 // sibling chunk already found a conflict, or when a sorted chunk starts at w >= v)
 // and ORs its verdict into the hub's lost flag; the chunk that completes the
 // finished-chunk count settles the hub or requeues it with a fresh chunk range.
+template <bool W>
 __device__ __forceinline__ void detect_split(const RoundArgs& a, const int* list, int nchunks, int j, int nbk,
                                              RoundLds& s, int* outl, int* cnt_out, int& cmax) {
     const int* cstart = a.cstart[a.par_in];
@@ -1283,7 +1305,7 @@ __device__ __forceinline__ void detect_split(const RoundArgs& a, const int* list
                     s.sh[2] = qn;
                     s.sh[3] = cs;
                 } else {
-                    settle(a, v, cv, cmax);
+                    settle<W>(a, v, cv, cmax);
                     s.sh[3] = a.settled ? atomicAdd(&a.ctl->nsettled, nch) : 0;
                 }
             }
@@ -1305,6 +1327,7 @@ __device__ __forceinline__ void detect_split(const RoundArgs& a, const int* list
 // Split bucket with live lists: the lists of a hub's chunks shrink quickly, so one
 // wavefront (not a workgroup) handles a chunk, four chunks per block at a time.  The
 // merge of the verdicts is that of detect_split, done by lane 0.
+template <bool W>
 __device__ __forceinline__ void detect_split_wave(const RoundArgs& a, const int* list, int nchunks, int j,
                                                   int nbk, int* outl, int* cnt_out, int& cmax) {
     const int* cstart = a.cstart[a.par_in];
@@ -1358,7 +1381,7 @@ __device__ __forceinline__ void detect_split_wave(const RoundArgs& a, const int*
                     outl[qn] = v;
                     cstart_out[qn] = cs;
                 } else {
-                    settle(a, v, cv, cmax);
+                    settle<W>(a, v, cv, cmax);
                     cs = a.settled ? atomicAdd(&a.ctl->nsettled, nch) : 0;
                 }
             }
@@ -1378,6 +1401,7 @@ __device__ __forceinline__ void detect_split_wave(const RoundArgs& a, const int*
 }
 
 // One conflict-test phase for the block `bid` of a grid partitioned by boff.
+template <bool W>
 __device__ __forceinline__ void detect_phase(const RoundArgs& a, RoundLds& s, int bid, const int* boff, int& cmax) {
     int b, j, nbk;
     block_bucket(boff, bid, b, j, nbk);
@@ -1387,7 +1411,9 @@ __device__ __forceinline__ void detect_phase(const RoundArgs& a, RoundLds& s, in
             tot += a.ctl->cnt[a.par_in][k];
             a.ctl->dyn[0][k] = 0;
         }
-        if (tot > 0) {
+        // with wake flags the conflict test marks the rounds that test a vertex
+        if (tot > 0 && W) a.ctl->rounds = a.wround;
+        if (tot > 0 && !W) {
             const int ridx = a.ctl->rounds;
             if (a.st_wsize && ridx < a.st_cap) a.st_wsize[ridx] = tot;
             a.ctl->rounds = ridx + 1;
@@ -1417,22 +1443,22 @@ __device__ __forceinline__ void detect_phase(const RoundArgs& a, RoundLds& s, in
         return;
     }
     if (b < NTILE && (a.lane_mode_detect >> b & 1)) {
-        detect_lanes(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j);
+        detect_lanes<W>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j);
     } else {
         switch (b) {
-            case 0: detect_tiles<2>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j); break;
-            case 1: detect_tiles<4>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j); break;
-            case 2: detect_tiles<8>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j); break;
-            case 3: detect_tiles<16>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j); break;
-            case 4: detect_wave(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j); break;
+            case 0: detect_tiles<2, W>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j); break;
+            case 1: detect_tiles<4, W>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j); break;
+            case 2: detect_tiles<8, W>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j); break;
+            case 3: detect_tiles<16, W>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j); break;
+            case 4: detect_wave<W>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j); break;
             case 5:
                 // with live lists a wavefront per vertex does (the lists shrink quickly)
-                if (a.live) detect_wave(a, list, lo, hi, s, outl, cnt_out, cmax, nullptr, 0);
-                else detect_wg(a, list, cnt, s, outl, cnt_out, cmax);
+                if (a.live) detect_wave<W>(a, list, lo, hi, s, outl, cnt_out, cmax, nullptr, 0);
+                else detect_wg<W>(a, list, cnt, s, outl, cnt_out, cmax);
                 break;
             default:
-                if (a.live) detect_split_wave(a, list, a.ctl->ccnt[a.par_in], j, nbk, outl, cnt_out, cmax);
-                else detect_split(a, list, a.ctl->ccnt[a.par_in], j, nbk, s, outl, cnt_out, cmax);
+                if (a.live) detect_split_wave<W>(a, list, a.ctl->ccnt[a.par_in], j, nbk, outl, cnt_out, cmax);
+                else detect_split<W>(a, list, a.ctl->ccnt[a.par_in], j, nbk, s, outl, cnt_out, cmax);
                 break;
         }
     }
@@ -1452,27 +1478,9 @@ __global__ void k_jp_prep(Ctl* ctl, int par_out, unsigned long long* lbs, int nl
         for (int i = k; i < nlbs; i += blockDim.x) lbs[i] = 0;
 }
 
-__global__ __launch_bounds__(WG, 6) void k_detect(RoundArgs a) {
-    __shared__ RoundLds s;
-    __shared__ int boff[NB + 1];
-    if (threadIdx.x == 0) {
-        if (a.dev_plan) {
-            int cnt[NB];
-            queue_sizes(a.ctl, a.par_in, cnt);
-            device_plan(cnt, gridDim.x, boff);
-        } else {
-            for (int k = 0; k <= NB; ++k) boff[k] = a.boff[k];
-        }
-    }
-    __syncthreads();
-    int cmax = 0;
-    detect_phase(a, s, blockIdx.x, boff, cmax);
-    cmax = block_max(cmax, s.red);
-    if (threadIdx.x == 0 && cmax > 0) atomicMax(&a.ctl->maxcolor, cmax);
-}
-
 // Push phase for the split bucket (push mode): every chunk of a hub that settled this
 // round pushes the hub's colour over the chunk's part of the row.
+template <bool W>
 __device__ __forceinline__ void push_split_phase(const RoundArgs& a, int j, int nbk) {
     const int* list = a.wl_in + a.seg[BSPLIT];
     if (a.settled) {
@@ -1484,7 +1492,7 @@ __device__ __forceinline__ void push_split_phase(const RoundArgs& a, int j, int 
             const int x = a.X[v];
             const int rb = a.rowptr[v], re = a.rowptr[v + 1];
             const int beg = rb + k * SPLIT_CH, end = min(beg + SPLIT_CH, re);
-            push_row_coop(a, v, x, beg, end, threadIdx.x, WG);
+            push_row_coop<W>(a, v, x, beg, end, threadIdx.x, WG);
         }
         return;
     }
@@ -1499,11 +1507,12 @@ __device__ __forceinline__ void push_split_phase(const RoundArgs& a, int j, int 
         const int k = t - cstart[p];
         const int rb = a.rowptr[v], re = a.rowptr[v + 1];
         const int beg = rb + k * SPLIT_CH, end = min(beg + SPLIT_CH, re);
-        push_row_coop(a, v, x, beg, end, threadIdx.x, WG);
+        push_row_coop<W>(a, v, x, beg, end, threadIdx.x, WG);
     }
 }
 
-__global__ __launch_bounds__(WG) void k_push(RoundArgs a) { push_split_phase(a, blockIdx.x, gridDim.x); }
+template <bool W>
+__global__ __launch_bounds__(WG) void k_push(RoundArgs a) { push_split_phase<W>(a, blockIdx.x, gridDim.x); }
 
 // ---------------------------------------------------------------------------
 // Persistent mode (the kernel fusion of Sec. 3.3): every round of a colouring in
@@ -1561,10 +1570,10 @@ __device__ __forceinline__ bool persistent_round(const RoundArgs& a, RoundLds& s
     }
     assign_phase(a, s, blockIdx.x, boff);
     grid_sync(a.ctl, gen);
-    detect_phase(a, s, blockIdx.x, boff, cmax);
+    detect_phase<false>(a, s, blockIdx.x, boff, cmax);
     grid_sync(a.ctl, gen);
     if (a.pushff && boff[BSPLIT + 1] > boff[BSPLIT]) {
-        push_split_phase(a, blockIdx.x, gridDim.x);
+        push_split_phase<false>(a, blockIdx.x, gridDim.x);
         grid_sync(a.ctl, gen);
     }
     return true;

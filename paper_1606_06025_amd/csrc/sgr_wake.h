@@ -1,0 +1,327 @@
+// Wake flags: the rounds of Sec. 3.1 (Algorithm Data-GC, id rule) without re-testing
+// the requeued vertices whose verdict cannot have changed.
+//
+// Under the id rule with conflict hints, a requeued vertex v remembers the neighbour h
+// that beat it: h < v, h uncoloured, with v's tentative colour.  Next round v loses to
+// h again unless one of the two tentative colours changed, and a tentative colour only
+// changes when a neighbour settles with exactly that colour (FirstFit's smallest free
+// colour moves only when that very colour becomes forbidden).  So each round:
+//   * a winner that pushes colour c to a neighbour u holding tentative colour c sets
+//     u's recolour flag;
+//   * FirstFit runs only over the vertices whose recolour flag is set; each of them
+//     gets its test flag, and so does every uncoloured higher neighbour w whose hint is
+//     the recoloured vertex;
+//   * the conflict test runs only over the vertices whose test flag is set; a loser
+//     records its hint and clears its flag (it sleeps), a winner settles and pushes.
+// Every sleeping vertex keeps its tentative colour and loses to its hint, the verdict
+// the full round would give, so the colouring and the rounds are those of the paper's
+// method.  If h settles, it pushes its colour (= v's) to v, so v is recoloured.
+// Waking reads the row of the recoloured vertex, so only short rows may hold sleepers:
+// a requeued vertex whose hint has more than WAKE_DEG arcs (the hint then carries FLAG)
+// is awake and keeps its test flag; a vertex of more than WAKE_DEG arcs never sleeps
+// and stays on the degree-bucket worklists of the classic rounds.
+//
+// The flags are bytes, one per vertex, written with plain stores (every writer stores
+// the same value), and each round's kernels find their vertices by a dense, coalesced
+// scan of the flag bytes: VPW vertices per wavefront, a few bytes per vertex and
+// round, instead of device-wide list counters whose atomics would serialise.
+#pragma once
+
+#include "sgr_device.h"
+#include "sgr_round.h"
+
+namespace csrcolor {
+
+constexpr int VPW = 256;   // most vertices per wavefront in the flag scans (4 per lane)
+
+// Smallest free colour of v from its push-mode flags: the first clear flag at or after
+// position rowptr[v] + v (flags before it count as set); one exists within deg(v) + 1.
+__device__ __forceinline__ int first_free(const RoundArgs& a, int beg, int v, int& words) {
+    const long long bit = (long long)beg + v;
+    long long pos;
+    long long k0;
+    if (a.pushff == 2) {
+        long long k = bit >> 2;
+        k0 = k;
+        unsigned w = a.F[k] | ((1u << (8 * (bit & 3))) - 1u);
+        unsigned z = (w - 0x01010101u) & ~w & 0x80808080u;
+        while (z == 0) {
+            w = a.F[++k];
+            z = (w - 0x01010101u) & ~w & 0x80808080u;
+        }
+        pos = k * 4 + (__ffs(z) - 1) / 8;
+        words = (int)(k - k0) + 1;
+    } else {
+        long long k = bit >> 5;
+        k0 = k;
+        unsigned w = a.F[k] | ((1u << (bit & 31)) - 1u);
+        while (w == 0xffffffffu) w = a.F[++k];
+        pos = k * 32 + __ffs(~w) - 1;
+        words = (int)(k - k0) + 1;
+    }
+    return (int)(pos - bit + 1);
+}
+
+// Flag bytes of the wavefront's vertices v0 .. v0 + 64k - 1, k (1, 2 or 4) per lane
+// (the arrays are padded with zeros to a whole number of VPW).
+__device__ __forceinline__ unsigned load_flags(const unsigned char* fl, long long v0, int k) {
+    const int lane = __lane_id();
+    if (k == 4) return reinterpret_cast<const unsigned*>(fl + v0)[lane];
+    if (k == 2) return reinterpret_cast<const unsigned short*>(fl + v0)[lane];
+    return fl[v0 + lane];
+}
+
+// Lists the vertices whose flag byte is set (lane l holds the bytes of vertices
+// v0 + kl .. v0 + kl + k - 1 in f) in ids, in id order; returns their number.  Every
+// lane must call.
+__device__ __forceinline__ int flag_compact(unsigned f, int v0, int k, int* ids) {
+    const int lane = __lane_id();
+    unsigned m = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (j < k && ((f >> (8 * j)) & 0xffu)) m |= 1u << j;
+    int tot;
+    int pos = wave_excl(__popc(m), tot);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (m >> j & 1) ids[pos++] = v0 + k * lane + j;
+    __builtin_amdgcn_wave_barrier();
+    return tot;
+}
+
+// The wavefront walks the rows of its recoloured vertices (lane l: row [beg, end) of
+// u when `on`; at most WAKE_DEG arcs) as one concatenation of 16-byte quads, like
+// push_rows_wave, and sets the test flag of every uncoloured neighbour w > u of at most
+// WAKE_DEG arcs whose hint is u (without FLAG: w sleeps).  Every lane must call.
+template <bool C>
+__device__ __forceinline__ void wake_children(const RoundArgs& a, bool on, int u, int beg, int end,
+                                              long long& nb) {
+    const int lane = __lane_id();
+    const int mis = (int)((reinterpret_cast<uintptr_t>(a.colidx) >> 2) & 3);
+    const int nq = on && end > beg ? (((end - 1 + mis) >> 2) - ((beg + mis) >> 2) + 1) : 0;
+    int incl = nq;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    const int total = __shfl(incl, 63, 64);
+    for (int base = 0; base < total; base += 64) {
+        const int item = base + lane;
+        int j = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            if (__shfl(incl, j + step - 1, 64) <= item) j += step;
+        }
+        const int q = item - (__shfl(incl, j, 64) - __shfl(nq, j, 64));
+        const int uj = __shfl(u, j, 64);
+        const int bj = __shfl(beg, j, 64);
+        const int ej = __shfl(end, j, 64);
+        if (item >= total) continue;
+        int w[4];
+        load_quad(a.colidx, a.nnz, bj, ej, q, w);
+        int h[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) h[k] = w[k] > uj ? a.hint[w[k]] : -1;
+        int x[4], wb[4], we[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool c = w[k] > uj && h[k] == uj;
+            x[k] = c ? a.X[w[k]] : 1;
+            wb[k] = c ? a.rowptr[w[k]] : 0;
+            we[k] = c ? a.rowptr[w[k] + 1] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (x[k] < 0 && we[k] - wb[k] <= WAKE_DEG) a.aflag[w[k]] = 1;
+        if (C) {
+            // colidx entries, hints of the higher ones, colour and rowptr pair of the
+            // sleepers' candidates, their test flags
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                nb += (w[k] >= 0 ? 4 : 0) + (w[k] > uj ? 4 : 0) + (h[k] == uj && w[k] > uj ? 12 : 0) +
+                      (x[k] < 0 && we[k] - wb[k] <= WAKE_DEG ? 1 : 0);
+        }
+    }
+}
+
+// FirstFit of a round with wake flags: every wavefront scans the recolour flags of its
+// vpw vertices, recolours the flagged ones, sets their test flags (short rows; longer
+// ones are on the worklists) and those of their sleepers.  Block 0 also clears the
+// worklist counters the conflict test of the round fills.
+template <bool C>
+__global__ __launch_bounds__(WG) void k_wassign(RoundArgs a) {
+    __shared__ int ids[WAVES][VPW];
+    const int lane = __lane_id();
+    const int wv = threadIdx.x >> 6;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int k = 0; k < NB; ++k) {
+            a.ctl->cnt[a.par_out][k] = 0;
+            a.ctl->dyn[1][k] = 0;
+        }
+        a.ctl->ccnt[a.par_out] = 0;
+        a.ctl->nsettled = 0;
+    }
+    const long long nwv = (long long)gridDim.x * WAVES;
+    const int k = a.vpw / 64;
+    long long nb = 0;          // bytes moved (counted only on request)
+    for (long long wid = (long long)blockIdx.x * WAVES + wv; wid * a.vpw < a.n; wid += nwv) {
+        const long long v0 = wid * a.vpw;
+        const int cnt = flag_compact(load_flags(a.rflag, v0, k), (int)v0, k, ids[wv]);
+        if (C) nb += k;
+        for (int i0 = 0; i0 < cnt; i0 += 64) {
+            const int i = i0 + lane;
+            const int u = i < cnt ? ids[wv][i] : -1;
+            int beg = 0, end = 0, x = 1;
+            if (u >= 0) {
+                beg = a.rowptr[u];
+                end = a.rowptr[u + 1];
+                x = a.X[u];
+                a.rflag[u] = 0;
+                if (C) nb += 13;
+            }
+            const bool on = x < 0;     // flagged vertices are uncoloured; kept as a guard
+            if (on) {
+                int words = 0;
+                a.X[u] = FLAG | first_free(a, beg, u, words);
+                if (C) nb += 4 * words + 4;
+            }
+            const bool small = on && end - beg <= WAKE_DEG;
+            if (small) {
+                a.aflag[u] = 1;
+                if (C) nb += 1;
+            }
+            wake_children<C>(a, small, u, beg, end, nb);
+        }
+    }
+    if (C) {
+        __shared__ long long red64[WAVES];
+        const long long t = block_sum64(nb, red64);
+        if (threadIdx.x == 0 && t) atomicAdd(&a.ubytes[0], (unsigned long long)t);
+    }
+}
+
+// Conflict test of the flagged vertices of one wavefront's range (ids, cnt; all of at
+// most WAKE_DEG arcs).  Their rows are walked as one concatenation of quads; a lower
+// neighbour with the same tentative colour requeues the vertex, and the largest such
+// neighbour becomes its hint (slot: per-vertex LDS verdicts).  A loser sleeps unless
+// its hint is long; a winner settles and pushes its colour.  Every lane must call.
+template <bool C>
+__device__ __forceinline__ void test_flagged(const RoundArgs& a, const int* ids, int cnt, int* slot, int& cmax,
+                                             long long& nb) {
+    const int lane = __lane_id();
+    PushCtx P = push_ctx<true>(a);
+    if (C) P.nbytes = &nb;
+    const int mis = (int)((reinterpret_cast<uintptr_t>(a.colidx) >> 2) & 3);
+    for (int i0 = 0; i0 < cnt; i0 += 64) {
+        const int i = i0 + lane;
+        int v = i < cnt ? ids[i] : -1;
+        int cv = 0, beg = 0, end = 0, hv = -1;
+        if (v >= 0) {
+            const int x = a.X[v];
+            hv = a.hint[v];
+            beg = a.rowptr[v];
+            end = a.rowptr[v + 1];
+            cv = x & CMASK;
+            if (x > 0) {               // guard: a flagged vertex is uncoloured
+                a.aflag[v] = 0;
+                v = -1;
+            }
+        }
+        // an awake vertex (long hint) usually still loses to it: then no row walk
+        const bool held = v >= 0 && hv < 0 && hv != -1 && (a.X[hv & CMASK] & CMASK) == cv;
+        if (C && v >= 0) nb += 16 + (hv < 0 && hv != -1 ? 4 : 0);   // colour, hint, rowptr pair, hint's colour
+        slot[lane] = held ? (hv & CMASK) : -1;
+        __builtin_amdgcn_wave_barrier();
+        const int nq = v >= 0 && !held && end > beg ? (((end - 1 + mis) >> 2) - ((beg + mis) >> 2) + 1) : 0;
+        int incl = nq;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += t;
+        }
+        const int total = __shfl(incl, 63, 64);
+        for (int base = 0; base < total; base += 64) {
+            const int item = base + lane;
+            int j = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1) {
+                if (__shfl(incl, j + step - 1, 64) <= item) j += step;
+            }
+            const int q = item - (__shfl(incl, j, 64) - __shfl(nq, j, 64));
+            const int vj = __shfl(v, j, 64);
+            const int cj = __shfl(cv, j, 64);
+            const int bj = __shfl(beg, j, 64);
+            const int ej = __shfl(end, j, 64);
+            if (item >= total) continue;
+            int w[4];
+            load_quad(a.colidx, a.nnz, bj, ej, q, w);
+            int x[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) x[k] = (w[k] >= 0 && w[k] < vj) ? a.X[w[k]] : 0;
+            int found = -1;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if ((x[k] & CMASK) == cj) found = max(found, w[k]);
+            if (found >= 0) atomicMax(&slot[j], found);
+            if (C) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) nb += (w[k] >= 0 ? 4 : 0) + (w[k] >= 0 && w[k] < vj ? 4 : 0);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int h = slot[lane];
+        const bool win = v >= 0 && h < 0;
+        if (v >= 0 && !held) {
+            if (h >= 0) {
+                const bool big = a.rowptr[h + 1] - a.rowptr[h] > WAKE_DEG;
+                a.hint[v] = big ? (h | FLAG) : h;
+                if (!big) a.aflag[v] = 0;          // asleep until woken
+                if (C) nb += 12 + (big ? 0 : 1);
+            } else {
+                settle<true>(a, v, cv, cmax);
+                a.aflag[v] = 0;
+                if (C) nb += 13;
+            }
+        }
+        push_rows_wave(P, win, v, cv, beg, end);
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Per-round statistics from the settling rounds: bins[s-1] += 1 and abins[s-1] +=
+// deg(v) for every vertex v that settled in round s <= cap (the caller turns them
+// into worklist sizes and arcs).  Rounds up to HROUNDS are first summed in LDS per
+// block (one device atomic per block and round), later ones directly.
+constexpr int HROUNDS = 1024;
+__global__ __launch_bounds__(WG) void k_round_hist(int n, const int* __restrict__ rowptr, const int* srnd,
+                                                   long long* bins, long long* abins, int cap) {
+    __shared__ unsigned hb[HROUNDS];
+    __shared__ unsigned long long ha[HROUNDS];
+    for (int i = threadIdx.x; i < HROUNDS; i += WG) {
+        hb[i] = 0;
+        ha[i] = 0;
+    }
+    __syncthreads();
+    for (long long v = (long long)blockIdx.x * WG + threadIdx.x; v < n; v += (long long)gridDim.x * WG) {
+        const int s = srnd[v];
+        if (s < 1 || s > cap) continue;
+        const unsigned long long d = (unsigned long long)(rowptr[v + 1] - rowptr[v]);
+        if (s <= HROUNDS) {
+            atomicAdd(&hb[s - 1], 1u);
+            atomicAdd(&ha[s - 1], d);
+        } else {
+            atomicAdd((unsigned long long*)&bins[s - 1], 1ull);
+            atomicAdd((unsigned long long*)&abins[s - 1], d);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < HROUNDS && i < cap; i += WG) {
+        if (hb[i]) {
+            atomicAdd((unsigned long long*)&bins[i], (unsigned long long)hb[i]);
+            atomicAdd((unsigned long long*)&abins[i], ha[i]);
+        }
+    }
+}
+
+}  // namespace csrcolor

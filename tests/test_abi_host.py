@@ -81,6 +81,8 @@ def test_algorithm_option_errors_without_device_work(lib):
     assert ex(opts(hints=-2)) == L.EINVAL
     assert ex(opts(live_lists=2)) == L.EINVAL
     assert ex(opts(ordered=-3)) == L.EINVAL
+    assert ex(opts(wake=2)) == L.EINVAL
+    assert ex(opts(wake=-2)) == L.EINVAL
     for algo in (L.ALGO_SGR_TOPO, L.ALGO_JP):
         for mode in (L.MODE_PERSISTENT, L.MODE_GRAPH):
             assert ex(opts(algorithm=algo, mode=mode)) == L.EINVAL
@@ -100,9 +102,10 @@ def _header_struct_fields(name):
 
 
 def test_struct_layouts_match_header():
-    # csrcolor_opts: 16 x 32-bit fields (10 options, algorithm, two seed halves, hints, live lists, ordered)
-    # csrcolor_stats: 4 int32, int64, 2 int32, 2 pointers, 3 double, 2 int32
-    assert ctypes.sizeof(L.Opts) == 16 * 4
-    assert ctypes.sizeof(L.Stats) == 4 * 4 + 8 + 2 * 4 + 2 * 8 + 3 * 8 + 2 * 4
+    # csrcolor_opts: 17 x 32-bit fields (10 options, algorithm, two seed halves, hints, live lists, ordered,
+    # wake lists)
+    # csrcolor_stats: 4 int32, int64, 2 int32, 2 pointers, 3 double, 2 int32, a pointer
+    assert ctypes.sizeof(L.Opts) == 17 * 4
+    assert ctypes.sizeof(L.Stats) == 4 * 4 + 8 + 2 * 4 + 2 * 8 + 3 * 8 + 2 * 4 + 8
     assert _header_struct_fields("csrcolor_opts") == [f[0] for f in L.Opts._fields_]
     assert _header_struct_fields("csrcolor_stats") == [f[0] for f in L.Stats._fields_]

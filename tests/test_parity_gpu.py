@@ -123,7 +123,8 @@ def test_mixed_stencils(dev):
 @pytest.mark.parametrize("kw", [dict(t_wave=61), dict(t_wave=64), dict(t_wave=200),
                                 dict(blocks_per_cu=1), dict(blocks_per_cu=3), dict(sync_every=1),
                                 dict(sync_every=5), dict(t_wave=70, blocks_per_cu=2, sync_every=3),
-                                dict(hints=-1), dict(hints=1, lane_detect=-1), dict(hints=-1, lane_detect=-1)])
+                                dict(hints=-1), dict(hints=1, lane_detect=-1), dict(hints=-1, lane_detect=-1),
+                                dict(wake=-1), dict(wake=1, lane_detect=-1), dict(wake=1, firstfit=2)])
 def test_launch_options_do_not_change_result(dev, kw):
     import oracle
     g = gg.rmat(13, 16, 9)
@@ -402,6 +403,45 @@ def test_live_lists_on_and_off(dev, live, mode):
     for g in graphs:
         _assert_parity(g, dev, mode=mode, live_lists=live)
         _assert_parity(g, dev, mode=mode, live_lists=live, hints=-1, t_wave=128, t_split=1024)
+
+
+@pytest.mark.parametrize("wake", [-1, 1])
+@pytest.mark.parametrize("live", [-1, 1])
+def test_wake_lists_on_and_off(dev, wake, live):
+    """A requeued vertex may be left untested until its colour or that of its conflict
+    hint changes; on or off, with live lists on or off, bit or byte flags, every bucket
+    (tiles, lanes, wavefront, workgroup, split rows), sorted or unsorted rows, the
+    colouring, the rounds and the per-round worklist sizes are the oracle's."""
+    graphs = [gg.stencil27(24, 20, 16), gg.rmat(14, 16, 12), gg.complete(300),
+              _degree_ladder([5, 13, 29, 61, 62, 300, 1024, 1025, 2500, 9000], 7),
+              gg.star(3000, [i for i in range(6001) if i != 3000]),
+              gg.shuffle_rows(gg.erdos_renyi(20000, 200000, 8), 4), gg.cycle(1001)]
+    for g in graphs:
+        _assert_parity(g, dev, wake=wake, live_lists=live)
+        _assert_parity(g, dev, wake=wake, live_lists=live, firstfit=2, lane_detect=-1, t_wave=128, t_split=1024)
+
+
+def test_wake_lists_repeated_entries(dev):
+    """Rows that repeat an entry (sorted or not, with self-loops) would let a recoloured
+    vertex wake the same sleeper twice; the colouring and the statistics stay the
+    oracle's."""
+    base = gg.stencil27(12, 11, 10)
+    for shuffle in (False, True):
+        rows = []
+        for v in range(base.n):
+            r = base.colidx[base.rowptr[v]:base.rowptr[v + 1]].tolist()
+            r = sorted(r + r[::3] + [v])
+            rows.append(r[::-1] if shuffle else r)
+        _assert_parity(gg.raw_csr(base.n, rows), dev)
+
+
+def test_wake_lists_workspace_reuse(dev):
+    """Consecutive runs of different sizes share the stamps and recolour lists of the
+    workspace: stale entries of an earlier run must never be taken for this one's."""
+    seq = [gg.stencil27(20, 20, 20), gg.rmat(13, 16, 3), gg.stencil27(9, 8, 7), gg.erdos_renyi(5000, 40000, 2),
+           gg.stencil27(20, 20, 20)]
+    for g in seq:
+        _assert_parity(g, dev)
 
 
 def test_live_lists_workspace_reuse(dev):
