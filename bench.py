@@ -474,7 +474,7 @@ def main() -> int:
     ap.add_argument("--rule", type=int, default=0, help="conflict rule: 0 = higher id, 1 = smaller degree requeued")
     ap.add_argument("--hints", type=int, default=0, help="conflict hints: 0 = default (on), -1 = off")
     ap.add_argument("--live-lists", type=int, default=0, help="live lists: 0 = default (on), -1 = off")
-    ap.add_argument("--wake", type=int, default=0, help="wake lists: 0 = default (on), -1 = off")
+    ap.add_argument("--wake", type=int, default=0, help="wake flags: 0 = default (auto), 1 = on, -1 = off")
     ap.add_argument("--ordered", type=int, default=0, help="ordered worklist compaction: 0 = default (off), 1 = on")
     ap.add_argument("--jp-seed", type=int, default=1)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",

@@ -124,10 +124,11 @@ typedef struct {
     int32_t ordered;        /* 0: default (off); 1: on; -1: off.  Order-preserving worklist compaction: blocks
                                take tickets and place their losers after those of lower tickets (look-back
                                prefix), so every worklist keeps ascending id order (same colouring) */
-    int32_t wake;           /* 0: default (on); 1: on; -1: off.  Wake lists (id rule, push FirstFit, hints on,
-                               LOOP mode, unordered compaction): a requeued vertex is tested again only once its
-                               tentative colour or that of the neighbour that requeued it has changed; every
-                               other one loses again without being read (same colouring and rounds) */
+    int32_t wake;           /* 0: default (auto: on when rows longer than 61 arcs hold under a tenth of the
+                               arcs); 1: on; -1: off.  Wake flags (id rule, push FirstFit, hints on, LOOP mode,
+                               unordered compaction): a requeued vertex is tested again only once its tentative
+                               colour or that of the neighbour that requeued it has changed; every other one
+                               loses again without being read (same colouring and rounds) */
 } csrcolor_opts;
 
 /* Optional run statistics (HOST struct).  Set `cap`, `time_kernels` and the array

@@ -323,7 +323,9 @@ struct Options {
     int hints = 1;            // conflict hints (id rule)
     int live = 1;             // live lists for degree > 61 (id rule)
     int ordered = 0;          // order-preserving worklist compaction (measured slower on the stencil)
-    int wake = 1;             // wake lists (id rule, push FirstFit, hints, LOOP mode, unordered)
+    int wake = 0;             // wake flags: 0 auto (on when rows longer than 61 arcs hold under a
+                              // tenth of the arcs), 1 on, -1 off (id rule, push FirstFit, hints,
+                              // LOOP mode, unordered compaction)
     int rule = 0;             // conflict rule (csrcolor_rule)
     int algo = CSRCOLOR_ALGO_SGR;
     unsigned long long seed = 0;
@@ -360,7 +362,7 @@ Options parse_opts(const csrcolor_opts* o) {
     if (o->hints) r.hints = o->hints > 0;
     if (o->live_lists) r.live = o->live_lists > 0;
     if (o->ordered) r.ordered = o->ordered > 0;
-    if (o->wake) r.wake = o->wake > 0;
+    r.wake = o->wake;
     r.rule = o->rule;
     r.algo = o->algorithm;
     r.seed = ((unsigned long long)o->seed_hi << 32) | o->seed_lo;
@@ -689,7 +691,10 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     int* hint = (J.opt.hints && J.opt.rule == 0) ? w->hint : nullptr;
     // wake flags need the id rule's hints, push FirstFit and the host loop; ordered
     // compaction is a property of the full worklists they replace
-    const bool use_wake = J.opt.wake && hint && J.opt.pushff && J.opt.algo == CSRCOLOR_ALGO_SGR &&
+    // auto: the sleeping vertices are the short ones; where long rows hold most arcs the
+    // full worklist rounds measured faster (R-MAT: 66 vs 78 ms at scale 23)
+    const bool wake_wanted = J.opt.wake > 0 || (J.opt.wake == 0 && w->ctl_h->bigarcs * 10 < w->ctl_h->nnz);
+    const bool use_wake = wake_wanted && hint && J.opt.pushff && J.opt.algo == CSRCOLOR_ALGO_SGR &&
                           J.opt.mode == CSRCOLOR_MODE_LOOP && !J.opt.ordered;
     J.wake = use_wake;
     if (use_wake) {

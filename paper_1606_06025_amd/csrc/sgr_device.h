@@ -148,6 +148,7 @@ struct Ctl {
     int tk1;            // ordered compaction: round-1 tickets
     int nsettled;       // push tasks (split row, chunk) of the rows that settled this round
     int pad[2];
+    long long bigarcs;  // arcs of the rows longer than WAKE_DEG
     // device-wide barrier of the persistent mode, each counter on its own 128-byte line
     int bar[8][32];
     int bar_top[32];

@@ -29,12 +29,14 @@ __global__ __launch_bounds__(WG) void k_validate_rows(int n, const int* __restri
     int mydeg = 0;
     int hist[NB] = {};
     int bad = 0, desc = 0, chunks = 0;
+    long long big = 0;
     for (long long v = (long long)blockIdx.x * WG + threadIdx.x; v < n; v += (long long)gridDim.x * WG) {
         const int beg = rowptr[v], end = rowptr[v + 1];
         const bool ok = beg >= 0 && beg <= end && end <= nnz && (v != 0 || beg == 0);
         if (!ok) { bad = 1; continue; }
         const int deg = end - beg;
         mydeg = max(mydeg, deg);
+        if (deg > WAKE_DEG) big += deg;
         if (deg > 0) {
             const int bk = bucket_of(deg, twave, tsplit);
             if (bk == BSPLIT) chunks += split_chunks(deg);
@@ -49,11 +51,14 @@ __global__ __launch_bounds__(WG) void k_validate_rows(int n, const int* __restri
     mydeg = block_max(mydeg, red);
     desc = block_sum(desc, red);
     chunks = block_sum(chunks, red);
+    __shared__ long long red64[WAVES];
+    big = block_sum64(big, red64);
 #pragma unroll
     for (int b = 0; b < NB; ++b) hist[b] = block_sum(hist[b], red);
     if (threadIdx.x == 0) {
         if (bad) atomicOr(&ctl->err, 1);
         if (chunks) atomicAdd(&ctl->hchunks, chunks);
+        if (big) atomicAdd((unsigned long long*)&ctl->bigarcs, (unsigned long long)big);
         if (mydeg) atomicMax(&ctl->maxdeg, mydeg);
         if (desc) atomicAdd(&ctl->desc_bound, desc);
 #pragma unroll
@@ -267,18 +272,18 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
 }
 
 
-// Flag-scanning conflict test of the vertices of at most WAKE_DEG arcs for the
-// wavefronts of blocks [0, nblk): every wavefront scans the test flags of its vpw
+// Flag-scanning conflict test of the vertices of at most WAKE_DEG arcs, run by block
+// bid of nblk such blocks: every wavefront scans the test flags of its vpw
 // vertices and tests the flagged ones.  A wavefront that tests a vertex stores the
 // round number (every writer stores the same).
 template <bool C>
-__device__ __forceinline__ void detect_flags_phase(const RoundArgs& a, int* ids, int* slot, int nblk, int& cmax,
-                                                   long long* red64) {
+__device__ __forceinline__ void detect_flags_phase(const RoundArgs& a, int* ids, int* slot, int bid, int nblk,
+                                                   int& cmax, long long* red64) {
     long long nb = 0;          // bytes moved (counted only on request)
     bool any = false;
     const long long nwv = (long long)nblk * WAVES;
     const int k = a.vpw / 64;
-    for (long long wid = (long long)blockIdx.x * WAVES + (threadIdx.x >> 6); wid * a.vpw < a.n; wid += nwv) {
+    for (long long wid = (long long)bid * WAVES + (threadIdx.x >> 6); wid * a.vpw < a.n; wid += nwv) {
         const long long v0 = wid * a.vpw;
         const int cnt = flag_compact(load_flags(a.aflag, v0, k), (int)v0, k, ids);
         if (C) nb += k;
@@ -295,20 +300,23 @@ __device__ __forceinline__ void detect_flags_phase(const RoundArgs& a, int* ids,
 }
 
 // Conflict test of a round (Sec. 3, ConflictResolve; see detect_phase), one launch for
-// every degree bucket.  With wake flags (W) the first gdense blocks run the flag scan
-// of the vertices of at most WAKE_DEG arcs and the others the worklists of the longer
-// ones (k_detect_flags alone serves graphs without longer rows).
+// every degree bucket.  With wake flags (W) the last gdense blocks run the flag scan of
+// the vertices of at most WAKE_DEG arcs and the others, dispatched first because their
+// long rows take longest, the worklists of the longer ones (k_detect_flags alone serves
+// graphs without longer rows).
 template <bool W>
 __global__ __launch_bounds__(WG, W ? 5 : 6) void k_detect(RoundArgs a) {
     __shared__ RoundLds s;
     __shared__ int boff[NB + 1];
     int cmax = 0;
-    if (W && (int)blockIdx.x < a.gdense) {
+    const int nlist = (int)gridDim.x - (W ? a.gdense : 0);
+    if (W && (int)blockIdx.x >= nlist) {
         const int wv = threadIdx.x >> 6;
-        detect_flags_phase<false>(a, s.lbuf + wv * WAVE_CAP, s.res + wv * 64, a.gdense, cmax, s.red64);
+        detect_flags_phase<false>(a, s.lbuf + wv * WAVE_CAP, s.res + wv * 64, (int)blockIdx.x - nlist,
+                                  a.gdense, cmax, s.red64);
     } else {
-        const int bid = W ? (int)blockIdx.x - a.gdense : (int)blockIdx.x;
-        const int nblk = W ? (int)gridDim.x - a.gdense : (int)gridDim.x;
+        const int bid = (int)blockIdx.x;
+        const int nblk = nlist;
         if (threadIdx.x == 0) {
             if (a.dev_plan) {
                 int cnt[NB];
@@ -336,7 +344,7 @@ __global__ __launch_bounds__(WG) void k_detect_flags(RoundArgs a) {
     __shared__ long long red64[WAVES];
     const int wv = threadIdx.x >> 6;
     int cmax = 0;
-    detect_flags_phase<C>(a, ids[wv], slot[wv], gridDim.x, cmax, red64);
+    detect_flags_phase<C>(a, ids[wv], slot[wv], blockIdx.x, gridDim.x, cmax, red64);
     cmax = block_max(cmax, red);
     if (threadIdx.x == 0 && cmax > ld_agent(&a.ctl->maxcolor)) atomicMax(&a.ctl->maxcolor, cmax);
 }
