@@ -45,6 +45,8 @@ struct Workspace {
     size_t lb_cap = 0;
     Ctl* ctl = nullptr;          // device control block
     Ctl* ctl_h = nullptr;        // pinned host mirror
+    Ctl* ctl_h2 = nullptr;       // second pinned mirror: read-backs that overlap the next rounds
+    hipEvent_t pev[2] = {nullptr, nullptr};
     int st_cap = 0;
     long long* st_wsize = nullptr;
     long long* st_arcs = nullptr;
@@ -475,7 +477,8 @@ int drive_loop(Workspace* w, Job& J, RoundArgs& a, int ub[NB], int budget, KTime
 // device-side partition) and, when split rows exist, their push phase.  The conflict
 // test stores the round number when it tests a vertex; a round that tests none means
 // every vertex is settled (the lowest uncoloured vertex is always tested).  That is
-// read back every few rounds; rounds launched past the end do nothing.
+// read back after every batch of rounds, one batch behind; rounds launched past the end
+// do nothing.
 int drive_wake(Workspace* w, Job& J, RoundArgs& a, int budget, bool big, int nhub, int nchunk, KTimer& T) {
     hipStream_t st = w->stream;
     a.dev_plan = 1;
@@ -484,10 +487,18 @@ int drive_wake(Workspace* w, Job& J, RoundArgs& a, int budget, bool big, int nhu
     const long long scans = ((long long)J.n + (long long)a.vpw * WAVES - 1) / ((long long)a.vpw * WAVES);
     a.gdense = (int)std::max<long long>(1, std::min<long long>(scans, 4LL * budget));
     const int pgrid = std::max(std::min(nchunk, budget), 1);
+    if (!w->ctl_h2) {
+        if (hipHostMalloc(&w->ctl_h2, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return CSRCOLOR_ENOMEM;
+        for (int i = 0; i < 2; ++i) HIP_TRY(hipEventCreateWithFlags(&w->pev[i], hipEventDisableTiming));
+    }
+    Ctl* mir[2] = {w->ctl_h, w->ctl_h2};
+    long long rend[2] = {0, 0};
     int par = 1;             // parity of the worklists of the next round
     long long r = 2;         // next round (round 1 was k_round1)
     int k = 2;
-    for (;;) {
+    // batches of k rounds; the control block after batch b is copied back behind it and
+    // read while batch b+1 runs, so the stream never waits for the host
+    for (int b = 0;; ++b) {
         for (int i = 0; i < k; ++i) {
             a.par_in = par;
             a.par_out = par ^ 1;
@@ -515,11 +526,22 @@ int drive_wake(Workspace* w, Job& J, RoundArgs& a, int budget, bool big, int nhu
             ++r;
         }
         HIP_TRY(hipGetLastError());
-        int rc = read_ctl(w);
-        if (rc) return rc;
-        if (w->ctl_h->err) return CSRCOLOR_EHIP;
-        if (w->ctl_h->rounds < r - 1) break;
-        if (r > (long long)J.n + 2) return CSRCOLOR_ELIMIT;
+        rend[b & 1] = r - 1;
+        HIP_TRY(hipMemcpyAsync(mir[b & 1], w->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipEventRecord(w->pev[b & 1], st));
+        if (b > 0) {
+            const int p = (b - 1) & 1;
+            HIP_TRY(hipEventSynchronize(w->pev[p]));
+            if (mir[p]->err) {
+                (void)hipStreamSynchronize(st);
+                return CSRCOLOR_EHIP;
+            }
+            if (mir[p]->rounds < rend[p]) break;    // the batch in flight only finds empty flags
+            if (rend[p] > (long long)J.n + 2) {      // a colouring takes at most n rounds
+                (void)hipStreamSynchronize(st);
+                return CSRCOLOR_ELIMIT;
+            }
+        }
         k = std::min(k * 2, J.opt.sync_every);
     }
     return CSRCOLOR_OK;
@@ -780,6 +802,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
         a.rflag = w->rflag;
         a.aflag = w->aflag;
         a.srnd = w->srnd;
+        a.hflag = FLAG;
         if (J.stats && J.stats->kernel_bytes) {
             k_fill<<<1, 64, 0, st>>>(reinterpret_cast<int*>(w->ubytes), 4, 0);
             a.ubytes = w->ubytes;
@@ -1123,6 +1146,9 @@ void csrcolor_release_workspace(void) {
         if (w->ctl) (void)hipFree(w->ctl);
         if (w->ubytes) (void)hipFree(w->ubytes);
         if (w->ctl_h) (void)hipHostFree(w->ctl_h);
+        if (w->ctl_h2) (void)hipHostFree(w->ctl_h2);
+        for (int i = 0; i < 2; ++i)
+            if (w->pev[i]) (void)hipEventDestroy(w->pev[i]);
         if (w->st_wsize) (void)hipFree(w->st_wsize);
         if (w->st_arcs) (void)hipFree(w->st_arcs);
         if (w->gexec) (void)hipGraphExecDestroy(w->gexec);

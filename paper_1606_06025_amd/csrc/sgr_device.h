@@ -76,6 +76,7 @@ struct PushCtx {
     unsigned char* rflag;
     bool all_tentative;           // round 1: every neighbour of a winner holds colour 1
     long long* nbytes;            // nullptr, or the calling thread's count of bytes moved
+    bool loaded;                  // the colidx entries were already read (not counted again)
 };
 
 // Marks colour c among the forbidden colours of neighbour u (push-mode FirstFit).
@@ -93,7 +94,7 @@ __device__ __forceinline__ void push_colour(const PushCtx& P, int u, int c) {
     const int ub = P.rowptr[u];
     const int ue = P.rowptr[u + 1];
     const int xu = (P.rflag && !P.all_tentative) ? P.X[u] : (FLAG | c);
-    if (P.nbytes) *P.nbytes += 12 + (P.rflag && !P.all_tentative ? 4 : 0);   // colidx entry, rowptr pair, colour
+    if (P.nbytes) *P.nbytes += (P.loaded ? 8 : 12) + (P.rflag && !P.all_tentative ? 4 : 0);   // colidx entry, rowptr pair, colour
     if (xu > 0) return;
     if (P.nbytes) *P.nbytes += (c - 1 <= ue - ub ? 1 : 0) + (P.rflag && xu == (FLAG | c) ? 1 : 0);
     if (c - 1 <= ue - ub) {
@@ -224,6 +225,7 @@ struct RoundArgs {
     unsigned char* rflag;
     unsigned char* aflag;
     int* srnd;
+    int hflag;          // FLAG with wake flags (a long row's hint never names it a sleeper), else 0
     int gdense;         // blocks of the flag-scanning grids
     int vpw;            // vertices per wavefront in the flag scans (64, 128 or 256)
     // nullptr, or bytes moved (algorithmic, each element at its size) by the recolouring

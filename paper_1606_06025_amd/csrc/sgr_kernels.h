@@ -143,6 +143,7 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
     P.rflag = rflag;
     P.all_tentative = true;
     P.nbytes = nullptr;
+    P.loaded = false;
     // SGR: this is round 1.  JP: this only builds W_1 (every vertex with a neighbour;
     // an isolated vertex is alone in its neighbourhood and takes colour 1 here), and
     // the conflict-test launches count the rounds.
@@ -185,14 +186,20 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
                     }
                 }
             }
-            if (lose && hint) {
-                if (rflag && end - beg <= WAKE_DEG) {
+            if (hint && rflag) {
+                // wake flags: the hint of a short loser names its class, a long loser's hint
+                // carries FLAG, a winner's is cleared: a hint without FLAG names a sleeper
+                if (!lose) {
+                    hint[v] = -1;
+                } else if (end - beg <= WAKE_DEG) {
                     const bool big = rowptr[by + 1] - rowptr[by] > WAKE_DEG;
                     hint[v] = big ? (by | FLAG) : by;
                     aflag[v] = big;
                 } else {
-                    hint[v] = by;
+                    hint[v] = by | FLAG;
                 }
+            } else if (lose && hint) {
+                hint[v] = by;
             }
             if (lose) {
                 X[v] = jp ? 0 : (FLAG | 1);
@@ -343,6 +350,7 @@ __global__ __launch_bounds__(WG) void k_detect_flags(RoundArgs a) {
     __shared__ int red[WAVES];
     __shared__ long long red64[WAVES];
     const int wv = threadIdx.x >> 6;
+    if (a.ctl->rounds < a.wround - 1) return;    // past the end of the colouring
     int cmax = 0;
     detect_flags_phase<C>(a, ids[wv], slot[wv], blockIdx.x, gridDim.x, cmax, red64);
     cmax = block_max(cmax, red);

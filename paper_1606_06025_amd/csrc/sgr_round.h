@@ -205,6 +205,7 @@ __device__ __forceinline__ PushCtx push_ctx(const RoundArgs& a) {
     P.rflag = W ? a.rflag : nullptr;
     P.all_tentative = false;
     P.nbytes = nullptr;
+    P.loaded = false;
     return P;
 }
 template <bool W>
@@ -862,7 +863,7 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
                     if (loses_to(a, w[k], v, cv, end - beg)) found = w[k];
-                if (found >= 0 && a.hint) a.hint[v] = found;    // any conflicting neighbour will do
+                if (found >= 0 && a.hint) a.hint[v] = found | a.hflag;    // any conflicting neighbour will do
                 const bool lost = ((__ballot(found >= 0) >> gshift) & gmask) != 0;
                 if (q == 0 && real) res2[e] = lost;
             }
@@ -930,7 +931,7 @@ __device__ __forceinline__ void detect_lanes(const RoundArgs& a, const int* list
             }
             if (found >= 0) {
                 lost = true;
-                if (a.hint) a.hint[v_l] = found;
+                if (a.hint) a.hint[v_l] = found | a.hflag;
             }
             if (v_l >= 0 && !lost) settle<W>(a, v_l, cv, cmax);
             if (a.pushff) push_rows_wave<W>(a, v_l >= 0 && !lost, v_l, cv, beg, end);
@@ -974,7 +975,7 @@ __device__ __forceinline__ void live_step(const RoundArgs& a, const int* src, in
     }
     if (found >= 0) {
         hit = true;
-        if (a.hint) a.hint[v] = found;     // any conflicting neighbour will do
+        if (a.hint) a.hint[v] = found | a.hflag;     // any conflicting neighbour will do
     }
 }
 
@@ -1148,7 +1149,7 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
                         if (loses_to(a, w[k], v, cv, end - beg)) found = w[k];
                         stop |= a.sorted && a.rule == 0 && w[k] >= v;
                     }
-                    if (found >= 0 && a.hint) a.hint[v] = found;   // any conflicting neighbour will do
+                    if (found >= 0 && a.hint) a.hint[v] = found | a.hflag;   // any conflicting neighbour will do
                     if (__ballot(found >= 0)) {
                         lost = true;
                         break;
@@ -1196,7 +1197,7 @@ __device__ __forceinline__ void detect_wg(const RoundArgs& a, const int* list, i
             for (int k = 0; k < 4; ++k) {
                 if (loses_to(a, w[k], v, cv, end - beg)) {
                     hit = true;
-                    if (a.hint) a.hint[v] = w[k];
+                    if (a.hint) a.hint[v] = w[k] | a.hflag;
                 }
                 stop |= a.sorted && a.rule == 0 && w[k] >= v;
             }
@@ -1278,7 +1279,7 @@ __device__ __forceinline__ void detect_split(const RoundArgs& a, const int* list
                 for (int kk = 0; kk < 4; ++kk) {
                     if (loses_to(a, w[kk], v, cv, re - rb)) {
                         hit = true;
-                        if (a.hint) a.hint[v] = w[kk];
+                        if (a.hint) a.hint[v] = w[kk] | a.hflag;
                     }
                 }
             }

@@ -91,8 +91,8 @@ __device__ __forceinline__ int flag_compact(unsigned f, int v0, int k, int* ids)
 
 // The wavefront walks the rows of its recoloured vertices (lane l: row [beg, end) of
 // u when `on`; at most WAKE_DEG arcs) as one concatenation of 16-byte quads, like
-// push_rows_wave, and sets the test flag of every uncoloured neighbour w > u of at most
-// WAKE_DEG arcs whose hint is u (without FLAG: w sleeps).  Every lane must call.
+// push_rows_wave, and sets the test flag of every neighbour w > u whose hint is u
+// (without FLAG: w sleeps).  Every lane must call.
 template <bool C>
 __device__ __forceinline__ void wake_children(const RoundArgs& a, bool on, int u, int beg, int end,
                                               long long& nb) {
@@ -123,24 +123,16 @@ __device__ __forceinline__ void wake_children(const RoundArgs& a, bool on, int u
         int h[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) h[k] = w[k] > uj ? a.hint[w[k]] : -1;
-        int x[4], wb[4], we[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const bool c = w[k] > uj && h[k] == uj;
-            x[k] = c ? a.X[w[k]] : 1;
-            wb[k] = c ? a.rowptr[w[k]] : 0;
-            we[k] = c ? a.rowptr[w[k] + 1] : 0;
-        }
+        // a hint equal to u (no FLAG) is held only by an uncoloured vertex of at most
+        // WAKE_DEG arcs: settling clears a hint and long rows' hints carry FLAG
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (x[k] < 0 && we[k] - wb[k] <= WAKE_DEG) a.aflag[w[k]] = 1;
+            if (w[k] > uj && h[k] == uj) a.aflag[w[k]] = 1;
         if (C) {
-            // colidx entries, hints of the higher ones, colour and rowptr pair of the
-            // sleepers' candidates, their test flags
+            // colidx entries, hints of the higher ones, the sleepers' test flags
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                nb += (w[k] >= 0 ? 4 : 0) + (w[k] > uj ? 4 : 0) + (h[k] == uj && w[k] > uj ? 12 : 0) +
-                      (x[k] < 0 && we[k] - wb[k] <= WAKE_DEG ? 1 : 0);
+                nb += (w[k] >= 0 ? 4 : 0) + (w[k] > uj ? 4 : 0) + (w[k] > uj && h[k] == uj ? 1 : 0);
         }
     }
 }
@@ -154,6 +146,9 @@ __global__ __launch_bounds__(WG) void k_wassign(RoundArgs a) {
     __shared__ int ids[WAVES][VPW];
     const int lane = __lane_id();
     const int wv = threadIdx.x >> 6;
+    // a previous round that tested nothing ended the colouring: rounds launched past the
+    // end return at once
+    if (a.ctl->rounds < a.wround - 1) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         for (int k = 0; k < NB; ++k) {
             a.ctl->cnt[a.par_out][k] = 0;
@@ -241,20 +236,23 @@ __device__ __forceinline__ void test_flagged(const RoundArgs& a, const int* ids,
             if (lane >= off) incl += t;
         }
         const int total = __shfl(incl, 63, 64);
+        // the quads of the last pass stay in registers: when one pass covers every row,
+        // the winners push from them without reading their rows again
+        int w[4] = {-1, -1, -1, -1};
+        int j = 0, vj = -1, cj = 0;
         for (int base = 0; base < total; base += 64) {
             const int item = base + lane;
-            int j = 0;
+            j = 0;
 #pragma unroll
             for (int step = 32; step >= 1; step >>= 1) {
                 if (__shfl(incl, j + step - 1, 64) <= item) j += step;
             }
             const int q = item - (__shfl(incl, j, 64) - __shfl(nq, j, 64));
-            const int vj = __shfl(v, j, 64);
-            const int cj = __shfl(cv, j, 64);
+            vj = __shfl(v, j, 64);
+            cj = __shfl(cv, j, 64);
             const int bj = __shfl(beg, j, 64);
             const int ej = __shfl(end, j, 64);
             if (item >= total) continue;
-            int w[4];
             load_quad(a.colidx, a.nnz, bj, ej, q, w);
             int x[4];
 #pragma unroll
@@ -281,10 +279,22 @@ __device__ __forceinline__ void test_flagged(const RoundArgs& a, const int* ids,
             } else {
                 settle<true>(a, v, cv, cmax);
                 a.aflag[v] = 0;
-                if (C) nb += 13;
+                a.hint[v] = -1;                    // a settled vertex is nobody's sleeper
+                if (C) nb += 17;
             }
         }
-        push_rows_wave(P, win, v, cv, beg, end);
+        if (total <= 64) {
+            // item lane: its quad belongs to vertex j, a winner when no conflict was found
+            if (lane < total && slot[j] < 0) {
+                PushCtx Q = P;
+                Q.loaded = true;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (w[k] >= 0 && w[k] != vj) push_colour(Q, w[k], cj);
+            }
+        } else {
+            push_rows_wave(P, win, v, cv, beg, end);
+        }
         __builtin_amdgcn_wave_barrier();
     }
 }
