@@ -38,6 +38,7 @@ struct Workspace {
     unsigned char* rflag = nullptr;   // wake flags: recolour this round (padded to whole scans)
     unsigned char* aflag = nullptr;   // wake flags: test this round (padded likewise)
     int* srnd = nullptr;              // wake flags: settling round per vertex
+    unsigned long long* Fs = nullptr; // wake flags: forbidden-colour masks of the short rows
     unsigned long long* ubytes = nullptr;   // wake flags: bytes moved by the two kernels (on request)
     int* live = nullptr;         // live lists, same offsets as colidx
     size_t live_cap = 0;         // ints
@@ -192,8 +193,10 @@ void free_vertex_arrays(Workspace* w) {
     if (w->rflag) (void)hipFree(w->rflag);
     if (w->aflag) (void)hipFree(w->aflag);
     if (w->srnd) (void)hipFree(w->srnd);
+    if (w->Fs) (void)hipFree(w->Fs);
     w->rflag = w->aflag = nullptr;
     w->srnd = nullptr;
+    w->Fs = nullptr;
     w->X = w->wl[0] = w->wl[1] = w->hint = w->llen = nullptr;
     w->dirty = nullptr;
     w->cap_n = 0;
@@ -238,6 +241,7 @@ int ensure_capacity(Workspace* w, size_t n, int st_cap) {
             hipMalloc(&w->rflag, flag_bytes(want)) != hipSuccess ||
             hipMalloc(&w->aflag, flag_bytes(want)) != hipSuccess ||
             hipMalloc(&w->srnd, want * sizeof(int)) != hipSuccess ||
+            hipMalloc(&w->Fs, want * sizeof(unsigned long long)) != hipSuccess ||
             hipMalloc(&w->dirty, want + 16) != hipSuccess) {
             free_vertex_arrays(w);
             return CSRCOLOR_ENOMEM;
@@ -716,14 +720,21 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     // auto: the sleeping vertices are the short ones; where long rows hold most arcs the
     // full worklist rounds measured faster (R-MAT: 66 vs 78 ms at scale 23)
     const bool wake_wanted = J.opt.wake > 0 || (J.opt.wake == 0 && w->ctl_h->bigarcs * 10 < w->ctl_h->nnz);
+    // (colour words keep BIG at bit 30, so colours must stay below 2^30)
     const bool use_wake = wake_wanted && hint && J.opt.pushff && J.opt.algo == CSRCOLOR_ALGO_SGR &&
-                          J.opt.mode == CSRCOLOR_MODE_LOOP && !J.opt.ordered;
+                          J.opt.mode == CSRCOLOR_MODE_LOOP && !J.opt.ordered && J.maxdeg < CMASK - 1;
+    const bool longrows = hist[NTILE] + hist[NTILE + 1] + hist[BSPLIT] > 0;
     J.wake = use_wake;
     if (use_wake) {
         const int fw = (int)(flag_bytes((size_t)n) / 4);
         T.run(0, [&] {
             k_fill<<<std::min((fw + WG - 1) / WG, cus * 8), WG, 0, st>>>(reinterpret_cast<int*>(w->rflag), fw, 0);
             k_fill<<<std::min((fw + WG - 1) / WG, cus * 8), WG, 0, st>>>(reinterpret_cast<int*>(w->aflag), fw, 0);
+            for (size_t off = 0; off < 2 * (size_t)n; off += (size_t)1 << 30) {
+                const int cnt = (int)std::min<size_t>(2 * (size_t)n - off, (size_t)1 << 30);
+                k_fill<<<std::min((cnt + WG - 1) / WG, cus * 8), WG, 0, st>>>(reinterpret_cast<int*>(w->Fs) + off,
+                                                                                cnt, 0);
+            }
         });
     }
 
@@ -735,10 +746,13 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
         const size_t words = J.opt.pushff == 2 ? flags / 4 + 4 : flags / 32 + 2;
         if ((rc = ensure_F(w, words))) return rc;
         F = w->F;
-        T.run(0, [&] {
-            k_fill<<<(int)std::min<size_t>((words + WG - 1) / WG, (size_t)cus * 8), WG, 0, st>>>(
-                reinterpret_cast<int*>(F), (int)words, 0);
-        });
+        // with wake flags only the long rows use these flags (short ones: Fs)
+        if (!use_wake || longrows) {
+            T.run(0, [&] {
+                k_fill<<<(int)std::min<size_t>((words + WG - 1) / WG, (size_t)cus * 8), WG, 0, st>>>(
+                    reinterpret_cast<int*>(F), (int)words, 0);
+            });
+        }
         const int dwords = n / 4 + 1;
         if (!use_wake) {
             T.run(0, [&] {
@@ -768,7 +782,8 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
                                           w->ctl_h->nnz, J.opt.rule, J.opt.algo == CSRCOLOR_ALGO_JP, hint,
                                           use_live ? w->llen : nullptr, clen, lb, J.opt.pushff == 2,
                                           (F && !use_wake) ? w->dirty : nullptr,
-                                          use_wake ? w->rflag : nullptr, w->aflag, use_wake ? w->srnd : nullptr);
+                                          use_wake ? w->rflag : nullptr, w->aflag, use_wake ? w->srnd : nullptr,
+                                          w->Fs);
     });
     HIP_TRY(hipGetLastError());
 
@@ -803,6 +818,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
         a.aflag = w->aflag;
         a.srnd = w->srnd;
         a.hflag = FLAG;
+        a.Fs = w->Fs;
         if (J.stats && J.stats->kernel_bytes) {
             k_fill<<<1, 64, 0, st>>>(reinterpret_cast<int*>(w->ubytes), 4, 0);
             a.ubytes = w->ubytes;
@@ -829,7 +845,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     } else if (J.opt.mode == CSRCOLOR_MODE_GRAPH) {
         rc = drive_graph(w, J, a, budget);
     } else if (use_wake) {
-        rc = drive_wake(w, J, a, budget, hist[NTILE] + hist[NTILE + 1] + hist[BSPLIT] > 0, nhub, nchunk, T);
+        rc = drive_wake(w, J, a, budget, longrows, nhub, nchunk, T);
     } else {
         int ub[NB];
         for (int b = 0; b < NB; ++b) ub[b] = hist[b];

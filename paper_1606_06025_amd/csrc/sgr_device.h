@@ -3,7 +3,8 @@
 // Colour state: one int32 per vertex, X[v]:
 //   X[v] > 0                 v is settled with colour X[v] (1-based)
 //   X[v] == 0 or X[v] < 0    v is uncoloured in the snapshot; a negative value is
-//                            FLAG | c, the tentative colour c of the current round.
+//                            FLAG | c, the tentative colour c of the current round
+//                            (with wake flags also BIG when v has more than WAKE_DEG arcs).
 // FirstFit reads only X[w] > 0 (the previous round's snapshot) and writes FLAG|c
 // for its own worklist vertex; the conflict test compares colour parts
 // (X & CMASK), so the value a neighbour holds before or after its own write in the
@@ -21,7 +22,9 @@ constexpr int WG = 256;               // threads per workgroup (4 wavefronts of 
 constexpr int WAVES = WG / 64;
 constexpr int NB = 7;                 // degree buckets
 constexpr int FLAG = (int)0x80000000;
-constexpr int CMASK = 0x7fffffff;
+constexpr int BIG = 0x40000000;       // wake flags: marks the tentative colour of a row longer than WAKE_DEG
+constexpr int CMASK = 0x3fffffff;     // colour part of a colour word (colours stay below 2^30)
+constexpr int IDMASK = 0x7fffffff;    // vertex id part of a conflict hint
 constexpr int WAVE_CAP = 512;         // per-wavefront loser buffer (LDS entries)
 constexpr int SUB = WAVES * WAVE_CAP; // worklist entries per LDS flush
 constexpr int OVW = 32;               // overflow bitmap words per wavefront (colours 65..1088)
@@ -58,9 +61,14 @@ __device__ __forceinline__ bool beats(int rule, const int* __restrict__ rowptr, 
 __device__ __forceinline__ bool conflict(int rule, const int* __restrict__ rowptr, const int* X, int w, int v,
                                          int cv, int dv) {
     if (w < 0 || w == v) return false;
-    if (rule == 0) return w < v && (X[w] & 0x7fffffff) == cv;
-    return (X[w] & 0x7fffffff) == cv && beats(1, rowptr, w, v, dv);
+    if (rule == 0) return w < v && (X[w] & CMASK) == cv;
+    return (X[w] & CMASK) == cv && beats(1, rowptr, w, v, dv);
 }
+
+// Wake flags: a vertex sleeps only when it and the neighbour that beat it have at most
+// WAKE_DEG arcs (the tile buckets), so waking the sleepers of a recoloured vertex reads
+// a short row; every other requeued vertex is awake (tested every round).
+constexpr int WAKE_DEG = 61;
 
 // Where a settling vertex pushes its colour (push-mode FirstFit).
 struct PushCtx {
@@ -74,6 +82,9 @@ struct PushCtx {
     // pushed colour must take a new one next round, so its recolour flag is set
     const int* X;
     unsigned char* rflag;
+    // wake flags: the forbidden colours 1..64 of a vertex of at most WAKE_DEG arcs as one
+    // 64-bit mask (bit c-1), set by atomic OR; longer rows keep their flags in F
+    unsigned long long* Fs;
     bool all_tentative;           // round 1: every neighbour of a winner holds colour 1
     long long* nbytes;            // nullptr, or the calling thread's count of bytes moved
     bool loaded;                  // the colidx entries were already read (not counted again)
@@ -90,13 +101,7 @@ struct PushCtx {
 // With wake flags a settled neighbour is skipped (its flags are never read again), and
 // a neighbour holding tentative colour c gets its recolour flag (its smallest free
 // colour moves); concurrent writers all store 1.
-__device__ __forceinline__ void push_colour(const PushCtx& P, int u, int c) {
-    const int ub = P.rowptr[u];
-    const int ue = P.rowptr[u + 1];
-    const int xu = (P.rflag && !P.all_tentative) ? P.X[u] : (FLAG | c);
-    if (P.nbytes) *P.nbytes += (P.loaded ? 8 : 12) + (P.rflag && !P.all_tentative ? 4 : 0);   // colidx entry, rowptr pair, colour
-    if (xu > 0) return;
-    if (P.nbytes) *P.nbytes += (c - 1 <= ue - ub ? 1 : 0) + (P.rflag && xu == (FLAG | c) ? 1 : 0);
+__device__ __forceinline__ void push_flag(const PushCtx& P, int u, int c, int ub, int ue) {
     if (c - 1 <= ue - ub) {
         const long long pos = (long long)ub + u + c - 1;
         if (P.bytes) {
@@ -106,7 +111,41 @@ __device__ __forceinline__ void push_colour(const PushCtx& P, int u, int c) {
         }
         if (P.dirty) P.dirty[u] = 1;
     }
-    if (P.rflag && xu == (FLAG | c)) P.rflag[u] = 1;
+}
+__device__ __forceinline__ void push_colour(const PushCtx& P, int u, int c) {
+    if (P.rflag && !P.all_tentative) {
+        // wake flags: the colour word says whether u is settled, short (mask) or long
+        const int xu = P.X[u];
+        if (P.nbytes) *P.nbytes += (P.loaded ? 0 : 4) + 4;   // colidx entry, colour
+        if (xu > 0) return;
+        if (xu & BIG) {
+            const int ub = P.rowptr[u];
+            const int ue = P.rowptr[u + 1];
+            push_flag(P, u, c, ub, ue);
+            if (P.nbytes) *P.nbytes += 8 + (c - 1 <= ue - ub ? 1 : 0);
+        } else if (c <= 64) {
+            // colours above 64 cannot be the smallest free colour of u (at most 62)
+            atomicOr(&P.Fs[u], 1ull << (c - 1));
+            if (P.nbytes) *P.nbytes += 8;
+        }
+        if ((xu & (FLAG | CMASK)) == (FLAG | c)) {
+            P.rflag[u] = 1;
+            if (P.nbytes) *P.nbytes += 1;
+        }
+        return;
+    }
+    const int ub = P.rowptr[u];
+    const int ue = P.rowptr[u + 1];
+    if (P.nbytes) *P.nbytes += (P.loaded ? 8 : 12);   // colidx entry, rowptr pair
+    if (P.rflag) {
+        // round 1 with wake flags: every neighbour of a winner is a loser holding colour 1;
+        // a short one keeps its forbidden colours in its mask (all writers store 1)
+        P.rflag[u] = 1;
+        if (ue - ub <= WAKE_DEG) P.Fs[u] = 1ull;
+        else push_flag(P, u, c, ub, ue);
+        return;
+    }
+    push_flag(P, u, c, ub, ue);
 }
 
 // Internal rule number of the Jones-Plassmann independent-set colouring (Sec. 2.2,
@@ -226,6 +265,7 @@ struct RoundArgs {
     unsigned char* aflag;
     int* srnd;
     int hflag;          // FLAG with wake flags (a long row's hint never names it a sleeper), else 0
+    unsigned long long* Fs;   // wake flags: forbidden-colour masks of the rows of at most WAKE_DEG arcs
     int gdense;         // blocks of the flag-scanning grids
     int vpw;            // vertices per wavefront in the flag scans (64, 128 or 256)
     // nullptr, or bytes moved (algorithmic, each element at its size) by the recolouring
@@ -237,11 +277,6 @@ struct RoundArgs {
     int seg[NB + 1];    // bucket segment offsets inside the worklist arrays
     int boff[NB + 1];   // block offsets of each bucket inside the grid
 };
-
-// Wake flags: a vertex sleeps only when it and the neighbour that beat it have at most
-// WAKE_DEG arcs (the tile buckets), so waking the sleepers of a recoloured vertex reads
-// a short row; every other requeued vertex is awake (tested every round).
-constexpr int WAKE_DEG = 61;
 
 // Tentative colour of worklist vertex v: the FirstFit result in X, or under JP the
 // colour of the round.
@@ -258,7 +293,7 @@ __device__ __forceinline__ int tentative(const RoundArgs& a, int v) {
 __device__ __forceinline__ bool hint_hit(const RoundArgs& a, int v, int cv) {
     if (!a.hint) return false;
     const int h = a.hint[v];
-    return h != -1 && (h & CMASK) < v && (a.X[h & CMASK] & CMASK) == cv;
+    return h != -1 && (h & IDMASK) < v && (a.X[h & IDMASK] & CMASK) == cv;
 }
 
 // Is worklist vertex v (tentative colour cv, degree dv) requeued because of row entry

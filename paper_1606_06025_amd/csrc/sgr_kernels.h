@@ -121,7 +121,8 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
                                                Seg seg, int* cstart1, int* owner1, unsigned* F, int nnz,
                                                int rule, int jp, int* hint, int* llen, int* clen,
                                                unsigned long long* lb1, int fbytes, unsigned char* dirty,
-                                               unsigned char* rflag, unsigned char* aflag, int* srnd) {
+                                               unsigned char* rflag, unsigned char* aflag, int* srnd,
+                                               unsigned long long* Fs) {
     constexpr int ITER = 4;
     __shared__ int buf[WAVES][NB][ITER * 64];
     __shared__ int wcnt[WAVES][NB];
@@ -141,6 +142,7 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
     P.dirty = dirty;
     P.X = X;
     P.rflag = rflag;
+    P.Fs = Fs;
     P.all_tentative = true;
     P.nbytes = nullptr;
     P.loaded = false;
@@ -202,7 +204,7 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
                 hint[v] = by;
             }
             if (lose) {
-                X[v] = jp ? 0 : (FLAG | 1);
+                X[v] = jp ? 0 : (FLAG | 1 | (rflag && end - beg > WAKE_DEG ? BIG : 0));
                 bkt = bucket_of(end - beg, twave, tsplit);
                 if (rflag && bkt < NTILE) bkt = -1;      // wake flags: not listed
                 if (llen && bkt >= NTILE && bkt < BSPLIT) llen[v] = -1;   // live list not built yet

@@ -203,6 +203,7 @@ __device__ __forceinline__ PushCtx push_ctx(const RoundArgs& a) {
     P.dirty = a.dirty;
     P.X = a.X;
     P.rflag = W ? a.rflag : nullptr;
+    P.Fs = W ? a.Fs : nullptr;
     P.all_tentative = false;
     P.nbytes = nullptr;
     P.loaded = false;
@@ -863,7 +864,7 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
                     if (loses_to(a, w[k], v, cv, end - beg)) found = w[k];
-                if (found >= 0 && a.hint) a.hint[v] = found | a.hflag;    // any conflicting neighbour will do
+                if (found >= 0 && a.hint) a.hint[v] = found | (W ? a.hflag : 0);    // any conflicting neighbour will do
                 const bool lost = ((__ballot(found >= 0) >> gshift) & gmask) != 0;
                 if (q == 0 && real) res2[e] = lost;
             }
@@ -931,7 +932,7 @@ __device__ __forceinline__ void detect_lanes(const RoundArgs& a, const int* list
             }
             if (found >= 0) {
                 lost = true;
-                if (a.hint) a.hint[v_l] = found | a.hflag;
+                if (a.hint) a.hint[v_l] = found | (W ? a.hflag : 0);
             }
             if (v_l >= 0 && !lost) settle<W>(a, v_l, cv, cmax);
             if (a.pushff) push_rows_wave<W>(a, v_l >= 0 && !lost, v_l, cv, beg, end);
@@ -958,7 +959,8 @@ __device__ __forceinline__ void detect_lanes(const RoundArgs& a, const int* list
 // src[beg, end) (quad q of the range), tests them against v and returns the lower
 // neighbours still uncoloured in keep/w.
 __device__ __forceinline__ void live_step(const RoundArgs& a, const int* src, int beg, int end, int q, int v,
-                                          int cv, bool build, int w[4], unsigned& keep, bool& hit, bool& stop) {
+                                          int cv, bool build, int w[4], unsigned& keep, bool& hit, bool& stop,
+                                          int hf) {
     load_quad(src, a.nnz, beg, end, q, w);
     keep = 0;
     int found = -1;
@@ -975,7 +977,7 @@ __device__ __forceinline__ void live_step(const RoundArgs& a, const int* src, in
     }
     if (found >= 0) {
         hit = true;
-        if (a.hint) a.hint[v] = found | a.hflag;     // any conflicting neighbour will do
+        if (a.hint) a.hint[v] = found | hf;     // any conflicting neighbour will do
     }
 }
 
@@ -989,7 +991,7 @@ __device__ __forceinline__ int quad_end(const int* src, int beg, int q) {
 // [rb, re)) on its live list of length len (-1: build it from the row).  Updates the
 // list and its length *lenp; returns whether v is requeued.  Every lane must call.
 __device__ __forceinline__ bool live_test_wave(const RoundArgs& a, int v, int cv, int rb, int re, int len,
-                                               int* lenp) {
+                                               int* lenp, int hf) {
     const int lane = __lane_id();
     const bool build = len < 0;
     const int* src = build ? a.colidx : a.live;
@@ -1003,7 +1005,7 @@ __device__ __forceinline__ bool live_test_wave(const RoundArgs& a, int v, int cv
         int w[4];
         unsigned keep;
         bool hit = false, stop = false;
-        live_step(a, src, rb, send, q0 + lane, v, cv, build, w, keep, hit, stop);
+        live_step(a, src, rb, send, q0 + lane, v, cv, build, w, keep, hit, stop, hf);
         int tot;
         int pos = rb + K + wave_excl(__popc(keep), tot);
         const int qs = rb + quad_end(src, rb, q0 + lane);   // position of w[0] in src
@@ -1040,7 +1042,7 @@ __device__ __forceinline__ bool live_test_wave(const RoundArgs& a, int v, int cv
 // `early` the scan of a built list stops at the first conflict; the returned verdict
 // is the same in every thread.
 __device__ __forceinline__ bool live_test_wg(const RoundArgs& a, int v, int cv, int rb, int re, int len,
-                                             int* lenp, bool early, RoundLds& s) {
+                                             int* lenp, bool early, RoundLds& s, int hf) {
     const int tid = threadIdx.x;
     const int lane = __lane_id();
     const int wv = tid >> 6;
@@ -1056,7 +1058,7 @@ __device__ __forceinline__ bool live_test_wg(const RoundArgs& a, int v, int cv, 
         int w[4];
         unsigned keep;
         bool hit = false, stop = false;
-        live_step(a, src, rb, send, q0 + tid, v, cv, build, w, keep, hit, stop);
+        live_step(a, src, rb, send, q0 + tid, v, cv, build, w, keep, hit, stop, hf);
         int wtot;
         const int wex = wave_excl(__popc(keep), wtot);
         if (lane == 0) s.lpre[wv] = wtot;
@@ -1133,7 +1135,7 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
                 const int cv = __builtin_amdgcn_readlane(cv_l, j);
                 if (a.live) {
                     const bool lost = live_test_wave(a, v, cv, beg, end, __builtin_amdgcn_readlane(len_l, j),
-                                                     &a.llen[v]);
+                                                     &a.llen[v], W ? a.hflag : 0);
                     if (lane == j) lost_l = lost;
                     continue;
                 }
@@ -1149,7 +1151,7 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
                         if (loses_to(a, w[k], v, cv, end - beg)) found = w[k];
                         stop |= a.sorted && a.rule == 0 && w[k] >= v;
                     }
-                    if (found >= 0 && a.hint) a.hint[v] = found | a.hflag;   // any conflicting neighbour will do
+                    if (found >= 0 && a.hint) a.hint[v] = found | (W ? a.hflag : 0);   // any conflicting neighbour will do
                     if (__ballot(found >= 0)) {
                         lost = true;
                         break;
@@ -1187,7 +1189,7 @@ __device__ __forceinline__ void detect_wg(const RoundArgs& a, const int* list, i
         const int v = list[i];
         const int beg = a.rowptr[v], end = a.rowptr[v + 1];
         const int cv = tentative(a, v);
-        if (a.live && !lost) lost = live_test_wg(a, v, cv, beg, end, len, &a.llen[v], true, s);
+        if (a.live && !lost) lost = live_test_wg(a, v, cv, beg, end, len, &a.llen[v], true, s, W ? a.hflag : 0);
         const int nq = (lost || a.live) ? 0 : ((end - beg) + 3 + 3) / 4 + 1;
         for (int q0 = 0; q0 < nq; q0 += WG) {
             int w[4];
@@ -1197,7 +1199,7 @@ __device__ __forceinline__ void detect_wg(const RoundArgs& a, const int* list, i
             for (int k = 0; k < 4; ++k) {
                 if (loses_to(a, w[k], v, cv, end - beg)) {
                     hit = true;
-                    if (a.hint) a.hint[v] = w[k] | a.hflag;
+                    if (a.hint) a.hint[v] = w[k] | (W ? a.hflag : 0);
                 }
                 stop |= a.sorted && a.rule == 0 && w[k] >= v;
             }
@@ -1264,7 +1266,7 @@ __device__ __forceinline__ void detect_split(const RoundArgs& a, const int* list
             const int cl = s.lsh[2];
             const int ci = s.lsh[3];
             __syncthreads();
-            if (!sk && cl != 0) hit = live_test_wg(a, v, cv, beg, end, cl, &a.clen[ci], false, s);
+            if (!sk && cl != 0) hit = live_test_wg(a, v, cv, beg, end, cl, &a.clen[ci], false, s, W ? a.hflag : 0);
         }
         // the remembered neighbour decides for every chunk of the hub at once
         if (!a.live) hit = hint_hit(a, v, cv);
@@ -1279,7 +1281,7 @@ __device__ __forceinline__ void detect_split(const RoundArgs& a, const int* list
                 for (int kk = 0; kk < 4; ++kk) {
                     if (loses_to(a, w[kk], v, cv, re - rb)) {
                         hit = true;
-                        if (a.hint) a.hint[v] = w[kk] | a.hflag;
+                        if (a.hint) a.hint[v] = w[kk] | (W ? a.hflag : 0);
                     }
                 }
             }
@@ -1360,7 +1362,7 @@ __device__ __forceinline__ void detect_split_wave(const RoundArgs& a, const int*
         sk = __builtin_amdgcn_readfirstlane(sk);
         cl = __builtin_amdgcn_readfirstlane(cl);
         bool hit = h != 0;
-        if (!sk && cl != 0) hit = live_test_wave(a, v, cv, beg, end, cl, &a.clen[ci]);
+        if (!sk && cl != 0) hit = live_test_wave(a, v, cv, beg, end, cl, &a.clen[ci], W ? a.hflag : 0);
         int decide = 0;
         if (lane == 0) {
             unsigned old = 0;

@@ -177,9 +177,19 @@ __global__ __launch_bounds__(WG) void k_wassign(RoundArgs a) {
             }
             const bool on = x < 0;     // flagged vertices are uncoloured; kept as a guard
             if (on) {
-                int words = 0;
-                a.X[u] = FLAG | first_free(a, beg, u, words);
-                if (C) nb += 4 * words + 4;
+                int c;
+                if (x & BIG) {
+                    int words = 0;
+                    c = first_free(a, beg, u, words);
+                    if (C) nb += 4 * words;
+                } else {
+                    // a short row's forbidden colours in one mask: the smallest free colour
+                    // is at most 62, so the lowest clear bit exists
+                    c = __ffsll((long long)~a.Fs[u]);
+                    if (C) nb += 8;
+                }
+                a.X[u] = (x & BIG) | FLAG | c;
+                if (C) nb += 4;
             }
             const bool small = on && end - beg <= WAKE_DEG;
             if (small) {
@@ -224,9 +234,11 @@ __device__ __forceinline__ void test_flagged(const RoundArgs& a, const int* ids,
             }
         }
         // an awake vertex (long hint) usually still loses to it: then no row walk
-        const bool held = v >= 0 && hv < 0 && hv != -1 && (a.X[hv & CMASK] & CMASK) == cv;
+        const bool held = v >= 0 && hv < 0 && hv != -1 && (a.X[hv & IDMASK] & CMASK) == cv;
         if (C && v >= 0) nb += 16 + (hv < 0 && hv != -1 ? 4 : 0);   // colour, hint, rowptr pair, hint's colour
-        slot[lane] = held ? (hv & CMASK) : -1;
+        // verdict slot: 0 = no conflict, else 1 + (2 * neighbour + 1 if it is long); the
+        // largest conflicting neighbour wins the atomic maximum
+        slot[lane] = held ? (int)(2u * (unsigned)(hv & IDMASK) + 2u) : 0;
         __builtin_amdgcn_wave_barrier();
         const int nq = v >= 0 && !held && end > beg ? (((end - 1 + mis) >> 2) - ((beg + mis) >> 2) + 1) : 0;
         int incl = nq;
@@ -257,25 +269,27 @@ __device__ __forceinline__ void test_flagged(const RoundArgs& a, const int* ids,
             int x[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) x[k] = (w[k] >= 0 && w[k] < vj) ? a.X[w[k]] : 0;
-            int found = -1;
+            unsigned found = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                if ((x[k] & CMASK) == cj) found = max(found, w[k]);
-            if (found >= 0) atomicMax(&slot[j], found);
+                if ((x[k] & CMASK) == cj)
+                    found = max(found, 2u * (unsigned)w[k] + ((x[k] & BIG) ? 2u : 1u));
+            if (found) atomicMax(reinterpret_cast<unsigned*>(&slot[j]), found);
             if (C) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) nb += (w[k] >= 0 ? 4 : 0) + (w[k] >= 0 && w[k] < vj ? 4 : 0);
             }
         }
         __builtin_amdgcn_wave_barrier();
-        const int h = slot[lane];
-        const bool win = v >= 0 && h < 0;
+        const unsigned e = (unsigned)slot[lane];
+        const bool win = v >= 0 && e == 0;
         if (v >= 0 && !held) {
-            if (h >= 0) {
-                const bool big = a.rowptr[h + 1] - a.rowptr[h] > WAKE_DEG;
+            if (e) {
+                const int h = (int)((e - 1) >> 1);
+                const bool big = ((e - 1) & 1) != 0;
                 a.hint[v] = big ? (h | FLAG) : h;
                 if (!big) a.aflag[v] = 0;          // asleep until woken
-                if (C) nb += 12 + (big ? 0 : 1);
+                if (C) nb += 4 + (big ? 0 : 1);
             } else {
                 settle<true>(a, v, cv, cmax);
                 a.aflag[v] = 0;
@@ -285,7 +299,7 @@ __device__ __forceinline__ void test_flagged(const RoundArgs& a, const int* ids,
         }
         if (total <= 64) {
             // item lane: its quad belongs to vertex j, a winner when no conflict was found
-            if (lane < total && slot[j] < 0) {
+            if (lane < total && slot[j] == 0) {
                 PushCtx Q = P;
                 Q.loaded = true;
 #pragma unroll
