@@ -267,7 +267,7 @@ struct RoundArgs {
     int hflag;          // FLAG with wake flags (a long row's hint never names it a sleeper), else 0
     unsigned long long* Fs;   // wake flags: forbidden-colour masks of the rows of at most WAKE_DEG arcs
     int gdense;         // blocks of the flag-scanning grids
-    int vpw;            // vertices per wavefront in the flag scans (64, 128 or 256)
+    int vpw;            // vertices per wavefront in the flag scans (64, 128, 256 or 512)
     // nullptr, or bytes moved (algorithmic, each element at its size) by the recolouring
     // and the flag-scanning test launches: [0] and [1], summed over the run
     unsigned long long* ubytes;

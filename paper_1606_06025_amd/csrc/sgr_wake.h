@@ -32,7 +32,7 @@
 
 namespace csrcolor {
 
-constexpr int VPW = 256;   // most vertices per wavefront in the flag scans (4 per lane)
+constexpr int VPW = 512;   // most vertices per wavefront in the flag scans (8 per lane)
 
 // Smallest free colour of v from its push-mode flags: the first clear flag at or after
 // position rowptr[v] + v (flags before it count as set); one exists within deg(v) + 1.
@@ -62,10 +62,11 @@ __device__ __forceinline__ int first_free(const RoundArgs& a, int beg, int v, in
     return (int)(pos - bit + 1);
 }
 
-// Flag bytes of the wavefront's vertices v0 .. v0 + 64k - 1, k (1, 2 or 4) per lane
+// Flag bytes of the wavefront's vertices v0 .. v0 + 64k - 1, k (1, 2, 4 or 8) per lane
 // (the arrays are padded with zeros to a whole number of VPW).
-__device__ __forceinline__ unsigned load_flags(const unsigned char* fl, long long v0, int k) {
+__device__ __forceinline__ unsigned long long load_flags(const unsigned char* fl, long long v0, int k) {
     const int lane = __lane_id();
+    if (k == 8) return reinterpret_cast<const unsigned long long*>(fl + v0)[lane];
     if (k == 4) return reinterpret_cast<const unsigned*>(fl + v0)[lane];
     if (k == 2) return reinterpret_cast<const unsigned short*>(fl + v0)[lane];
     return fl[v0 + lane];
@@ -74,16 +75,16 @@ __device__ __forceinline__ unsigned load_flags(const unsigned char* fl, long lon
 // Lists the vertices whose flag byte is set (lane l holds the bytes of vertices
 // v0 + kl .. v0 + kl + k - 1 in f) in ids, in id order; returns their number.  Every
 // lane must call.
-__device__ __forceinline__ int flag_compact(unsigned f, int v0, int k, int* ids) {
+__device__ __forceinline__ int flag_compact(unsigned long long f, int v0, int k, int* ids) {
     const int lane = __lane_id();
     unsigned m = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 8; ++j)
         if (j < k && ((f >> (8 * j)) & 0xffu)) m |= 1u << j;
     int tot;
     int pos = wave_excl(__popc(m), tot);
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 8; ++j)
         if (m >> j & 1) ids[pos++] = v0 + k * lane + j;
     __builtin_amdgcn_wave_barrier();
     return tot;
