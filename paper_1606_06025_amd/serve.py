@@ -78,7 +78,9 @@ class Backend:
 
 class HipBackend(Backend):
     """Graphs live in device tensors; a batch is one csrcolor_color_multi call on the
-    slot's stream."""
+    slot's stream.  Uploads go through freshly pinned host copies on a stream of their
+    own (so they overlap the batches running on the slots), each followed by an event
+    the batch's stream waits for; a batch's colours come back in one pinned buffer."""
 
     def __init__(self, nslots: int = 2, device: str = "cuda:0", opts=None):
         import torch
@@ -88,26 +90,44 @@ class HipBackend(Backend):
         self.device = torch.device(device)
         self.nslots = nslots
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(nslots)]
+        self.up_stream = torch.cuda.Stream(device=self.device)
         self.opts = opts
 
     def upload(self, rowptr, colidx):
         torch = self.torch
-        rp = torch.from_numpy(np.ascontiguousarray(rowptr, dtype=np.int32)).to(self.device)
-        ci = torch.from_numpy(np.ascontiguousarray(colidx, dtype=np.int32)).to(self.device)
-        out = torch.empty(max(len(rowptr) - 1, 0), dtype=torch.int32, device=self.device)
-        torch.cuda.current_stream(self.device).synchronize()
-        return (rp, ci, out, int(len(colidx)))
+        n = max(len(rowptr) - 1, 0)
+        hrp = torch.from_numpy(np.ascontiguousarray(rowptr, dtype=np.int32)).pin_memory()
+        hci = torch.from_numpy(np.ascontiguousarray(colidx, dtype=np.int32)).pin_memory()
+        with torch.cuda.stream(self.up_stream):
+            rp = hrp.to(self.device, non_blocking=True)
+            ci = hci.to(self.device, non_blocking=True)
+            out = torch.empty(n, dtype=torch.int32, device=self.device)
+            ev = torch.cuda.Event()
+            ev.record(self.up_stream)
+        # the pinned copies stay referenced until the batch has waited for the event
+        return (rp, ci, out, int(len(colidx)), ev, (hrp, hci))
 
     def run_batch(self, slot, handles):
         from . import api
         torch = self.torch
         st = self.streams[slot]
+        for h in handles:
+            st.wait_event(h[4])
+        sizes = [h[2].numel() for h in handles]
+        host = torch.empty(sum(sizes), dtype=torch.int32, pin_memory=True)
         with torch.cuda.stream(st):
             outs, ncol = api.color_multi([(h[0], h[1]) for h in handles], outs=[h[2] for h in handles],
                                          nnz=[h[3] for h in handles], opts=self.opts, stream=st)
-            res = [o.cpu().numpy() for o in outs]
+            off = 0
+            for o, k in zip(outs, sizes):
+                host[off:off + k].copy_(o[:k], non_blocking=True)
+                off += k
             nc = ncol.cpu().numpy()
         st.synchronize()
+        res, off = [], 0
+        for k in sizes:
+            res.append(host[off:off + k].numpy().copy())
+            off += k
         return [(res[i], int(nc[i])) for i in range(len(handles))]
 
 

@@ -407,7 +407,7 @@ def test_live_lists_on_and_off(dev, live, mode):
 
 @pytest.mark.parametrize("wake", [-1, 1])
 @pytest.mark.parametrize("live", [-1, 1])
-def test_wake_lists_on_and_off(dev, wake, live):
+def test_wake_flags_on_and_off(dev, wake, live):
     """A requeued vertex may be left untested until its colour or that of its conflict
     hint changes; on or off, with live lists on or off, bit or byte flags, every bucket
     (tiles, lanes, wavefront, workgroup, split rows), sorted or unsorted rows, the
@@ -421,7 +421,7 @@ def test_wake_lists_on_and_off(dev, wake, live):
         _assert_parity(g, dev, wake=wake, live_lists=live, firstfit=2, lane_detect=-1, t_wave=128, t_split=1024)
 
 
-def test_wake_lists_repeated_entries(dev):
+def test_wake_flags_repeated_entries(dev):
     """Rows that repeat an entry (sorted or not, with self-loops) would let a recoloured
     vertex wake the same sleeper twice; the colouring and the statistics stay the
     oracle's."""
@@ -435,13 +435,39 @@ def test_wake_lists_repeated_entries(dev):
         _assert_parity(gg.raw_csr(base.n, rows), dev)
 
 
-def test_wake_lists_workspace_reuse(dev):
+def test_wake_flags_workspace_reuse(dev):
     """Consecutive runs of different sizes share the stamps and recolour lists of the
     workspace: stale entries of an earlier run must never be taken for this one's."""
     seq = [gg.stencil27(20, 20, 20), gg.rmat(13, 16, 3), gg.stencil27(9, 8, 7), gg.erdos_renyi(5000, 40000, 2),
            gg.stencil27(20, 20, 20)]
     for g in seq:
         _assert_parity(g, dev)
+
+
+@pytest.mark.parametrize("n", [262144, 262145, 524289, 1048577])
+def test_wake_flags_scan_widths(dev, n):
+    """The flag scans take 64, 128, 256 or 512 vertices per wavefront by graph size;
+    sizes at and just past each step give the oracle's colouring, including the padded
+    tail of the last scan."""
+    _assert_parity(gg.erdos_renyi(n, 4 * n, n % 97), dev, wake=1)
+
+
+def test_wake_flags_byte_counting(dev):
+    """The counting instantiations of the wake kernels colour exactly like the timed
+    ones and report bytes; runs without wake flags report none."""
+    import oracle
+    from paper_1606_06025_amd import api
+    for g, wake in [(gg.stencil27(30, 20, 10), 0), (gg.rmat(13, 16, 5), 1), (gg.rmat(13, 16, 5), -1)]:
+        ref = oracle.sgr(g.n, g.rowptr, g.colidx)
+        rp = torch.from_numpy(g.rowptr).to(dev)
+        ci = torch.from_numpy(g.colidx).to(dev)
+        colors, nc, st = api.color(rp, ci, opts=api.make_opts(wake=wake), stats=True, count_bytes=True)
+        assert (colors.cpu().numpy() == ref.colors).all() and nc == ref.ncolors
+        assert st.rounds == ref.rounds
+        if wake >= 0:
+            assert st.kernel_bytes[0] > 0 and st.kernel_bytes[1] > 0
+        else:
+            assert st.kernel_bytes == [0, 0]
 
 
 def test_live_lists_workspace_reuse(dev):
