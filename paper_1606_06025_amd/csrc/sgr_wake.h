@@ -249,36 +249,56 @@ __device__ __forceinline__ void test_flagged(const RoundArgs& a, const int* ids,
             if (lane >= off) incl += t;
         }
         const int total = __shfl(incl, 63, 64);
-        // the quads of the last pass stay in registers: when one pass covers every row,
-        // the winners push from them without reading their rows again
-        int w[4] = {-1, -1, -1, -1};
-        int j = 0, vj = -1, cj = 0;
-        for (int base = 0; base < total; base += 64) {
-            const int item = base + lane;
-            j = 0;
+        // two quads per lane per pass (items lane and 64 + lane), their loads and colour
+        // gathers in flight together; the quads of the last pass stay in registers: when
+        // one pass covers every row, the winners push from them without reading their rows
+        // again
+        int w[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};
+        int j[2] = {0, 0}, vj[2] = {-1, -1}, cj[2] = {0, 0};
+        for (int base = 0; base < total; base += 128) {
+            int q[2], bj[2], ej[2];
 #pragma unroll
-            for (int step = 32; step >= 1; step >>= 1) {
-                if (__shfl(incl, j + step - 1, 64) <= item) j += step;
+            for (int u = 0; u < 2; ++u) {
+                const int item = base + 64 * u + lane;
+                int jj = 0;
+#pragma unroll
+                for (int step = 32; step >= 1; step >>= 1) {
+                    if (__shfl(incl, jj + step - 1, 64) <= item) jj += step;
+                }
+                j[u] = jj;
+                q[u] = item - (__shfl(incl, jj, 64) - __shfl(nq, jj, 64));
+                vj[u] = __shfl(v, jj, 64);
+                cj[u] = __shfl(cv, jj, 64);
+                bj[u] = __shfl(beg, jj, 64);
+                ej[u] = __shfl(end, jj, 64);
             }
-            const int q = item - (__shfl(incl, j, 64) - __shfl(nq, j, 64));
-            vj = __shfl(v, j, 64);
-            cj = __shfl(cv, j, 64);
-            const int bj = __shfl(beg, j, 64);
-            const int ej = __shfl(end, j, 64);
-            if (item >= total) continue;
-            load_quad(a.colidx, a.nnz, bj, ej, q, w);
-            int x[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) x[k] = (w[k] >= 0 && w[k] < vj) ? a.X[w[k]] : 0;
-            unsigned found = 0;
+            for (int u = 0; u < 2; ++u) {
+                if (base + 64 * u + lane < total) {
+                    load_quad(a.colidx, a.nnz, bj[u], ej[u], q[u], w[u]);
+                } else {
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if ((x[k] & CMASK) == cj)
-                    found = max(found, 2u * (unsigned)w[k] + ((x[k] & BIG) ? 2u : 1u));
-            if (found) atomicMax(reinterpret_cast<unsigned*>(&slot[j]), found);
-            if (C) {
+                    for (int k = 0; k < 4; ++k) w[u][k] = -1;
+                }
+            }
+            int x[2][4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) nb += (w[k] >= 0 ? 4 : 0) + (w[k] >= 0 && w[k] < vj ? 4 : 0);
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) x[u][k] = (w[u][k] >= 0 && w[u][k] < vj[u]) ? a.X[w[u][k]] : 0;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                unsigned found = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if ((x[u][k] & CMASK) == cj[u])
+                        found = max(found, 2u * (unsigned)w[u][k] + ((x[u][k] & BIG) ? 2u : 1u));
+                if (found) atomicMax(reinterpret_cast<unsigned*>(&slot[j[u]]), found);
+                if (C) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        nb += (w[u][k] >= 0 ? 4 : 0) + (w[u][k] >= 0 && w[u][k] < vj[u] ? 4 : 0);
+                }
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -298,14 +318,18 @@ __device__ __forceinline__ void test_flagged(const RoundArgs& a, const int* ids,
                 if (C) nb += 17;
             }
         }
-        if (total <= 64) {
-            // item lane: its quad belongs to vertex j, a winner when no conflict was found
-            if (lane < total && slot[j] == 0) {
-                PushCtx Q = P;
-                Q.loaded = true;
+        if (total <= 128) {
+            // item lane (+ 64 u): its quad belongs to vertex j[u], a winner when no conflict
+            // was found
+            PushCtx Q = P;
+            Q.loaded = true;
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (w[k] >= 0 && w[k] != vj) push_colour(Q, w[k], cj);
+            for (int u = 0; u < 2; ++u) {
+                if (64 * u + lane < total && slot[j[u]] == 0) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (w[u][k] >= 0 && w[u][k] != vj[u]) push_colour(Q, w[u][k], cj[u]);
+                }
             }
         } else {
             push_rows_wave(P, win, v, cv, beg, end);
