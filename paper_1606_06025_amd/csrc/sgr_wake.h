@@ -107,33 +107,52 @@ __device__ __forceinline__ void wake_children(const RoundArgs& a, bool on, int u
         if (lane >= off) incl += t;
     }
     const int total = __shfl(incl, 63, 64);
-    for (int base = 0; base < total; base += 64) {
-        const int item = base + lane;
-        int j = 0;
+    // two quads per lane per pass (items lane and 64 + lane), loads in flight together
+    for (int base = 0; base < total; base += 128) {
+        int q[2], uj[2], bj[2], ej[2];
 #pragma unroll
-        for (int step = 32; step >= 1; step >>= 1) {
-            if (__shfl(incl, j + step - 1, 64) <= item) j += step;
+        for (int t = 0; t < 2; ++t) {
+            const int item = base + 64 * t + lane;
+            int j = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1) {
+                if (__shfl(incl, j + step - 1, 64) <= item) j += step;
+            }
+            q[t] = item - (__shfl(incl, j, 64) - __shfl(nq, j, 64));
+            uj[t] = __shfl(u, j, 64);
+            bj[t] = __shfl(beg, j, 64);
+            ej[t] = __shfl(end, j, 64);
         }
-        const int q = item - (__shfl(incl, j, 64) - __shfl(nq, j, 64));
-        const int uj = __shfl(u, j, 64);
-        const int bj = __shfl(beg, j, 64);
-        const int ej = __shfl(end, j, 64);
-        if (item >= total) continue;
-        int w[4];
-        load_quad(a.colidx, a.nnz, bj, ej, q, w);
-        int h[4];
+        int w[2][4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) h[k] = w[k] > uj ? a.hint[w[k]] : -1;
+        for (int t = 0; t < 2; ++t) {
+            if (base + 64 * t + lane < total) {
+                load_quad(a.colidx, a.nnz, bj[t], ej[t], q[t], w[t]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) w[t][k] = -1;
+            }
+        }
+        int h[2][4];
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) h[t][k] = w[t][k] > uj[t] ? a.hint[w[t][k]] : -1;
         // a hint equal to u (no FLAG) is held only by an uncoloured vertex of at most
         // WAKE_DEG arcs: settling clears a hint and long rows' hints carry FLAG
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (w[k] > uj && h[k] == uj) a.aflag[w[k]] = 1;
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (w[t][k] > uj[t] && h[t][k] == uj[t]) a.aflag[w[t][k]] = 1;
         if (C) {
             // colidx entries, hints of the higher ones, the sleepers' test flags
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                nb += (w[k] >= 0 ? 4 : 0) + (w[k] > uj ? 4 : 0) + (w[k] > uj && h[k] == uj ? 1 : 0);
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    nb += (w[t][k] >= 0 ? 4 : 0) + (w[t][k] > uj[t] ? 4 : 0) +
+                          (w[t][k] > uj[t] && h[t][k] == uj[t] ? 1 : 0);
         }
     }
 }
