@@ -514,20 +514,10 @@ int drive_wake(Workspace* w, Job& J, RoundArgs& a, int budget, bool big, int nhu
             a.wround = (int)r;
             if (a.ubytes) T.run(1, [&] { k_wassign<true><<<a.gdense, WG, 0, st>>>(a); });
             else T.run(1, [&] { k_wassign<false><<<a.gdense, WG, 0, st>>>(a); });
-            if (big && a.ubytes) {
-                // counting: the flag scan on its own, then the worklists of the long rows
-                RoundArgs al = a;
-                al.gdense = 0;
-                T.run(2, [&] { k_detect_flags<true><<<a.gdense, WG, 0, st>>>(a); });
-                T.run(2, [&] { k_detect<true><<<budget, WG, 0, st>>>(al); });
-            } else if (big) {
-                // one launch: flag scan in the first gdense blocks, worklists of the long rows after
-                T.run(2, [&] { k_detect<true><<<a.gdense + budget, WG, 0, st>>>(a); });
-            } else if (a.ubytes) {
-                T.run(2, [&] { k_detect_flags<true><<<a.gdense, WG, 0, st>>>(a); });
-            } else {
-                T.run(2, [&] { k_detect_flags<false><<<a.gdense, WG, 0, st>>>(a); });
-            }
+            if (a.ubytes) T.run(2, [&] { k_detect_flags<true><<<a.gdense, WG, 0, st>>>(a); });
+            else T.run(2, [&] { k_detect_flags<false><<<a.gdense, WG, 0, st>>>(a); });
+            // the worklists of the long rows, if any, in a launch of their own
+            if (big) T.run(2, [&] { k_detect<true><<<budget, WG, 0, st>>>(a); });
             if (nhub > 0) T.run(2, [&] { k_push<true><<<pgrid, WG, 0, st>>>(a); });
             par ^= 1;
             ++r;

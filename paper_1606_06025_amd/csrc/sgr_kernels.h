@@ -309,42 +309,33 @@ __device__ __forceinline__ void detect_flags_phase(const RoundArgs& a, int* ids,
 }
 
 // Conflict test of a round (Sec. 3, ConflictResolve; see detect_phase), one launch for
-// every degree bucket.  With wake flags (W) the last gdense blocks run the flag scan of
-// the vertices of at most WAKE_DEG arcs and the others, dispatched first because their
-// long rows take longest, the worklists of the longer ones (k_detect_flags alone serves
-// graphs without longer rows).
+// every degree bucket (with wake flags only the rows longer than WAKE_DEG are on the
+// worklists).
 template <bool W>
-__global__ __launch_bounds__(WG, W ? 5 : 6) void k_detect(RoundArgs a) {
+__global__ __launch_bounds__(WG, 6) void k_detect(RoundArgs a) {
     __shared__ RoundLds s;
     __shared__ int boff[NB + 1];
-    int cmax = 0;
-    const int nlist = (int)gridDim.x - (W ? a.gdense : 0);
-    if (W && (int)blockIdx.x >= nlist) {
-        const int wv = threadIdx.x >> 6;
-        detect_flags_phase<false>(a, s.lbuf + wv * WAVE_CAP, s.res + wv * 64, (int)blockIdx.x - nlist,
-                                  a.gdense, cmax, s.red64);
-    } else {
-        const int bid = (int)blockIdx.x;
-        const int nblk = nlist;
-        if (threadIdx.x == 0) {
-            if (a.dev_plan) {
-                int cnt[NB];
-                queue_sizes(a.ctl, a.par_in, cnt);
-                device_plan(cnt, nblk, boff);
-            } else {
-                for (int k = 0; k <= NB; ++k) boff[k] = a.boff[k];
-            }
+    if (threadIdx.x == 0) {
+        if (a.dev_plan) {
+            int cnt[NB];
+            queue_sizes(a.ctl, a.par_in, cnt);
+            device_plan(cnt, gridDim.x, boff);
+        } else {
+            for (int k = 0; k <= NB; ++k) boff[k] = a.boff[k];
         }
-        __syncthreads();
-        detect_phase<W>(a, s, bid, boff, cmax);
     }
+    __syncthreads();
+    int cmax = 0;
+    detect_phase<W>(a, s, blockIdx.x, boff, cmax);
     cmax = block_max(cmax, s.red);
     // with wake flags a colour at or below the current maximum needs no device atomic
     if (threadIdx.x == 0 && cmax > 0 && (!W || cmax > ld_agent(&a.ctl->maxcolor)))
         atomicMax(&a.ctl->maxcolor, cmax);
 }
 
-// Flag-scanning conflict test alone (wake flags, no row longer than WAKE_DEG).
+// Flag-scanning conflict test of a round with wake flags (the rows longer than WAKE_DEG,
+// if any, are tested by k_detect<true> in a launch of their own: measured faster than
+// one launch for both, whose register allocation suits neither).
 template <bool C>
 __global__ __launch_bounds__(WG) void k_detect_flags(RoundArgs a) {
     __shared__ int ids[WAVES][VPW];

@@ -24,6 +24,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "csrcolor", "tun
 
 # knob -> values tried (0 = library default)
 KNOBS: List[Tuple[str, Sequence[int]]] = [
+    ("wake", (0, 1, -1)),
     ("firstfit", (3, 2, 1)),
     ("mode", (1, 3)),
     ("t_wave", (1024, 256, 128)),
