@@ -7,8 +7,8 @@ synthetic graph whose CSR is already resident in HBM; the workload defaults to t
 
 Printed (one JSON line on stdout): value = arcs / second over the K timed steps;
 ``roofline`` for the dominant kernel (FirstFit) from its algorithmic bytes and its
-average launch time, measured with HIP events on the library's stream during a
-second pass of K steps; ``cpu_baseline`` = the serial CPU oracle on the same graph.
+average launch time, measured during a second pass of K steps with HIP events that
+each kernel dispatch on the library's stream stamps at its start and end; ``cpu_baseline`` = the serial CPU oracle on the same graph.
 """
 from __future__ import annotations
 

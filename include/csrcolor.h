@@ -141,7 +141,9 @@ typedef struct {
     int32_t max_degree;     /* out */
     int64_t nnz;            /* out: rowptr[n] */
     int32_t cap;            /* in: capacity of the per-round arrays */
-    int32_t time_kernels;   /* in: 1 = bracket every kernel launch with HIP events on `stream` */
+    int32_t time_kernels;   /* in: 1 = time every kernel launch on `stream`: per-round kernels by events
+                               that the dispatch itself stamps (hipExtLaunchKernelGGL), setup groups by
+                               events recorded around them */
     int64_t *wsize;         /* out: |W_r| for r = 0 .. min(rounds, cap)-1 */
     int64_t *arcs;          /* out: sum of row lengths over W_r (arcs scanned by FirstFit); for
                                CSRCOLOR_ALGO_SGR_TOPO and CSRCOLOR_ALGO_JP only arcs[0] (= rowptr[n]) is

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcsrcolor.so")
 SOURCES = ["csrcolor_api.hip"]
-HEADERS = ["sgr_device.h", "sgr_kernels.h", "sgr_round.h", "sgr_topo.h"]
+HEADERS = ["sgr_device.h", "sgr_kernels.h", "sgr_round.h", "sgr_topo.h", "sgr_wake.h"]   # included by the source
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

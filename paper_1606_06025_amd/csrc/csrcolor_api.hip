@@ -9,6 +9,7 @@
 // each degree bucket owns a fixed segment of both worklist arrays whose size is the
 // number of vertices of that bucket, so no push can overflow.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cstdio>
@@ -76,21 +77,28 @@ struct Workspace {
     std::mutex mu;
 };
 
-// Brackets kernel launches with HIP events on the workspace stream when enabled.
+// Times kernel launches on the workspace stream when enabled.  A single kernel goes
+// through hipExtLaunchKernelGGL, whose start and stop events take the timestamps of
+// the dispatch itself (the kernel's own execution time, as a kernel trace reports
+// it); a group of launches is bracketed by events recorded on the stream.
 struct KTimer {
     Workspace* w;
     bool on;
     size_t next = 0;
     std::vector<std::pair<size_t, size_t>> spans[3];   // 0 setup, 1 assign, 2 detect
     KTimer(Workspace* ws, bool enable) : w(ws), on(enable) {}
-    size_t mark() {
+    size_t event() {
         if (next == w->evs.size()) {
             hipEvent_t e;
             if (hipEventCreate(&e) != hipSuccess) { on = false; return 0; }
             w->evs.push_back(e);
         }
-        (void)hipEventRecord(w->evs[next], w->stream);
         return next++;
+    }
+    size_t mark() {
+        const size_t i = event();
+        if (on) (void)hipEventRecord(w->evs[i], w->stream);
+        return i;
     }
     template <class F>
     void run(int kind, F&& launch) {
@@ -99,6 +107,20 @@ struct KTimer {
         launch();
         const size_t b = mark();
         if (on) spans[kind].push_back({a, b});
+    }
+    template <class K, class... A>
+    void kern(int kind, K kernel, int grid, int block, A... args) {
+        if (on) {
+            const size_t a = event();
+            const size_t b = event();
+            if (on) {
+                hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, w->stream, w->evs[a], w->evs[b], 0,
+                                      args...);
+                spans[kind].push_back({a, b});
+                return;
+            }
+        }
+        kernel<<<grid, block, 0, w->stream>>>(args...);
     }
     double total_ms(int kind, int* count) const {
         double t = 0;
@@ -423,7 +445,6 @@ struct Job {
 // sizes are read back every few rounds (2, 4, 8, ... up to sync_every).  Rounds
 // launched past the end find empty queues and do nothing.
 int drive_loop(Workspace* w, Job& J, RoundArgs& a, int ub[NB], int budget, KTimer& T) {
-    hipStream_t st = w->stream;
     int par = 1;             // parity of the worklist holding W of the next round
     const bool jp = a.rule == RULE_JP;
     long long launched = jp ? 0 : 1;   // rounds enqueued so far (SGR round 1 is k_round1)
@@ -449,16 +470,16 @@ int drive_loop(Workspace* w, Job& J, RoundArgs& a, int ub[NB], int budget, KTime
             a.wl_out = w->wl[par ^ 1];
             if (jp) {
                 a.jpc = (int)launched + 1;    // colour of this JP round
-                T.run(1, [&] { k_jp_prep<<<1, 256, 0, st>>>(a.ctl, a.par_out, a.lbs, grid); });
+                T.kern(1, k_jp_prep, 1, 256, a.ctl, a.par_out, a.lbs, grid);
             } else {
                 RoundArgs aa = a;
                 for (int b = 0; b <= NB; ++b) aa.boff[b] = aboff[b];
-                T.run(1, [&] { k_assign<<<agrid, WG, 0, st>>>(aa); });
+                T.kern(1, k_assign, agrid, WG, aa);
             }
-            T.run(2, [&] { k_detect<false><<<grid, WG, 0, st>>>(a); });
+            T.kern(2, k_detect<false>, grid, WG, a);
             if (a.pushff && ub[BSPLIT] > 0) {
                 const int pg = std::min(ub[BSPLIT], budget);
-                T.run(2, [&] { k_push<false><<<pg, WG, 0, st>>>(a); });
+                T.kern(2, k_push<false>, pg, WG, a);
             }
             par ^= 1;
             ++launched;
@@ -512,13 +533,13 @@ int drive_wake(Workspace* w, Job& J, RoundArgs& a, int budget, bool big, int nhu
             a.wl_in = w->wl[par];
             a.wl_out = w->wl[par ^ 1];
             a.wround = (int)r;
-            if (a.ubytes) T.run(1, [&] { k_wassign<true><<<a.gdense, WG, 0, st>>>(a); });
-            else T.run(1, [&] { k_wassign<false><<<a.gdense, WG, 0, st>>>(a); });
-            if (a.ubytes) T.run(2, [&] { k_detect_flags<true><<<a.gdense, WG, 0, st>>>(a); });
-            else T.run(2, [&] { k_detect_flags<false><<<a.gdense, WG, 0, st>>>(a); });
+            if (a.ubytes) T.kern(1, k_wassign<true>, a.gdense, WG, a);
+            else T.kern(1, k_wassign<false>, a.gdense, WG, a);
+            if (a.ubytes) T.kern(2, k_detect_flags<true>, a.gdense, WG, a);
+            else T.kern(2, k_detect_flags<false>, a.gdense, WG, a);
             // the worklists of the long rows, if any, in a launch of their own
-            if (big) T.run(2, [&] { k_detect<true><<<budget, WG, 0, st>>>(a); });
-            if (nhub > 0) T.run(2, [&] { k_push<true><<<pgrid, WG, 0, st>>>(a); });
+            if (big) T.kern(2, k_detect<true>, budget, WG, a);
+            if (nhub > 0) T.kern(2, k_push<true>, pgrid, WG, a);
             par ^= 1;
             ++r;
         }
@@ -654,13 +675,9 @@ int drive_topo(Workspace* w, Job& J, int budget, int st_cap, KTimer& T) {
     int k = 2;
     for (;;) {
         for (int i = 0; i < k; ++i) {
-            T.run(1, [&] {
-                k_topo_assign<<<grid, WG, 0, st>>>(n, J.rowptr, J.colidx, w->X, w->ctl, par, wsz, st_cap);
-            });
-            T.run(2, [&] {
-                k_topo_detect<<<grid, WG, 0, st>>>(n, J.rowptr, J.colidx, w->X, J.colors_out, w->ctl, par,
-                                                   J.sorted, J.opt.rule);
-            });
+            T.kern(1, k_topo_assign, grid, WG, n, J.rowptr, (const int*)J.colidx, w->X, w->ctl, par, wsz, st_cap);
+            T.kern(2, k_topo_detect, grid, WG, n, J.rowptr, J.colidx, w->X, J.colors_out, w->ctl, par, J.sorted,
+                   J.opt.rule);
             par ^= 1;
             ++launched;
         }

@@ -33,6 +33,8 @@
 namespace csrcolor {
 
 constexpr int VPW = 512;   // most vertices per wavefront in the flag scans (8 per lane)
+constexpr int TQ = 2;      // quads of colidx per lane and pass in the conflict test
+constexpr int WQ = 2;      // the same in the walk that wakes sleepers
 
 // Smallest free colour of v from its push-mode flags: the first clear flag at or after
 // position rowptr[v] + v (flags before it count as set); one exists within deg(v) + 1.
@@ -107,11 +109,11 @@ __device__ __forceinline__ void wake_children(const RoundArgs& a, bool on, int u
         if (lane >= off) incl += t;
     }
     const int total = __shfl(incl, 63, 64);
-    // two quads per lane per pass (items lane and 64 + lane), loads in flight together
-    for (int base = 0; base < total; base += 128) {
-        int q[2], uj[2], bj[2], ej[2];
+    // WQ quads per lane per pass (items lane, 64 + lane, ...), loads in flight together
+    for (int base = 0; base < total; base += 64 * WQ) {
+        int q[WQ], uj[WQ], bj[WQ], ej[WQ];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < WQ; ++t) {
             const int item = base + 64 * t + lane;
             int j = 0;
 #pragma unroll
@@ -123,9 +125,9 @@ __device__ __forceinline__ void wake_children(const RoundArgs& a, bool on, int u
             bj[t] = __shfl(beg, j, 64);
             ej[t] = __shfl(end, j, 64);
         }
-        int w[2][4];
+        int w[WQ][4];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < WQ; ++t) {
             if (base + 64 * t + lane < total) {
                 load_quad(a.colidx, a.nnz, bj[t], ej[t], q[t], w[t]);
             } else {
@@ -133,22 +135,22 @@ __device__ __forceinline__ void wake_children(const RoundArgs& a, bool on, int u
                 for (int k = 0; k < 4; ++k) w[t][k] = -1;
             }
         }
-        int h[2][4];
+        int h[WQ][4];
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+        for (int t = 0; t < WQ; ++t)
 #pragma unroll
             for (int k = 0; k < 4; ++k) h[t][k] = w[t][k] > uj[t] ? a.hint[w[t][k]] : -1;
         // a hint equal to u (no FLAG) is held only by an uncoloured vertex of at most
         // WAKE_DEG arcs: settling clears a hint and long rows' hints carry FLAG
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+        for (int t = 0; t < WQ; ++t)
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 if (w[t][k] > uj[t] && h[t][k] == uj[t]) a.aflag[w[t][k]] = 1;
         if (C) {
             // colidx entries, hints of the higher ones, the sleepers' test flags
 #pragma unroll
-            for (int t = 0; t < 2; ++t)
+            for (int t = 0; t < WQ; ++t)
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
                     nb += (w[t][k] >= 0 ? 4 : 0) + (w[t][k] > uj[t] ? 4 : 0) +
@@ -268,16 +270,24 @@ __device__ __forceinline__ void test_flagged(const RoundArgs& a, const int* ids,
             if (lane >= off) incl += t;
         }
         const int total = __shfl(incl, 63, 64);
-        // two quads per lane per pass (items lane and 64 + lane), their loads and colour
+        // TQ quads per lane per pass (items lane, 64 + lane, ...), their loads and colour
         // gathers in flight together; the quads of the last pass stay in registers: when
         // one pass covers every row, the winners push from them without reading their rows
         // again
-        int w[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};
-        int j[2] = {0, 0}, vj[2] = {-1, -1}, cj[2] = {0, 0};
-        for (int base = 0; base < total; base += 128) {
-            int q[2], bj[2], ej[2];
+        int w[TQ][4];
+        int j[TQ], vj[TQ], cj[TQ];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < TQ; ++u) {
+            j[u] = 0;
+            vj[u] = -1;
+            cj[u] = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) w[u][k] = -1;
+        }
+        for (int base = 0; base < total; base += 64 * TQ) {
+            int q[TQ], bj[TQ], ej[TQ];
+#pragma unroll
+            for (int u = 0; u < TQ; ++u) {
                 const int item = base + 64 * u + lane;
                 int jj = 0;
 #pragma unroll
@@ -292,7 +302,7 @@ __device__ __forceinline__ void test_flagged(const RoundArgs& a, const int* ids,
                 ej[u] = __shfl(end, jj, 64);
             }
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
+            for (int u = 0; u < TQ; ++u) {
                 if (base + 64 * u + lane < total) {
                     load_quad(a.colidx, a.nnz, bj[u], ej[u], q[u], w[u]);
                 } else {
@@ -300,13 +310,13 @@ __device__ __forceinline__ void test_flagged(const RoundArgs& a, const int* ids,
                     for (int k = 0; k < 4; ++k) w[u][k] = -1;
                 }
             }
-            int x[2][4];
+            int x[TQ][4];
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
+            for (int u = 0; u < TQ; ++u)
 #pragma unroll
                 for (int k = 0; k < 4; ++k) x[u][k] = (w[u][k] >= 0 && w[u][k] < vj[u]) ? a.X[w[u][k]] : 0;
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
+            for (int u = 0; u < TQ; ++u) {
                 unsigned found = 0;
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
@@ -337,13 +347,13 @@ __device__ __forceinline__ void test_flagged(const RoundArgs& a, const int* ids,
                 if (C) nb += 17;
             }
         }
-        if (total <= 128) {
+        if (total <= 64 * TQ) {
             // item lane (+ 64 u): its quad belongs to vertex j[u], a winner when no conflict
             // was found
             PushCtx Q = P;
             Q.loaded = true;
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
+            for (int u = 0; u < TQ; ++u) {
                 if (64 * u + lane < total && slot[j[u]] == 0) {
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
