@@ -1,8 +1,8 @@
 // Host driver and C-ABI of the speculative-greedy colouring library.
 //
 // One colouring (Sec. 3.1, Algorithm Data-GC):
-//   k_init -> k_validate_rows -> [read back: errors, degree histogram, max degree]
-//   -> k_validate_arcs (+ k_check_symmetric) -> [read back: errors, row order]
+//   k_init -> k_validate_rows -> k_validate_arcs -> [read back: errors, degree
+//   histogram, max degree, row order] (-> k_check_symmetric -> [read back])
 //   -> k_round1 -> { k_assign ; k_detect } per round, the worklist length read back
 //   every few rounds -> [read back: colour count].
 // Worklists are double-buffered by round parity (Sec. 3.1, swap of W_in / W_out);
@@ -877,12 +877,12 @@ int run_job(Workspace* w, Job& J, const long long* voff, int G) {
     KTimer T(w, J.stats && J.stats->time_kernels);
     T.run(0, [&] { k_init<<<1, WG, 0, st>>>(w->ctl); });
     const int vblocks = (int)std::min<long long>(((long long)n + WG - 1) / WG, (long long)cus * 4);
-    T.run(0, [&] {
-        k_validate_rows<<<std::max(vblocks, 1), WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl, twave,
-                                                             J.opt.tsplit);
-    });
-    // the arc pass skips itself when the row pass found an error, so one read-back covers both
-    T.run(0, [&] { k_validate_arcs<<<cus * 4, WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl); });
+    const int rblocks = (int)std::max<long long>(
+        1, std::min<long long>(((long long)n + WG * VROWS - 1) / (WG * VROWS), (long long)cus * 4));
+    T.kern(0, k_validate_rows, rblocks, WG, n, J.rowptr, J.colidx, w->ctl, twave, J.opt.tsplit);
+    // the arc pass skips itself when the vertex pass found an error, so one read-back
+    // covers both
+    T.kern(0, k_validate_arcs, cus * 4, WG, n, J.rowptr, J.colidx, w->ctl);
     if (voff) k_validate_batch<<<std::min(G, cus * 16), WG, 0, st>>>(G, n, voff, J.rowptr, J.colidx, w->ctl);
     HIP_TRY(hipGetLastError());
     if ((rc = read_ctl(w))) return rc;

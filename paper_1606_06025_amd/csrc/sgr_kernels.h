@@ -17,32 +17,65 @@ __global__ void k_init(Ctl* ctl) {
 }
 
 // ---------------------------------------------------------------------------
-// Structural validation, degree histogram and row-order detection.
-// Vertex pass: rowptr[0] == 0, 0 <= rowptr[v] <= rowptr[v+1] <= rowptr[n];
-// counts descents colidx[e] < colidx[e-1] at positions e that start a row.
+// Structural validation, degree histogram and row-order detection, two launches.
+// Vertex pass: rowptr[0] == 0, 0 <= rowptr[v] <= rowptr[v+1] <= rowptr[n]; degree
+// histogram, largest degree, arcs of the rows longer than WAKE_DEG; counts descents
+// colidx[e] < colidx[e-1] at positions e that start a non-empty row.
+// Arc pass, only once the vertex pass found rowptr consistent (so [0, rowptr[n]) is
+// the caller's colidx extent): colidx[e] in [0, n); counts all descents.  Rows are
+// sorted iff both descent counts agree.
 // ---------------------------------------------------------------------------
+constexpr int VROWS = 4;   // vertices per thread and loop pass of the vertex pass
+constexpr int VQUADS = 4;  // 16-byte quads of colidx per lane and loop pass of the arc pass
+
 __global__ __launch_bounds__(WG) void k_validate_rows(int n, const int* __restrict__ rowptr,
-                                                      const int* __restrict__ colidx, Ctl* ctl,
-                                                      int twave, int tsplit) {
+                                                      const int* __restrict__ colidx, Ctl* ctl, int twave,
+                                                      int tsplit) {
     const int nnz = rowptr[n];
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->nnz = nnz;
     int mydeg = 0;
     int hist[NB] = {};
     int bad = 0, desc = 0, chunks = 0;
     long long big = 0;
-    for (long long v = (long long)blockIdx.x * WG + threadIdx.x; v < n; v += (long long)gridDim.x * WG) {
-        const int beg = rowptr[v], end = rowptr[v + 1];
-        const bool ok = beg >= 0 && beg <= end && end <= nnz && (v != 0 || beg == 0);
-        if (!ok) { bad = 1; continue; }
-        const int deg = end - beg;
-        mydeg = max(mydeg, deg);
-        if (deg > WAKE_DEG) big += deg;
-        if (deg > 0) {
-            const int bk = bucket_of(deg, twave, tsplit);
-            if (bk == BSPLIT) chunks += split_chunks(deg);
+    const long long stride = (long long)gridDim.x * WG * VROWS;
+    for (long long v0 = (long long)blockIdx.x * WG * VROWS + threadIdx.x; v0 < n; v0 += stride) {
+        int beg[VROWS], end[VROWS], c0[VROWS], c1[VROWS];
+        bool ok[VROWS];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) hist[b] += (bk == b);
-            if (beg > 0 && colidx[beg] < colidx[beg - 1]) desc++;
+        for (int k = 0; k < VROWS; ++k) {
+            const long long v = v0 + (long long)k * WG;
+            beg[k] = 0;
+            end[k] = 0;
+            if (v < n) {
+                beg[k] = rowptr[v];
+                end[k] = rowptr[v + 1];
+            }
+            ok[k] = beg[k] >= 0 && beg[k] <= end[k] && end[k] <= nnz && (v != 0 || beg[k] == 0);
+        }
+#pragma unroll
+        for (int k = 0; k < VROWS; ++k) {
+            c0[k] = 0;
+            c1[k] = 0;
+            // a non-empty valid row: colidx[beg] and colidx[beg - 1] lie in [0, nnz)
+            if (ok[k] && end[k] > beg[k] && beg[k] > 0) {
+                c0[k] = colidx[beg[k]];
+                c1[k] = colidx[beg[k] - 1];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < VROWS; ++k) {
+            if (v0 + (long long)k * WG >= n) continue;
+            if (!ok[k]) { bad = 1; continue; }
+            const int deg = end[k] - beg[k];
+            mydeg = max(mydeg, deg);
+            if (deg > WAKE_DEG) big += deg;
+            if (deg > 0) {
+                const int bk = bucket_of(deg, twave, tsplit);
+                if (bk == BSPLIT) chunks += split_chunks(deg);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) hist[b] += (bk == b);
+                if (c0[k] < c1[k]) desc++;
+            }
         }
     }
     if (nnz < 0 || (colidx == nullptr && nnz != 0)) bad = 1;
@@ -67,17 +100,51 @@ __global__ __launch_bounds__(WG) void k_validate_rows(int n, const int* __restri
     }
 }
 
-// Arc pass: colidx in [0, n); counts all descents.  Launched only after the vertex
-// pass found rowptr consistent, so [0, rowptr[n]) is the caller's colidx extent.
+// Arc pass: the wavefronts stream colidx as aligned 16-byte quads (quad q holds the
+// positions 4q - mis .. 4q - mis + 3, mis = the array's offset in ints from a 16-byte
+// boundary; positions outside [0, nnz) are ignored, and they share their quad's 16
+// bytes with a valid position).  The position before a quad's first one is the last
+// one of the previous lane's quad, or read once per wavefront.
 __global__ __launch_bounds__(WG) void k_validate_arcs(int n, const int* __restrict__ rowptr,
                                                       const int* __restrict__ colidx, Ctl* ctl) {
     if (ctl->err) return;   // rowptr already failed: [0, rowptr[n]) is not trustworthy
     const long long nnz = rowptr[n];
+    const int blk = (int)blockIdx.x, nblk = (int)gridDim.x;
     int bad = 0, desc = 0;
-    for (long long e = (long long)blockIdx.x * WG + threadIdx.x; e < nnz; e += (long long)gridDim.x * WG) {
-        const int w = colidx[e];
-        if ((unsigned)w >= (unsigned)n) bad = 1;
-        if (e > 0 && w < colidx[e - 1]) desc++;
+    if (nnz > 0) {
+        const int lane = __lane_id();
+        const int mis = (int)((reinterpret_cast<uintptr_t>(colidx) >> 2) & 3);
+        const int4* base = reinterpret_cast<const int4*>(colidx - mis);
+        const long long nq = (nnz + mis + 3) >> 2;
+        const long long step = (long long)nblk * WAVES * 64 * VQUADS;
+        for (long long q0 = ((long long)blk * WAVES + (threadIdx.x >> 6)) * 64 * VQUADS; q0 < nq; q0 += step) {
+            int4 val[VQUADS];
+#pragma unroll
+            for (int u = 0; u < VQUADS; ++u) {
+                const long long q = q0 + 64 * u + lane;
+                val[u] = q < nq ? base[q] : make_int4(0, 0, 0, 0);
+            }
+            const long long e00 = 4 * q0 - mis;   // position of the wavefront's first element
+            const int before = e00 > 0 ? colidx[e00 - 1] : 0;
+#pragma unroll
+            for (int u = 0; u < VQUADS; ++u) {
+                const long long q = q0 + 64 * u + lane;
+                int prev = __shfl_up(val[u].w, 1, 64);
+                const int last_prev_u = u > 0 ? __shfl(val[u > 0 ? u - 1 : 0].w, 63, 64) : before;
+                if (lane == 0) prev = last_prev_u;
+                const int x[4] = {val[u].x, val[u].y, val[u].z, val[u].w};
+                const long long e0 = 4 * q - mis;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const long long e = e0 + k;
+                    if (q < nq && e >= 0 && e < nnz) {
+                        if ((unsigned)x[k] >= (unsigned)n) bad = 1;
+                        const int pv = k == 0 ? prev : x[k - 1];
+                        if (e > 0 && x[k] < pv) desc++;
+                    }
+                }
+            }
+        }
     }
     __shared__ int red[WAVES];
     bad = block_max(bad, red);

@@ -222,6 +222,44 @@ def test_batched_rejects_cross_graph_arcs(dev):
     assert e.value.status == L.EBADCSR
 
 
+@pytest.mark.parametrize("shift", [0, 1, 2, 3])
+def test_validation_at_every_alignment(dev, shift):
+    """The arc check streams colidx as aligned 16-byte quads: at every offset of the
+    array it finds an out-of-range first or last entry, and a descent inside a row at
+    quad, wavefront and loop-pass boundaries (unsorted rows, same colouring)."""
+    import oracle
+    from paper_1606_06025_amd import _lib as L, api
+    g = gg.erdos_renyi(6000, 60000, shift + 1)
+    ref = oracle.sgr(g.n, g.rowptr, g.colidx)
+    rp = torch.from_numpy(g.rowptr).to(dev)
+
+    def view(ci):
+        buf = torch.zeros(len(ci) + 8, dtype=torch.int32, device=dev)
+        buf[shift:shift + len(ci)] = torch.from_numpy(ci).to(dev)
+        v = buf[shift:shift + len(ci)]
+        assert v.data_ptr() % 16 == 4 * shift
+        return v
+
+    colors, nc, st = api.color(rp, view(g.colidx), stats=True)
+    assert st.rows_sorted and nc == ref.ncolors
+    row = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    for t in [1, 3, 4, 5, 255, 256, 257, 1023, 1024, 4095, 65536, g.nnz - 1]:
+        p = t - 1 if row[t - 1] == row[t] else t - 2     # swap positions p, p + 1 of one row
+        assert row[p] == row[p + 1] and g.colidx[p] < g.colidx[p + 1]
+        ci = g.colidx.copy()
+        ci[p], ci[p + 1] = ci[p + 1], ci[p]
+        colors, nc, st = api.color(rp, view(ci), stats=True)
+        assert not st.rows_sorted, t
+        assert (colors.cpu().numpy() == ref.colors).all() and nc == ref.ncolors
+    for pos in [0, g.nnz - 1]:
+        for bad in [-1, g.n]:
+            ci = g.colidx.copy()
+            ci[pos] = bad
+            with pytest.raises(L.CsrColorError) as e:
+                api.color(rp, view(ci))
+            assert e.value.status == L.EBADCSR
+
+
 def _degree_ladder(degs, seed=0):
     """A graph with one hub per requested degree (hub joined to its own leaves) plus a
     random sprinkle of extra edges, so rows of every bucket boundary occur at
