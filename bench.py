@@ -6,9 +6,10 @@ synthetic graph whose CSR is already resident in HBM; the workload defaults to t
 27-point stencil on a 128^3 grid (2,097,152 vertices, 53,645,816 arcs).
 
 Printed (one JSON line on stdout): value = arcs / second over the K timed steps;
-``roofline`` for the dominant kernel (FirstFit) from its algorithmic bytes and its
+``roofline`` for the dominant kernel (by measured time) from its algorithmic bytes and its
 average launch time, measured during a second pass of K steps with HIP events that
-each kernel dispatch on the library's stream stamps at its start and end; ``cpu_baseline`` = the serial CPU oracle on the same graph.
+each kernel dispatch on the library's stream stamps at its start and end;
+``cpu_baseline`` = the serial CPU oracle on the same graph.
 """
 from __future__ import annotations
 
