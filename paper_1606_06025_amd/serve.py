@@ -78,9 +78,11 @@ class Backend:
 
 class HipBackend(Backend):
     """Graphs live in device tensors; a batch is one csrcolor_color_multi call on the
-    slot's stream.  Uploads go through freshly pinned host copies on a stream of their
-    own (so they overlap the batches running on the slots), each followed by an event
-    the batch's stream waits for; a batch's colours come back in one pinned buffer."""
+    slot's stream.  Uploads are copies from the caller's (pageable) arrays on a stream of
+    their own, so they overlap the batches running on the slots, each followed by an
+    event the batch's stream waits for; a batch's colours come back in one pinned
+    buffer.  (Pinning every request's arrays first costs more than it saves: the pinned
+    allocation and its page locking ran at a fraction of the copy engine's rate.)"""
 
     def __init__(self, nslots: int = 2, device: str = "cuda:0", opts=None):
         import torch
@@ -96,15 +98,15 @@ class HipBackend(Backend):
     def upload(self, rowptr, colidx):
         torch = self.torch
         n = max(len(rowptr) - 1, 0)
-        hrp = torch.from_numpy(np.ascontiguousarray(rowptr, dtype=np.int32)).pin_memory()
-        hci = torch.from_numpy(np.ascontiguousarray(colidx, dtype=np.int32)).pin_memory()
+        hrp = torch.from_numpy(np.ascontiguousarray(rowptr, dtype=np.int32))
+        hci = torch.from_numpy(np.ascontiguousarray(colidx, dtype=np.int32))
         with torch.cuda.stream(self.up_stream):
-            rp = hrp.to(self.device, non_blocking=True)
-            ci = hci.to(self.device, non_blocking=True)
+            # from pageable memory the copy has taken the data when the call returns
+            rp = hrp.to(self.device)
+            ci = hci.to(self.device)
             out = torch.empty(n, dtype=torch.int32, device=self.device)
             ev = torch.cuda.Event()
             ev.record(self.up_stream)
-        # the pinned copies stay referenced until the batch has waited for the event
         return (rp, ci, out, int(len(colidx)), ev, (hrp, hci))
 
     def run_batch(self, slot, handles):
