@@ -47,6 +47,7 @@ class Request:
     started: float = -1.0
     done_time: float = -1.0
     batch_size: int = 0
+    group: int = 0                   # batching class: bit length of the largest degree
     _event: threading.Event = dataclasses.field(default_factory=threading.Event)
 
     def wait(self, timeout: Optional[float] = None) -> bool:
@@ -158,8 +159,10 @@ class ColoringServer:
     def submit(self, rowptr: np.ndarray, colidx: np.ndarray, arrival: Optional[float] = None) -> Request:
         n = len(rowptr) - 1
         nnz = int(rowptr[-1]) if n > 0 else 0
+        maxdeg = int(np.max(np.diff(np.asarray(rowptr, dtype=np.int64)))) if n > 0 else 0
         with self._cv:
-            req = Request(self._next_id, n, nnz, self.clock() if arrival is None else arrival)
+            req = Request(self._next_id, n, nnz, self.clock() if arrival is None else arrival,
+                          group=max(maxdeg, 0).bit_length())
             self._next_id += 1
             if footprint_bytes(n, nnz) > self.budget:
                 req.error = "request larger than the HBM budget"
@@ -230,15 +233,27 @@ class ColoringServer:
                         self._admitted.append(req)
                 while self._can_dispatch():
                     slot = self._free_slots.pop(0)
-                    batch, arcs = [], 0
-                    while self._admitted and len(batch) < self.max_batch:
-                        nxt = self._admitted[0]
-                        if batch and arcs + nxt.nnz > self.max_batch_arcs:
-                            break
-                        batch.append(self._admitted.popleft())
-                        arcs += nxt.nnz
+                    batch = self._take_batch()
                     self._slot_work[slot] = batch
                     self._slot_cv[slot].notify_all()
+
+    def _take_batch(self) -> List[Request]:
+        """The oldest admitted request and, in arrival order, the others of its batching
+        class or an adjacent one (caller holds the lock).  A batch runs as many rounds as
+        its slowest graph, and the rounds grow with the largest degree (hubs), so graphs
+        of like degree share a batch rather than small ones waiting on a hub graph."""
+        first = self._admitted.popleft()
+        batch, arcs, keep = [first], first.nnz, collections.deque()
+        while self._admitted:
+            nxt = self._admitted.popleft()
+            if (len(batch) < self.max_batch and abs(nxt.group - first.group) <= 1
+                    and arcs + nxt.nnz <= self.max_batch_arcs):
+                batch.append(nxt)
+                arcs += nxt.nnz
+            else:
+                keep.append(nxt)
+        self._admitted = keep
+        return batch
 
     def _can_admit(self) -> bool:
         if not self._pending:

@@ -79,6 +79,34 @@ def test_results_equal_alone_and_budget_respected(oracle_mod):
     assert s["count"] == len(gs) and s["p99_ms"] >= s["p50_ms"] > 0
 
 
+class RecordingBackend(OracleBackend):
+    def run_batch(self, slot, handles):
+        self.groups = getattr(self, "groups", [])
+        self.groups.append([int(np.diff(rp).max()).bit_length() for rp, _ in handles])
+        return super().run_batch(slot, handles)
+
+
+def test_batches_group_graphs_of_like_degree(oracle_mod):
+    """Interleaved hub graphs (R-MAT) and flat graphs (cycles, small ER): every batch
+    holds the oldest waiting request and only graphs whose largest degree has a bit
+    length within one of its own; all results are still the stand-alone colourings."""
+    gs = []
+    for i in range(24):
+        gs.append(gg.rmat(10, 16, i) if i % 2 == 0 else gg.cycle(50 + i))
+    be = RecordingBackend(nslots=1, delay=0.01)
+    with serve.ColoringServer(be, 1 << 40, max_batch=8) as srv:
+        reqs = [srv.submit(g.rowptr, g.colidx) for g in gs]
+        for r in reqs:
+            assert r.wait(60)
+    for b in be.groups:
+        assert max(b) - min(b) <= 2 and all(abs(x - b[0]) <= 1 for x in b), be.groups
+    assert max(len(b) for b in be.groups) > 1
+    assert sorted(sum(be.groups, [])) == sorted(int(np.diff(g.rowptr).max()).bit_length() for g in gs)
+    for g, r in zip(gs, reqs):
+        ref = oracle_mod.sgr(g.n, g.rowptr, g.colidx)
+        assert r.error is None and (r.colors == ref.colors).all()
+
+
 def test_oversize_request_rejected_others_served():
     gs = _graphs(6, seed=3)
     big = gg.erdos_renyi(20000, 200000, 5)
