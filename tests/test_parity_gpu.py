@@ -260,6 +260,35 @@ def test_validation_at_every_alignment(dev, shift):
             assert e.value.status == L.EBADCSR
 
 
+@pytest.mark.parametrize("case", ["wake", "classic", "topo", "jp"])
+def test_kernel_timing_stats(dev, case):
+    """With time_kernels every per-round kernel is launched with start and stop events
+    its dispatch stamps: the colouring is unchanged, every launch is counted, and the
+    summed kernel times are positive and within the call's wall time."""
+    import time
+    import oracle
+    from paper_1606_06025_amd import api
+    g = gg.stencil27(24, 20, 16) if case in ("wake", "topo") else gg.rmat(13, 16, 2)
+    kw = {"wake": dict(wake=1), "classic": dict(wake=-1), "topo": dict(algorithm=1),
+          "jp": dict(algorithm=2, seed=5)}[case]
+    ref = (oracle.jp(g.n, g.rowptr, g.colidx, seed=5) if case == "jp"
+           else oracle.sgr(g.n, g.rowptr, g.colidx))
+    rp = torch.from_numpy(g.rowptr).to(dev)
+    ci = torch.from_numpy(g.colidx).to(dev)
+    opts = api.make_opts(**kw)
+    api.color(rp, ci, opts=opts)                       # workspace warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    colors, nc, st = api.color(rp, ci, opts=opts, stats=True, time_kernels=True)
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    assert (colors.cpu().numpy() == ref.colors).all() and nc == ref.ncolors
+    assert st.n_assign > 0 and st.n_detect > 0
+    assert st.n_detect >= ref.rounds - 1
+    for ms in (st.ms_setup, st.ms_assign, st.ms_detect):
+        assert np.isfinite(ms) and ms > 0
+    assert st.ms_setup + st.ms_assign + st.ms_detect <= wall_ms
+
+
 def _degree_ladder(degs, seed=0):
     """A graph with one hub per requested degree (hub joined to its own leaves) plus a
     random sprinkle of extra edges, so rows of every bucket boundary occur at
