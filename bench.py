@@ -604,8 +604,11 @@ def main() -> int:
             # arcs pushed by winners of rounds >= 2 (every vertex pushes its row once; the
             # round-1 winners' rows are pushed by the round-1 kernel)
             pushed = int(st.arcs[1]) if len(st.arcs) > 1 else 0
+            # the conflict-test phase: k_detect, and in push mode the k_push launches of the
+            # split rows' winners (timed with it; its bytes include every pushed arc)
             kb = {"k_assign": (assign_bytes(st.wsize, st.arcs, push) * args.steps, tot_a, na),
-                  "k_detect": (detect_bytes(st.wsize, ocr, pushed, push, byte_flags) * args.steps, tot_d, nd)}
+                  ("k_detect+k_push" if push else "k_detect"):
+                      (detect_bytes(st.wsize, ocr, pushed, push, byte_flags) * args.steps, tot_d, nd)}
         dom = max(kb, key=lambda k: kb[k][1])
         byts, tms, nl = kb[dom]
         launches_per_step = nl / args.steps
