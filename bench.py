@@ -493,7 +493,7 @@ def main() -> int:
         return traffic_summary(args.workload, *args.traffic_summary, copy_mib=args.copy_mib)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build colours one graph on one GPU; runs on more than one GPU "
+        print("bench.py colours one graph on one GPU; runs on more than one GPU "
               "are not supported (use --gpus 1).", file=sys.stderr)
         return 2
 
