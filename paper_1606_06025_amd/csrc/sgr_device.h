@@ -112,10 +112,30 @@ __device__ __forceinline__ void push_flag(const PushCtx& P, int u, int c, int ub
         if (P.dirty) P.dirty[u] = 1;
     }
 }
-__device__ __forceinline__ void push_colour(const PushCtx& P, int u, int c) {
+// A push reads one thing of the neighbour u first (with wake flags its colour word,
+// else its rowptr pair) and then writes its flags.  The two halves are separate so that
+// a lane pushing to several neighbours issues all the reads before any write: a read
+// that follows a write waits for the write too (the vector memory counter covers both),
+// and the writes are atomics or stores that go to memory.
+struct PushRead {
+    int a;   // wake flags (not round 1): u's colour word; else rowptr[u]
+    int b;   // rowptr[u + 1] (not read with wake flags)
+};
+__device__ __forceinline__ PushRead push_read(const PushCtx& P, int u) {
+    PushRead r;
+    if (P.rflag && !P.all_tentative) {
+        r.a = P.X[u];
+        r.b = 0;
+    } else {
+        r.a = P.rowptr[u];
+        r.b = P.rowptr[u + 1];
+    }
+    return r;
+}
+__device__ __forceinline__ void push_write(const PushCtx& P, int u, int c, PushRead r) {
     if (P.rflag && !P.all_tentative) {
         // wake flags: the colour word says whether u is settled, short (mask) or long
-        const int xu = P.X[u];
+        const int xu = r.a;
         if (P.nbytes) *P.nbytes += (P.loaded ? 0 : 4) + 4;   // colidx entry, colour
         if (xu > 0) return;
         if (xu & BIG) {
@@ -134,8 +154,8 @@ __device__ __forceinline__ void push_colour(const PushCtx& P, int u, int c) {
         }
         return;
     }
-    const int ub = P.rowptr[u];
-    const int ue = P.rowptr[u + 1];
+    const int ub = r.a;
+    const int ue = r.b;
     if (P.nbytes) *P.nbytes += (P.loaded ? 8 : 12);   // colidx entry, rowptr pair
     if (P.rflag) {
         // round 1 with wake flags: every neighbour of a winner is a loser holding colour 1;
@@ -146,6 +166,32 @@ __device__ __forceinline__ void push_colour(const PushCtx& P, int u, int c) {
         return;
     }
     push_flag(P, u, c, ub, ue);
+}
+__device__ __forceinline__ void push_colour(const PushCtx& P, int u, int c) {
+    push_write(P, u, c, push_read(P, u));
+}
+// Holds the wavefront here until x is loaded.  Placed after a group of reads and before
+// the writes that use them, it makes the one wait cover every read of the group: the
+// compiler otherwise waits again before each later use inside the writes' branches, and
+// such a wait also waits for every write issued before it.
+__device__ __forceinline__ void reads_done(int x) { asm volatile("" ::"v"(x)); }
+
+// Pushes colour c of v to the neighbours w[0..3] (entries -1 and v itself are skipped),
+// all four reads first.
+__device__ __forceinline__ void push_quad(const PushCtx& P, const int* w, int v, int c) {
+    PushRead r[4];
+    int all = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        r[k].a = 1;
+        r[k].b = 0;
+        if (w[k] >= 0 && w[k] != v) r[k] = push_read(P, w[k]);
+        all |= r[k].a | r[k].b;
+    }
+    reads_done(all);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (w[k] >= 0 && w[k] != v) push_write(P, w[k], c, r[k]);
 }
 
 // Internal rule number of the Jones-Plassmann independent-set colouring (Sec. 2.2,

@@ -146,9 +146,7 @@ __device__ __forceinline__ void push_row_coop(const PushCtx& P, int v, int c, in
     for (int q0 = 0; q0 < nq; q0 += nthr) {
         int w[4];
         load_quad(P.colidx, P.nnz, beg, end, q0 + t, w);
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (w[k] >= 0 && w[k] != v) push_colour(P, w[k], c);
+        push_quad(P, w, v, c);
     }
 }
 
@@ -184,9 +182,7 @@ __device__ __forceinline__ void push_rows_wave(const PushCtx& P, bool win, int v
         if (item < total) {
             int w[4];
             load_quad(P.colidx, P.nnz, bj, ej, q, w);
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (w[k] >= 0 && w[k] != vj) push_colour(P, w[k], cj);
+            push_quad(P, w, vj, cj);
         }
     }
 }

@@ -352,13 +352,27 @@ __device__ __forceinline__ void test_flagged(const RoundArgs& a, const int* ids,
             // was found
             PushCtx Q = P;
             Q.loaded = true;
+            // every neighbour's colour word is read before any flag is written
+            bool go[TQ];
+            PushRead r[TQ][4];
+            int all = 0;
 #pragma unroll
             for (int u = 0; u < TQ; ++u) {
-                if (64 * u + lane < total && slot[j[u]] == 0) {
+                go[u] = 64 * u + lane < total && slot[j[u]] == 0;
 #pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        if (w[u][k] >= 0 && w[u][k] != vj[u]) push_colour(Q, w[u][k], cj[u]);
+                for (int k = 0; k < 4; ++k) {
+                    r[u][k].a = 1;
+                    r[u][k].b = 0;
+                    if (go[u] && w[u][k] >= 0 && w[u][k] != vj[u]) r[u][k] = push_read(Q, w[u][k]);
+                    all |= r[u][k].a | r[u][k].b;
                 }
+            }
+            reads_done(all);
+#pragma unroll
+            for (int u = 0; u < TQ; ++u) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (go[u] && w[u][k] >= 0 && w[u][k] != vj[u]) push_write(Q, w[u][k], cj[u], r[u][k]);
             }
         } else {
             push_rows_wave(P, win, v, cv, beg, end);
