@@ -189,17 +189,22 @@ __global__ __launch_bounds__(WG) void k_wassign(RoundArgs a) {
         for (int i0 = 0; i0 < cnt; i0 += 64) {
             const int i = i0 + lane;
             const int u = i < cnt ? ids[wv][i] : -1;
+            // every read of the lane (its row bounds, colour word, mask, then the walk
+            // over its row) comes before its writes: a read issued after a write would
+            // wait for that write as well
             int beg = 0, end = 0, x = 1;
+            unsigned long long fs = 0;
             if (u >= 0) {
                 beg = a.rowptr[u];
                 end = a.rowptr[u + 1];
                 x = a.X[u];
-                a.rflag[u] = 0;
+                fs = a.Fs[u];          // used by short rows only
                 if (C) nb += 13;
             }
+            reads_done(beg ^ end ^ x ^ (int)fs ^ (int)(fs >> 32));
             const bool on = x < 0;     // flagged vertices are uncoloured; kept as a guard
+            int c = 0;
             if (on) {
-                int c;
                 if (x & BIG) {
                     int words = 0;
                     c = first_free(a, beg, u, words);
@@ -207,18 +212,21 @@ __global__ __launch_bounds__(WG) void k_wassign(RoundArgs a) {
                 } else {
                     // a short row's forbidden colours in one mask: the smallest free colour
                     // is at most 62, so the lowest clear bit exists
-                    c = __ffsll((long long)~a.Fs[u]);
+                    c = __ffsll((long long)~fs);
                     if (C) nb += 8;
                 }
+            }
+            const bool small = on && end - beg <= WAKE_DEG;
+            wake_children<C>(a, small, u, beg, end, nb);
+            if (u >= 0) a.rflag[u] = 0;
+            if (on) {
                 a.X[u] = (x & BIG) | FLAG | c;
                 if (C) nb += 4;
             }
-            const bool small = on && end - beg <= WAKE_DEG;
             if (small) {
                 a.aflag[u] = 1;
                 if (C) nb += 1;
             }
-            wake_children<C>(a, small, u, beg, end, nb);
         }
     }
     if (C) {
