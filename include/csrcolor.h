@@ -29,10 +29,13 @@
  *     HOST.  Inputs are only read; outputs must not alias inputs.
  *   - Output colours are 0-based: colors_out[v] in [0, ncolors).
  *   - Work is enqueued on `stream`.  The library keeps a per-(device, stream)
- *     workspace (about 12 bytes per vertex plus a small control block) that is
- *     grown on demand and freed by csrcolor_release_workspace(); calls on the
- *     same stream are serialised by a lock, calls on different streams do not
- *     share scratch.
+ *     workspace that is grown on demand and freed by csrcolor_release_workspace():
+ *     with the default options about 35 bytes per vertex plus 5 bytes per arc (colour
+ *     state, two worklists, conflict hints, live-list lengths and lists, byte flags of
+ *     the forbidden colours, wake flags and masks) plus the split-row scratch and a
+ *     small control block; the multi-graph call adds a copy of the union CSR and its
+ *     colours.  Calls on the same stream are serialised by a lock, calls on different
+ *     streams do not share scratch.
  *   - Errors are negative csrcolor_status values; outputs are then unspecified.
  *     Structural validation (rowptr monotone and in range, colidx in range) is
  *     always done on the device before any colouring kernel runs, so a
@@ -57,14 +60,18 @@ typedef enum {
     CSRCOLOR_EHIP = -4,       /* a HIP runtime call failed */
     CSRCOLOR_EOVERFLOW = -5,  /* sizes beyond int32 (batched totals) */
     CSRCOLOR_ENOTSYM = -6,    /* validate >= 1 and the CSR is not symmetric */
-    CSRCOLOR_ELIMIT = -7      /* round limit reached (cannot happen for a valid graph: rounds <= n) */
+    CSRCOLOR_ELIMIT = -7,     /* round limit reached (cannot happen for a valid graph: rounds <= n) */
+    CSRCOLOR_ETIMEOUT = -8    /* a device-wide barrier of the persistent rounds waited more than 8 s:
+                                 the grid was not resident (another persistent kernel held the device) */
 } csrcolor_status;
 
 /* How the rounds are driven.  Every mode gives the identical colouring. */
 typedef enum {
     CSRCOLOR_MODE_AUTO = 0,        /* library choice */
     CSRCOLOR_MODE_LOOP = 1,        /* host loop: two kernels per round, worklist size read back every few rounds */
-    CSRCOLOR_MODE_PERSISTENT = 2,  /* one cooperative kernel runs all rounds with device-wide barriers */
+    CSRCOLOR_MODE_PERSISTENT = 2,  /* device-planned: the setup results never reach the host and one
+                                      kernel runs every round after the first with device-wide
+                                      barriers (the kernel fusion of Sec. 3.3); wake flags do not apply */
     CSRCOLOR_MODE_GRAPH = 3        /* blocks of rounds captured once in a hipGraph and replayed */
 } csrcolor_mode;
 
@@ -170,13 +177,31 @@ typedef struct {
 int csrcolor_color(int32_t n, const int32_t *rowptr, const int32_t *colidx,
                    int32_t *colors_out, int32_t *ncolors, hipStream_t stream);
 
-/* As csrcolor_color with options and statistics.
- *   ncolors_host  HOST int32* (may be NULL)
- *   opts          NULL for defaults
- *   stats         NULL, or a HOST struct filled on return
- * The call synchronises `stream` before returning. */
+/* Colour one graph with options and statistics (Sec. 3.1, Algorithm Data-GC), as the
+ * boundary of an asynchronous caller: the colour count goes to device memory.
+ *   n            number of vertices (>= 0)
+ *   rowptr       DEVICE int32[n+1];  colidx DEVICE int32[rowptr[n]];  colors_out DEVICE int32[n]
+ *   ncolors_dev  DEVICE int32* (may be NULL): receives the number of colours, or, when the device
+ *                finds the input or the run at fault, the negative csrcolor_status (EBADCSR,
+ *                ENOTSYM, EINVAL, ENOMEM, ETIMEOUT, ELIMIT)
+ *   opts         NULL for defaults
+ *   stats        NULL, or a HOST struct filled on return
+ * Asynchronous (device-planned) when opts->mode is CSRCOLOR_MODE_PERSISTENT, or AUTO with
+ * stats == NULL and the SGR algorithm: the call enqueues every kernel on `stream` and returns
+ * without waiting and without host<->device copies, so it can be captured into a hipGraph and
+ * replayed.  Only the first call on a stream, and a call whose n exceeds every earlier one on
+ * that stream, reads rowptr[n] back to size the workspace (that call waits; make it before a
+ * capture).  A later graph with more arcs than the workspace was sized for fails on the device
+ * with CSRCOLOR_ENOMEM in *ncolors_dev (any synchronous call on the stream, or an asynchronous
+ * call with more vertices, sizes it again).  The run uses one persistent kernel whose
+ * workgroups must all be resident: outside a capture it is a cooperative launch; inside a
+ * capture it is a plain launch, which assumes that no other persistent kernel shares the
+ * device while the graph runs (else the run ends with CSRCOLOR_ETIMEOUT, it does not hang).
+ * With stats != NULL, or another mode, the call waits for the stream before returning (host-
+ * driven modes: LOOP, GRAPH, and AUTO with statistics), and *ncolors_dev is written before it
+ * returns.  Host-detected errors (bad arguments, allocation or launch failures) are returned. */
 int csrcolor_color_ex(int32_t n, const int32_t *rowptr, const int32_t *colidx,
-                      int32_t *colors_out, int32_t *ncolors_host,
+                      int32_t *colors_out, int32_t *ncolors_dev,
                       const csrcolor_opts *opts, csrcolor_stats *stats, hipStream_t stream);
 
 /* Colour G independent graphs stored as one block-diagonal CSR with global ids
@@ -192,7 +217,10 @@ int csrcolor_color_ex(int32_t n, const int32_t *rowptr, const int32_t *colidx,
  *   colors_out   DEVICE int32[n_total], 0-based colours local to each graph
  *   ncolors_out  DEVICE int32[G], colours used by each graph
  *   opts         NULL for defaults
- * The call synchronises `stream` before returning. */
+ * With opts->mode == CSRCOLOR_MODE_PERSISTENT the whole union is coloured device-planned in
+ * one persistent launch (the kernel fusion of Sec. 3.3) and the call returns without waiting,
+ * as csrcolor_color_ex does: a device-detected error then puts the negative status in every
+ * ncolors_out entry.  Every other mode synchronises `stream` before returning. */
 int csrcolor_color_batched(int32_t G, int32_t n_total, const int64_t *voff,
                            const int32_t *rowptr, const int32_t *colidx,
                            int32_t *colors_out, int32_t *ncolors_out,

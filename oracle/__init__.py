@@ -52,6 +52,9 @@ def _load() -> ctypes.CDLL:
         lib.oracle_sgr.restype = ctypes.c_int
         lib.oracle_sgr_rule.argtypes = [ctypes.c_int32, P, P, P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32]
         lib.oracle_sgr_rule.restype = ctypes.c_int
+        lib.oracle_sgr_capped.argtypes = [ctypes.c_int32, P, P, P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32]
+        lib.oracle_sgr_capped.restype = ctypes.c_int
         lib.oracle_sgr_topo.argtypes = [ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32]
         lib.oracle_sgr_topo.restype = ctypes.c_int
         lib.oracle_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
@@ -92,8 +95,9 @@ RULE_ID = 0        # higher id of a same-colour adjacent pair is requeued
 RULE_DEGREE = 1    # heuristic conflict resolve (Sec. 3.2): smaller degree requeued, ties by id
 
 
-def sgr(n: int, rowptr, colidx, stats_cap: int = 1 << 16, rule: int = RULE_ID) -> SGRResult:
-    """Run the serial SGR oracle.  Raises on malformed input."""
+def sgr(n: int, rowptr, colidx, stats_cap: int = 1 << 16, rule: int = RULE_ID, max_rounds: int = 0) -> SGRResult:
+    """Run the serial SGR oracle.  Raises on malformed input.  max_rounds > 0 stops after
+    that many rounds (a bounded timing sample; vertices still uncoloured read -1)."""
     lib = _load()
     rp, ci = _as_i32(rowptr), _as_i32(colidx)
     out = np.zeros(max(n, 1), dtype=np.int32)
@@ -102,8 +106,8 @@ def sgr(n: int, rowptr, colidx, stats_cap: int = 1 << 16, rule: int = RULE_ID) -
     ws = np.zeros(stats_cap, dtype=np.int64)
     af = np.zeros(stats_cap, dtype=np.int64)
     ac = np.zeros(stats_cap, dtype=np.int64)
-    rc = lib.oracle_sgr_rule(n, _ptr(rp), _ptr(ci), _ptr(out), _ptr(nc), _ptr(rr),
-                             _ptr(ws), _ptr(af), _ptr(ac), stats_cap, rule)
+    rc = lib.oracle_sgr_capped(n, _ptr(rp), _ptr(ci), _ptr(out), _ptr(nc), _ptr(rr),
+                               _ptr(ws), _ptr(af), _ptr(ac), stats_cap, rule, max_rounds)
     if rc != 0:
         raise ValueError(f"oracle_sgr failed with status {rc}")
     r = int(rr[0])

@@ -69,9 +69,26 @@ int oracle_sgr(int32_t n, const int32_t *rowptr, const int32_t *colidx,
                            wsize, arcs_ff, arcs_cr, stats_cap, 0);
 }
 
+/* As oracle_sgr_rule, stopping after max_rounds rounds when max_rounds > 0 (only to time
+ * a bounded sample of a long colouring: colours of vertices still on the worklist then
+ * read as -1, and *rounds_out counts the rounds run). */
+int oracle_sgr_capped(int32_t n, const int32_t *rowptr, const int32_t *colidx,
+                      int32_t *colors_out, int32_t *ncolors_out, int32_t *rounds_out,
+                      int64_t *wsize, int64_t *arcs_ff, int64_t *arcs_cr, int32_t stats_cap, int32_t rule,
+                      int32_t max_rounds);
+
 int oracle_sgr_rule(int32_t n, const int32_t *rowptr, const int32_t *colidx,
                     int32_t *colors_out, int32_t *ncolors_out, int32_t *rounds_out,
                     int64_t *wsize, int64_t *arcs_ff, int64_t *arcs_cr, int32_t stats_cap, int32_t rule)
+{
+    return oracle_sgr_capped(n, rowptr, colidx, colors_out, ncolors_out, rounds_out, wsize, arcs_ff, arcs_cr,
+                             stats_cap, rule, 0);
+}
+
+int oracle_sgr_capped(int32_t n, const int32_t *rowptr, const int32_t *colidx,
+                      int32_t *colors_out, int32_t *ncolors_out, int32_t *rounds_out,
+                      int64_t *wsize, int64_t *arcs_ff, int64_t *arcs_cr, int32_t stats_cap, int32_t rule,
+                      int32_t max_rounds)
 {
     *ncolors_out = 0;
     *rounds_out = 0;
@@ -98,7 +115,7 @@ int oracle_sgr_rule(int32_t n, const int32_t *rowptr, const int32_t *colidx,
     int64_t wn = n;
     for (int32_t v = 0; v < n; ++v) W[v] = v;
     int32_t r = 0;
-    while (wn > 0) {
+    while (wn > 0 && (max_rounds <= 0 || r < max_rounds)) {
         int64_t aff = 0, acr = 0;
         /* FirstFit on every worklist vertex, against the snapshot S */
         for (int64_t i = 0; i < wn; ++i) {

@@ -21,6 +21,7 @@ EHIP = -4
 EOVERFLOW = -5
 ENOTSYM = -6
 ELIMIT = -7
+ETIMEOUT = -8
 
 RULE_ID = 0
 RULE_DEGREE = 1
@@ -80,8 +81,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     P, I32 = ctypes.c_void_p, ctypes.c_int32
     lib.csrcolor_color.argtypes = [I32, P, P, P, ctypes.POINTER(I32), P]
     lib.csrcolor_color.restype = ctypes.c_int
-    lib.csrcolor_color_ex.argtypes = [I32, P, P, P, ctypes.POINTER(I32), ctypes.POINTER(Opts),
-                                      ctypes.POINTER(Stats), P]
+    # the colour-count argument of csrcolor_color_ex is a DEVICE pointer
+    lib.csrcolor_color_ex.argtypes = [I32, P, P, P, P, ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
     lib.csrcolor_color_ex.restype = ctypes.c_int
     lib.csrcolor_color_batched.argtypes = [I32, I32, P, P, P, P, P, ctypes.POINTER(Opts), P]
     lib.csrcolor_color_batched.restype = ctypes.c_int

@@ -67,7 +67,10 @@ def color(rowptr: torch.Tensor, colidx: torch.Tensor, out: Optional[torch.Tensor
           opts: Optional[L.Opts] = None, stats: bool = False, stats_cap: int = 4096,
           time_kernels: bool = False, count_bytes: bool = False,
           stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, int, Optional[ColorStats]]:
-    """Colour one graph.  Returns (colors int32[n] on the device, ncolors, stats).
+    """Colour one graph and wait for it.  Returns (colors int32[n] on the device,
+    ncolors, stats).  Passes a statistics block to csrcolor_color_ex (of capacity 0
+    unless `stats`), which selects the synchronous path: the host-driven modes, or the
+    device-planned one with mode PERSISTENT.
     count_bytes: also count the bytes moved by the wake-flag kernels (slower kernels;
     ColorStats.kernel_bytes)."""
     lib = L.load()
@@ -76,31 +79,53 @@ def color(rowptr: torch.Tensor, colidx: torch.Tensor, out: Optional[torch.Tensor
         out = torch.empty(max(n, 0), dtype=torch.int32, device=rowptr.device)
     elif out.dtype != torch.int32 or out.numel() < n or not out.is_cuda:
         raise ValueError("out must be an int32 device tensor with n entries")
-    nc = ctypes.c_int32(0)
-    st = None
-    wbuf = abuf = kbuf = None
-    if stats or time_kernels or count_bytes:
-        st = L.Stats()
-        st.time_kernels = 1 if time_kernels else 0
-        wbuf = (ctypes.c_int64 * stats_cap)()
-        abuf = (ctypes.c_int64 * stats_cap)()
-        st.cap = stats_cap
-        st.wsize = ctypes.cast(wbuf, ctypes.POINTER(ctypes.c_int64))
-        st.arcs = ctypes.cast(abuf, ctypes.POINTER(ctypes.c_int64))
-        if count_bytes:
-            kbuf = (ctypes.c_int64 * 2)()
-            st.kernel_bytes = ctypes.cast(kbuf, ctypes.POINTER(ctypes.c_int64))
-    rc = lib.csrcolor_color_ex(n, rowptr.data_ptr(), colidx.data_ptr(), out.data_ptr(), ctypes.byref(nc),
-                               ctypes.byref(opts) if opts is not None else None,
-                               ctypes.byref(st) if st is not None else None, _stream_ptr(stream))
+    want = stats or time_kernels or count_bytes
+    cap = stats_cap if want else 0
+    st = L.Stats()
+    st.time_kernels = 1 if time_kernels else 0
+    wbuf = (ctypes.c_int64 * max(cap, 1))()
+    abuf = (ctypes.c_int64 * max(cap, 1))()
+    st.cap = cap
+    st.wsize = ctypes.cast(wbuf, ctypes.POINTER(ctypes.c_int64))
+    st.arcs = ctypes.cast(abuf, ctypes.POINTER(ctypes.c_int64))
+    kbuf = None
+    if count_bytes:
+        kbuf = (ctypes.c_int64 * 2)()
+        st.kernel_bytes = ctypes.cast(kbuf, ctypes.POINTER(ctypes.c_int64))
+    rc = lib.csrcolor_color_ex(n, rowptr.data_ptr(), colidx.data_ptr(), out.data_ptr(), None,
+                               ctypes.byref(opts) if opts is not None else None, ctypes.byref(st),
+                               _stream_ptr(stream))
     L.check(rc)
     cs = None
-    if st is not None:
+    if want:
         k = min(st.rounds, stats_cap)
         cs = ColorStats(st.rounds, st.ncolors, bool(st.rows_sorted), st.max_degree, st.nnz,
                         list(wbuf[:k]), list(abuf[:k]), st.ms_setup, st.ms_assign, st.ms_detect,
                         st.n_assign, st.n_detect, list(kbuf) if kbuf is not None else None)
-    return out[:n], int(nc.value), cs
+    return out[:n], int(st.ncolors), cs
+
+
+def color_async(rowptr: torch.Tensor, colidx: torch.Tensor, out: Optional[torch.Tensor] = None,
+                ncolors: Optional[torch.Tensor] = None, opts: Optional[L.Opts] = None,
+                stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Colour one graph without waiting (csrcolor_color_ex with a device colour count and
+    no statistics: device-planned, capturable into a CUDA/HIP graph after a first call has
+    sized the workspace).  Returns (colors int32[n], ncolors int32[1]) on the device;
+    ncolors[0] holds the colour count, or a negative status found on the device."""
+    lib = L.load()
+    n = _check_csr(rowptr, colidx)
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.int32, device=rowptr.device)
+    elif out.dtype != torch.int32 or out.numel() < n or not out.is_cuda:
+        raise ValueError("out must be an int32 device tensor with n entries")
+    if ncolors is None:
+        ncolors = torch.empty(1, dtype=torch.int32, device=rowptr.device)
+    elif ncolors.dtype != torch.int32 or ncolors.numel() < 1 or not ncolors.is_cuda:
+        raise ValueError("ncolors must be an int32 device tensor")
+    rc = lib.csrcolor_color_ex(n, rowptr.data_ptr(), colidx.data_ptr(), out.data_ptr(), ncolors.data_ptr(),
+                               ctypes.byref(opts) if opts is not None else None, None, _stream_ptr(stream))
+    L.check(rc)
+    return out[:n], ncolors
 
 
 def color_raw(n: int, rowptr_ptr: int, colidx_ptr: int, out_ptr: int,

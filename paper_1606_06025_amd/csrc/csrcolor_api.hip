@@ -22,6 +22,7 @@
 
 #include "../../include/csrcolor.h"
 #include "sgr_kernels.h"
+#include "sgr_plan.h"
 #include "sgr_topo.h"
 
 namespace csrcolor {
@@ -74,6 +75,12 @@ struct Workspace {
     hipGraphExec_t gexec = nullptr;
     RoundArgs gargs;
     int gbudget = 0;
+    // device-planned runs: the plan block, the largest arc count the arc-sized buffers
+    // (flags, live lists, split-row scratch) were sized for, and a pinned word for the
+    // sizing read of rowptr[n]
+    DevPlan* plan = nullptr;
+    long long arc_cap = 0;
+    int* sz_h = nullptr;
     std::mutex mu;
 };
 
@@ -227,6 +234,7 @@ void free_vertex_arrays(Workspace* w) {
 // Frees every device array of the workspace (release_workspace).
 void free_ws_arrays(Workspace* w) {
     free_union(w);
+    w->arc_cap = 0;
     if (w->F) (void)hipFree(w->F);
     w->F = nullptr;
     w->F_cap = 0;
@@ -565,40 +573,6 @@ int drive_wake(Workspace* w, Job& J, RoundArgs& a, int budget, bool big, int nhu
     return CSRCOLOR_OK;
 }
 
-// Persistent mode: one cooperative launch runs every remaining round; the grid is the
-// co-resident block count (capped by blocks_per_cu per CU).
-int drive_persistent(Workspace* w, Job& J, RoundArgs& a, int budget, KTimer& T) {
-    int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_persistent, WG, 0));
-    const int cus = num_cus(w->device);
-    const int grid = std::min(std::max(per_cu, 1) * cus, budget);
-    a.dev_plan = 1;
-    a.lbs_n = grid;
-    // round index 1 (the second round) reads parity 1; odd rounds 1 -> 0, even rounds 0 -> 1
-    RoundArgs a_odd = a, a_even = a;
-    a_odd.par_in = 1;
-    a_odd.par_out = 0;
-    a_odd.wl_in = w->wl[1];
-    a_odd.wl_out = w->wl[0];
-    a_even.par_in = 0;
-    a_even.par_out = 1;
-    a_even.wl_in = w->wl[0];
-    a_even.wl_out = w->wl[1];
-    int first = 1;
-    int maxr = J.n + 2;
-    void* args[] = {&a_odd, &a_even, &first, &maxr};
-    hipError_t e = hipSuccess;
-    T.run(1, [&] {
-        e = hipLaunchCooperativeKernel((const void*)k_persistent, dim3(grid), dim3(WG), args, 0, w->stream);
-    });
-    HIP_TRY(e);
-    int rc = read_ctl(w);
-    if (rc) return rc;
-    if (w->ctl_h->err) return CSRCOLOR_EHIP;
-    if (!w->ctl_h->pdone) return CSRCOLOR_ELIMIT;
-    return CSRCOLOR_OK;
-}
-
 // Graph mode: two rounds (parity 1 -> 0 -> 1) with device-side partitions are captured
 // once into a hipGraph on a private stream and replayed; the queue sizes are read
 // back every few replays.  The capture is reused while the kernel arguments stay the
@@ -850,9 +824,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
         HIP_TRY(hipMemsetAsync(w->st_arcs, 0, st_cap * sizeof(long long), st));
     }
 
-    if (J.opt.mode == CSRCOLOR_MODE_PERSISTENT) {
-        rc = drive_persistent(w, J, a, budget, T);
-    } else if (J.opt.mode == CSRCOLOR_MODE_GRAPH) {
+    if (J.opt.mode == CSRCOLOR_MODE_GRAPH) {
         rc = drive_graph(w, J, a, budget);
     } else if (use_wake) {
         rc = drive_wake(w, J, a, budget, longrows, nhub, nchunk, T);
@@ -865,54 +837,12 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     return rc;
 }
 
-int run_job(Workspace* w, Job& J, const long long* voff, int G) {
+// After the rounds: per-round statistics rebuilt from settling rounds (wake flags), the
+// colour count and the statistics the caller asked for.
+int finish_job(Workspace* w, Job& J, int st_cap, KTimer& T, int vblocks) {
     const int n = J.n;
     hipStream_t st = w->stream;
-    const int st_cap = J.stats ? std::max(J.stats->cap, 0) : 0;
-    int rc = ensure_capacity(w, (size_t)n, st_cap);
-    if (rc) return rc;
-    const int cus = num_cus(w->device);
-    const int twave = J.opt.twave;
-
-    KTimer T(w, J.stats && J.stats->time_kernels);
-    T.run(0, [&] { k_init<<<1, WG, 0, st>>>(w->ctl); });
-    const int vblocks = (int)std::min<long long>(((long long)n + WG - 1) / WG, (long long)cus * 4);
-    const int rblocks = (int)std::max<long long>(
-        1, std::min<long long>(((long long)n + WG * VROWS - 1) / (WG * VROWS), (long long)cus * 4));
-    T.kern(0, k_validate_rows, rblocks, WG, n, J.rowptr, J.colidx, w->ctl, twave, J.opt.tsplit);
-    // the arc pass skips itself when the vertex pass found an error, so one read-back
-    // covers both
-    T.kern(0, k_validate_arcs, cus * 4, WG, n, J.rowptr, J.colidx, w->ctl);
-    if (voff) k_validate_batch<<<std::min(G, cus * 16), WG, 0, st>>>(G, n, voff, J.rowptr, J.colidx, w->ctl);
-    HIP_TRY(hipGetLastError());
-    if ((rc = read_ctl(w))) return rc;
-    if (w->ctl_h->err) return CSRCOLOR_EBADCSR;
-    J.sorted = w->ctl_h->desc_total == w->ctl_h->desc_bound;
-    J.maxdeg = w->ctl_h->maxdeg;
-    if (J.opt.validate >= 1) {
-        if (!J.sorted) return CSRCOLOR_EINVAL;   // symmetry check needs sorted rows
-        k_check_symmetric<<<vblocks, WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl);
-        HIP_TRY(hipGetLastError());
-        if ((rc = read_ctl(w))) return rc;
-        if (w->ctl_h->err & 4) return CSRCOLOR_ENOTSYM;
-        if (w->ctl_h->err) return CSRCOLOR_EBADCSR;
-    }
-    int hist[NB];
-    Seg seg;
-    seg.s[0] = 0;
-    for (int b = 0; b < NB; ++b) {
-        hist[b] = w->ctl_h->hist[b];
-        seg.s[b + 1] = seg.s[b] + hist[b];
-    }
-
-    if (J.opt.algo == CSRCOLOR_ALGO_SGR_TOPO) {
-        if (st_cap) HIP_TRY(hipMemsetAsync(w->st_wsize, 0, st_cap * sizeof(long long), st));
-        if (st_cap) HIP_TRY(hipMemsetAsync(w->st_arcs, 0, st_cap * sizeof(long long), st));
-        rc = drive_topo(w, J, cus * J.opt.blocks_per_cu, st_cap, T);
-    } else {
-        rc = run_rounds(w, J, hist, seg, st_cap, T);
-    }
-    if (rc) return rc;
+    int rc = 0;
     if (J.wake && st_cap) {
         // per-round settle counts and their arcs, from the settling rounds
         k_round_hist<<<std::max(vblocks, 1), WG, 0, st>>>(n, J.rowptr, w->srnd, w->st_wsize, w->st_arcs, st_cap);
@@ -985,6 +915,240 @@ int run_job(Workspace* w, Job& J, const long long* voff, int G) {
     return CSRCOLOR_OK;
 }
 
+
+// Status of a device-planned run from its control block (the host twin of dev_status).
+int status_of(const Ctl* c) {
+    const int e = c->err;
+    if (e & (ERR_ROWPTR | ERR_COLIDX | ERR_MULTI | ERR_BATCH)) return CSRCOLOR_EBADCSR;
+    if (e & ERR_ASYM) return CSRCOLOR_ENOTSYM;
+    if (e & ERR_UNSORTED) return CSRCOLOR_EINVAL;
+    if (e & ERR_NOMEM) return CSRCOLOR_ENOMEM;
+    if (e & ERR_BARRIER) return CSRCOLOR_ETIMEOUT;
+    if (e) return CSRCOLOR_EHIP;
+    if (!c->pdone) return CSRCOLOR_ELIMIT;
+    return CSRCOLOR_OK;
+}
+
+int g_pers_per_cu[64] = {0};
+long long g_wall_khz[64] = {0};
+
+// Workgroups of the persistent round kernel: no more than fit on the device at once
+// (every barrier waits for all of them), no more than the launch budget, and for
+// small graphs about one per 256 vertices (fewer blocks make every barrier cheaper).
+int persistent_grid(int dev, int n, int budget) {
+    if (dev < 0 || dev >= 64) dev = 0;
+    if (g_pers_per_cu[dev] == 0) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_persistent_dev, WG, 0) !=
+                hipSuccess || per_cu <= 0)
+            per_cu = 1;
+        g_pers_per_cu[dev] = per_cu;
+    }
+    const int resident = g_pers_per_cu[dev] * num_cus(dev);
+    const int want = (int)std::max<long long>(64, ((long long)n + 255) / 256);
+    return std::max(std::min(std::min(resident, budget), want), std::min(resident, 16));
+}
+
+// Wall-clock ticks a persistent barrier may wait before giving up (8 seconds).
+long long barrier_limit(int dev) {
+    if (dev < 0 || dev >= 64) dev = 0;
+    if (g_wall_khz[dev] == 0) {
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+            khz = 100000;
+        g_wall_khz[dev] = khz;
+    }
+    return 8000LL * g_wall_khz[dev];
+}
+
+// Device-planned run (the rounds of Sec. 3.1 driven on the device, see sgr_plan.h):
+// everything is enqueued on the workspace stream.  The arc-sized buffers (push flags,
+// live lists, split-row scratch) are sized on the host from a read-back of rowptr[n]
+// when the call is synchronous (`sync`) or the workspace has never been sized for this
+// many vertices; otherwise the call makes no allocation, no copy and no wait, and the
+// plan kernel checks that the graph fits (ERR_NOMEM when it does not).  With `sync`
+// the call waits and fills J (colour count, rounds, statistics) or returns the status
+// the device found; `ncolors_dev` (device, may be null) receives the colour count, or
+// for G > 0 graphs one count per graph, or the negative status.
+int run_device(Workspace* w, Job& J, const long long* voff, int G, int* ncolors_dev, bool sync) {
+    const int n = J.n;
+    hipStream_t st = w->stream;
+    const Options& o = J.opt;
+    const int st_cap = J.stats ? std::max(J.stats->cap, 0) : 0;
+    // the arc-sized buffers must cover every graph of at most cap_n vertices and arc_cap
+    // arcs (a host-driven call may have grown the vertex arrays since they were sized)
+    const bool covered = w->arc_cap > 0 && w->F_cap >= (w->cap_n + (size_t)w->arc_cap) / 4 + 4 &&
+                         w->split_cap >= (size_t)(w->arc_cap / 23 + 64) && w->live_cap >= (size_t)w->arc_cap;
+    const bool fresh = (size_t)n > w->cap_n || !w->ctl || !w->plan || !covered;
+    int rc = ensure_capacity(w, (size_t)n, st_cap);
+    if (rc) return rc;
+    if (!w->plan && hipMalloc(&w->plan, sizeof(DevPlan)) != hipSuccess) return CSRCOLOR_ENOMEM;
+    if (!w->sz_h && hipHostMalloc(&w->sz_h, sizeof(int), hipHostMallocDefault) != hipSuccess) return CSRCOLOR_ENOMEM;
+    if (sync || fresh) {
+        HIP_TRY(hipMemcpyAsync(w->sz_h, J.rowptr + n, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const long long arcs = std::max<long long>(std::max(*w->sz_h, 0), w->arc_cap);
+        // byte flags for every vertex and arc the workspace holds (the larger flag
+        // variant); split-row scratch for the most hubs and chunks that many arcs allow
+        // (a hub has more than 1024 arcs: 36 ints per hub, 5 per 2048-arc chunk)
+        if ((rc = ensure_F(w, (size_t)((w->cap_n + arcs) / 4 + 4)))) return rc;
+        if ((rc = ensure_split(w, (size_t)(arcs / 23 + 64)))) return rc;
+        if ((rc = ensure_live(w, (size_t)std::max<long long>(arcs, 1)))) return rc;
+        w->arc_cap = std::max<long long>(arcs, 1);
+    }
+    const int cus = num_cus(w->device);
+    const int budget = cus * o.blocks_per_cu;
+    const int grid = persistent_grid(w->device, n, budget);
+    const int r1blocks = (int)(((long long)n + 4 * WG - 1) / (4 * WG));
+    unsigned long long* lb = nullptr;
+    if (o.ordered) {
+        if ((rc = ensure_lb(w, std::max((size_t)NB * r1blocks, (size_t)grid + 2 * NB + 8)))) return rc;
+        lb = w->lb;
+    }
+
+    RoundArgs t;
+    memset(&t, 0, sizeof(t));
+    t.n = n;
+    t.rowptr = J.rowptr;
+    t.colidx = J.colidx;
+    t.X = w->X;
+    t.out = J.colors_out;
+    t.ctl = w->ctl;
+    t.wl_in = w->wl[1];
+    t.wl_out = w->wl[0];
+    t.twave = o.twave;
+    t.tsplit = o.tsplit;
+    t.lane_mode_assign = o.lane_assign;
+    t.lane_mode_detect = o.lane_detect;
+    t.dev_plan = 1;
+    t.pushff = o.pushff;
+    t.F = w->F;
+    t.dirty = w->dirty;
+    t.rule = o.rule;
+    t.hint = (o.hints && o.rule == 0) ? w->hint : nullptr;
+    t.live = w->live;
+    t.llen = w->llen;
+    t.lbs = lb;
+    t.lbs_n = grid;
+    t.st_cap = st_cap;
+    t.st_wsize = st_cap ? w->st_wsize : nullptr;
+    t.st_arcs = st_cap ? w->st_arcs : nullptr;
+    DevCaps c;
+    c.f_words = (long long)w->F_cap;
+    c.live_ints = (long long)w->live_cap;
+    c.split_ints = (long long)w->split_cap;
+    c.split = w->split;
+    c.lb1 = lb;
+    c.lb1_ints = lb ? 2 * NB * r1blocks : 0;
+    c.want_live = o.live && o.rule == 0;
+
+    KTimer T(w, J.stats && J.stats->time_kernels);
+    T.run(0, [&] { k_init<<<1, WG, 0, st>>>(w->ctl); });
+    const int vblocks = (int)std::min<long long>(((long long)n + WG - 1) / WG, (long long)cus * 4);
+    const int rblocks = (int)std::max<long long>(
+        1, std::min<long long>(((long long)n + WG * VROWS - 1) / (WG * VROWS), (long long)cus * 4));
+    T.kern(0, k_validate_rows, rblocks, WG, n, J.rowptr, J.colidx, w->ctl, o.twave, o.tsplit);
+    T.kern(0, k_validate_arcs, cus * 4, WG, n, J.rowptr, J.colidx, w->ctl);
+    if (voff) k_validate_batch<<<std::min(G, cus * 16), WG, 0, st>>>(G, n, voff, J.rowptr, J.colidx, w->ctl);
+    if (o.validate >= 1) k_check_symmetric<<<std::max(vblocks, 1), WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl);
+    if (st_cap) {
+        k_fill<<<std::max(1, std::min((2 * st_cap + WG - 1) / WG, cus)), WG, 0, st>>>(
+            reinterpret_cast<int*>(w->st_wsize), 2 * st_cap, 0);
+        k_fill<<<std::max(1, std::min((2 * st_cap + WG - 1) / WG, cus)), WG, 0, st>>>(
+            reinterpret_cast<int*>(w->st_arcs), 2 * st_cap, 0);
+    }
+    T.run(0, [&] {
+        k_dev_plan<<<1, 64, 0, st>>>(t, c, w->plan);
+        k_dev_clear<<<cus * 4, WG, 0, st>>>(w->plan);
+        k_round1_dev<<<std::max(r1blocks, 1), WG, 0, st>>>(w->plan);
+    });
+    HIP_TRY(hipGetLastError());
+    // every later round in one launch: cooperative (the runtime guarantees that every
+    // workgroup is resident) unless the stream is being captured into a graph, where a
+    // plain launch of no more workgroups than fit at once is used (its barriers are
+    // bounded, so a grid that is not resident ends with CSRCOLOR_ETIMEOUT)
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) cs = hipStreamCaptureStatusNone;
+    const DevPlan* plan = w->plan;
+    int maxr = n + 2;
+    long long limit = barrier_limit(w->device);
+    hipError_t e = hipSuccess;
+    T.run(1, [&] {
+        if (cs == hipStreamCaptureStatusActive) {
+            k_persistent_dev<<<grid, WG, 0, st>>>(plan, maxr, limit);
+            e = hipGetLastError();
+        } else {
+            void* args[] = {&plan, &maxr, &limit};
+            e = hipLaunchCooperativeKernel((const void*)k_persistent_dev, dim3(grid), dim3(WG), args, 0, st);
+        }
+    });
+    HIP_TRY(e);
+    if (ncolors_dev) {
+        const int fg = G > 0 ? std::min(G, cus * 8) : 1;
+        k_dev_finish<<<fg, WG, 0, st>>>(w->ctl, G, voff, J.colors_out, ncolors_dev);
+        HIP_TRY(hipGetLastError());
+    }
+    if (!sync) return CSRCOLOR_OK;
+    if ((rc = read_ctl(w))) return rc;
+    if ((rc = status_of(w->ctl_h))) return rc;
+    J.sorted = w->ctl_h->desc_total == w->ctl_h->desc_bound;
+    J.maxdeg = w->ctl_h->maxdeg;
+    J.wake = false;
+    return finish_job(w, J, st_cap, T, vblocks);
+}
+
+int run_job(Workspace* w, Job& J, const long long* voff, int G) {
+    if (J.opt.mode == CSRCOLOR_MODE_PERSISTENT) return run_device(w, J, voff, G, nullptr, true);
+    const int n = J.n;
+    hipStream_t st = w->stream;
+    const int st_cap = J.stats ? std::max(J.stats->cap, 0) : 0;
+    int rc = ensure_capacity(w, (size_t)n, st_cap);
+    if (rc) return rc;
+    const int cus = num_cus(w->device);
+    const int twave = J.opt.twave;
+
+    KTimer T(w, J.stats && J.stats->time_kernels);
+    T.run(0, [&] { k_init<<<1, WG, 0, st>>>(w->ctl); });
+    const int vblocks = (int)std::min<long long>(((long long)n + WG - 1) / WG, (long long)cus * 4);
+    const int rblocks = (int)std::max<long long>(
+        1, std::min<long long>(((long long)n + WG * VROWS - 1) / (WG * VROWS), (long long)cus * 4));
+    T.kern(0, k_validate_rows, rblocks, WG, n, J.rowptr, J.colidx, w->ctl, twave, J.opt.tsplit);
+    // the arc pass skips itself when the vertex pass found an error, so one read-back
+    // covers both
+    T.kern(0, k_validate_arcs, cus * 4, WG, n, J.rowptr, J.colidx, w->ctl);
+    if (voff) k_validate_batch<<<std::min(G, cus * 16), WG, 0, st>>>(G, n, voff, J.rowptr, J.colidx, w->ctl);
+    HIP_TRY(hipGetLastError());
+    if ((rc = read_ctl(w))) return rc;
+    if (w->ctl_h->err) return CSRCOLOR_EBADCSR;
+    J.sorted = w->ctl_h->desc_total == w->ctl_h->desc_bound;
+    J.maxdeg = w->ctl_h->maxdeg;
+    if (J.opt.validate >= 1) {
+        if (!J.sorted) return CSRCOLOR_EINVAL;   // symmetry check needs sorted rows
+        k_check_symmetric<<<vblocks, WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl);
+        HIP_TRY(hipGetLastError());
+        if ((rc = read_ctl(w))) return rc;
+        if (w->ctl_h->err & 4) return CSRCOLOR_ENOTSYM;
+        if (w->ctl_h->err) return CSRCOLOR_EBADCSR;
+    }
+    int hist[NB];
+    Seg seg;
+    seg.s[0] = 0;
+    for (int b = 0; b < NB; ++b) {
+        hist[b] = w->ctl_h->hist[b];
+        seg.s[b + 1] = seg.s[b] + hist[b];
+    }
+
+    if (J.opt.algo == CSRCOLOR_ALGO_SGR_TOPO) {
+        if (st_cap) HIP_TRY(hipMemsetAsync(w->st_wsize, 0, st_cap * sizeof(long long), st));
+        if (st_cap) HIP_TRY(hipMemsetAsync(w->st_arcs, 0, st_cap * sizeof(long long), st));
+        rc = drive_topo(w, J, cus * J.opt.blocks_per_cu, st_cap, T);
+    } else {
+        rc = run_rounds(w, J, hist, seg, st_cap, T);
+    }
+    if (rc) return rc;
+    return finish_job(w, J, st_cap, T, vblocks);
+}
+
 }  // namespace
 }  // namespace csrcolor
 
@@ -992,9 +1156,13 @@ using namespace csrcolor;
 
 extern "C" {
 
-int csrcolor_color_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx, int32_t* colors_out,
-                      int32_t* ncolors_host, const csrcolor_opts* opts, csrcolor_stats* stats,
-                      hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+// Host-driven colouring of one graph (every mode but the device-planned one): the call
+// waits for the stream and returns the colour count on the host.
+int color_host(int32_t n, const int32_t* rowptr, const int32_t* colidx, int32_t* colors_out,
+               int32_t* ncolors_host, const csrcolor_opts* opts, csrcolor_stats* stats, hipStream_t stream) {
     if (n < 0) return CSRCOLOR_EINVAL;
     if (!opts_valid(opts, true)) return CSRCOLOR_EINVAL;
     if (stats && stats->cap > 0 && stats->cap > (1 << 24)) return CSRCOLOR_EINVAL;
@@ -1024,11 +1192,62 @@ int csrcolor_color_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx, i
     if (ncolors_host) *ncolors_host = J.ncolors;
     return CSRCOLOR_OK;
 }
+}  // namespace
+
+extern "C" {
+
+int csrcolor_color_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx, int32_t* colors_out,
+                      int32_t* ncolors_dev, const csrcolor_opts* opts, csrcolor_stats* stats,
+                      hipStream_t stream) {
+    if (n < 0) return CSRCOLOR_EINVAL;
+    if (!opts_valid(opts, true)) return CSRCOLOR_EINVAL;
+    if (stats && stats->cap > 0 && stats->cap > (1 << 24)) return CSRCOLOR_EINVAL;
+    const int mode = opts ? opts->mode : CSRCOLOR_MODE_AUTO;
+    const int algo = opts ? opts->algorithm : CSRCOLOR_ALGO_SGR;
+    const bool device = mode == CSRCOLOR_MODE_PERSISTENT ||
+                        (mode == CSRCOLOR_MODE_AUTO && !stats && algo == CSRCOLOR_ALGO_SGR);
+    if (!device) {
+        int32_t nc = 0;
+        int rc = color_host(n, rowptr, colidx, colors_out, &nc, opts, stats, stream);
+        if (rc) return rc;
+        if (ncolors_dev) {
+            k_fill<<<1, 64, 0, stream>>>(ncolors_dev, 1, nc);
+            if (hipGetLastError() != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) return CSRCOLOR_EHIP;
+        }
+        return CSRCOLOR_OK;
+    }
+    if (n == 0) {
+        if (stats) {
+            stats->rounds = stats->ncolors = stats->max_degree = 0;
+            stats->rows_sorted = 1;
+            stats->nnz = 0;
+        }
+        if (ncolors_dev) {
+            k_fill<<<1, 64, 0, stream>>>(ncolors_dev, 1, 0);
+            if (hipGetLastError() != hipSuccess) return CSRCOLOR_EHIP;
+        }
+        return CSRCOLOR_OK;
+    }
+    if (!rowptr || !colors_out) return CSRCOLOR_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return CSRCOLOR_EHIP;
+    Workspace* w = get_ws(dev, stream);
+    std::lock_guard<std::mutex> lk(w->mu);
+    Job J;
+    J.n = n;
+    J.rowptr = rowptr;
+    J.colidx = colidx;
+    J.colors_out = colors_out;
+    J.opt = parse_opts(opts);
+    J.opt.mode = CSRCOLOR_MODE_PERSISTENT;
+    J.stats = stats;
+    return run_device(w, J, nullptr, 0, ncolors_dev, stats != nullptr);
+}
 
 int csrcolor_color(int32_t n, const int32_t* rowptr, const int32_t* colidx, int32_t* colors_out,
                    int32_t* ncolors, hipStream_t stream) {
     if (!ncolors) return CSRCOLOR_EINVAL;
-    return csrcolor_color_ex(n, rowptr, colidx, colors_out, ncolors, nullptr, nullptr, stream);
+    return color_host(n, rowptr, colidx, colors_out, ncolors, nullptr, nullptr, stream);
 }
 
 int csrcolor_color_batched(int32_t G, int32_t n_total, const int64_t* voff, const int32_t* rowptr,
@@ -1051,6 +1270,8 @@ int csrcolor_color_batched(int32_t G, int32_t n_total, const int64_t* voff, cons
         J.colors_out = colors_out;
         J.opt = parse_opts(opts);
         J.stats = nullptr;
+        if (J.opt.mode == CSRCOLOR_MODE_PERSISTENT)   // one fused launch, no host wait
+            return run_device(w, J, reinterpret_cast<const long long*>(voff), G, ncolors_out, false);
         int rc = run_job(w, J, reinterpret_cast<const long long*>(voff), G);
         if (rc) return rc;
     }
@@ -1155,6 +1376,7 @@ const char* csrcolor_strerror(int status) {
         case CSRCOLOR_EOVERFLOW: return "size exceeds int32 range";
         case CSRCOLOR_ENOTSYM: return "CSR is not symmetric";
         case CSRCOLOR_ELIMIT: return "round limit exceeded";
+        case CSRCOLOR_ETIMEOUT: return "a device-wide barrier timed out (the persistent grid was not resident)";
         default: return "unknown status";
     }
 }
@@ -1169,20 +1391,37 @@ void csrcolor_release_workspace(void) {
         (void)hipSetDevice(w->device);
         (void)hipStreamSynchronize(w->stream);
         free_ws_arrays(w);
+        // every handle is reset after it is freed: the next call on this stream starts
+        // from an empty workspace and recreates what it needs
         if (w->ctl) (void)hipFree(w->ctl);
         if (w->ubytes) (void)hipFree(w->ubytes);
         if (w->ctl_h) (void)hipHostFree(w->ctl_h);
         if (w->ctl_h2) (void)hipHostFree(w->ctl_h2);
-        for (int i = 0; i < 2; ++i)
+        w->ctl = nullptr;
+        w->ubytes = nullptr;
+        w->ctl_h = w->ctl_h2 = nullptr;
+        for (int i = 0; i < 2; ++i) {
             if (w->pev[i]) (void)hipEventDestroy(w->pev[i]);
+            w->pev[i] = nullptr;
+        }
+        for (hipEvent_t e : w->evs) (void)hipEventDestroy(e);
+        w->evs.clear();
         if (w->st_wsize) (void)hipFree(w->st_wsize);
         if (w->st_arcs) (void)hipFree(w->st_arcs);
-        if (w->gexec) (void)hipGraphExecDestroy(w->gexec);
-        w->gexec = nullptr;
-        w->ctl = nullptr;
-        w->ctl_h = nullptr;
         w->st_wsize = w->st_arcs = nullptr;
         w->st_cap = 0;
+        if (w->gexec) (void)hipGraphExecDestroy(w->gexec);
+        w->gexec = nullptr;
+        w->gbudget = 0;
+        memset(&w->gargs, 0, sizeof(w->gargs));
+        if (w->gev) (void)hipEventDestroy(w->gev);
+        w->gev = nullptr;
+        if (w->gstream) (void)hipStreamDestroy(w->gstream);
+        w->gstream = nullptr;
+        if (w->plan) (void)hipFree(w->plan);
+        w->plan = nullptr;
+        if (w->sz_h) (void)hipHostFree(w->sz_h);
+        w->sz_h = nullptr;
     }
     (void)hipSetDevice(cur);
 }

@@ -213,6 +213,20 @@ __host__ __device__ __forceinline__ unsigned long long jp_prio(unsigned long lon
     return splitmix64(seed, ((unsigned long long)(unsigned)c << 32) + (unsigned)v);
 }
 
+// Bits of Ctl::err.  The host maps them to a status: ROWPTR, COLIDX, MULTI and
+// BATCH to CSRCOLOR_EBADCSR, ASYM to CSRCOLOR_ENOTSYM, UNSORTED to CSRCOLOR_EINVAL,
+// NOMEM to CSRCOLOR_ENOMEM, BARRIER to CSRCOLOR_ETIMEOUT, the others to CSRCOLOR_EHIP.
+constexpr int ERR_ROWPTR = 1;      // rowptr not monotone from 0 within [0, rowptr[n]]
+constexpr int ERR_COLIDX = 2;      // a colidx entry outside [0, n)
+constexpr int ERR_ASYM = 4;        // symmetry check failed
+constexpr int ERR_INTERNAL = 8;
+constexpr int ERR_LOOKBACK = 16;   // an ordered-compaction look-back gave up
+constexpr int ERR_MULTI = 32;      // multi-graph call: a graph's rowptr does not span [0, nnz_g]
+constexpr int ERR_BATCH = 64;      // batched call: bad vertex offsets or an arc leaving its graph
+constexpr int ERR_UNSORTED = 128;  // the symmetry check was asked for on unsorted rows
+constexpr int ERR_BARRIER = 256;   // a device-wide barrier of the persistent rounds timed out
+constexpr int ERR_NOMEM = 512;     // device-planned run: the graph needs more scratch than was given
+
 // Device-resident control block.
 struct Ctl {
     int cnt[2][8];      // worklist length per bucket, double-buffered by round parity

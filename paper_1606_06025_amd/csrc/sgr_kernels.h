@@ -89,7 +89,7 @@ __global__ __launch_bounds__(WG) void k_validate_rows(int n, const int* __restri
 #pragma unroll
     for (int b = 0; b < NB; ++b) hist[b] = block_sum(hist[b], red);
     if (threadIdx.x == 0) {
-        if (bad) atomicOr(&ctl->err, 1);
+        if (bad) atomicOr(&ctl->err, ERR_ROWPTR);
         if (chunks) atomicAdd(&ctl->hchunks, chunks);
         if (big) atomicAdd((unsigned long long*)&ctl->bigarcs, (unsigned long long)big);
         if (mydeg) atomicMax(&ctl->maxdeg, mydeg);
@@ -150,15 +150,22 @@ __global__ __launch_bounds__(WG) void k_validate_arcs(int n, const int* __restri
     bad = block_max(bad, red);
     desc = block_sum(desc, red);
     if (threadIdx.x == 0) {
-        if (bad) atomicOr(&ctl->err, 2);
+        if (bad) atomicOr(&ctl->err, ERR_COLIDX);
         if (desc) atomicAdd(&ctl->desc_total, desc);
     }
 }
 
 // Symmetry check (sorted rows): arc (v, w) needs v in row w.  One thread per vertex
-// row entry; binary search in row w.
+// row entry; binary search in row w.  It runs only on a graph the structural passes
+// accepted (every row bound and id in range) and whose rows are sorted (the search
+// needs them sorted): otherwise it returns, flagging unsorted rows.
 __global__ __launch_bounds__(WG) void k_check_symmetric(int n, const int* __restrict__ rowptr,
                                                         const int* __restrict__ colidx, Ctl* ctl) {
+    if (ctl->err) return;
+    if (ctl->desc_total != ctl->desc_bound) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctl->err, ERR_UNSORTED);
+        return;
+    }
     int bad = 0;
     for (long long v = (long long)blockIdx.x * WG + threadIdx.x; v < n; v += (long long)gridDim.x * WG) {
         for (int e = rowptr[v]; e < rowptr[v + 1]; ++e) {
@@ -171,7 +178,7 @@ __global__ __launch_bounds__(WG) void k_check_symmetric(int n, const int* __rest
             if (lo >= rowptr[w + 1] || colidx[lo] != v) bad = 1;
         }
     }
-    if (__ballot(bad) && __lane_id() == 0) atomicOr(&ctl->err, 4);
+    if (__ballot(bad) && __lane_id() == 0) atomicOr(&ctl->err, ERR_ASYM);
 }
 
 // ---------------------------------------------------------------------------
@@ -182,14 +189,14 @@ __global__ __launch_bounds__(WG) void k_check_symmetric(int n, const int* __rest
 // One workgroup handles 4*WG consecutive vertices and compacts them per bucket in
 // LDS, so there are at most NB global atomics per workgroup.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ rowptr,
-                                               const int* __restrict__ colidx, int* X, int* out,
-                                               int* wl1, Ctl* ctl, int sorted, int twave, int tsplit,
-                                               Seg seg, int* cstart1, int* owner1, unsigned* F, int nnz,
-                                               int rule, int jp, int* hint, int* llen, int* clen,
-                                               unsigned long long* lb1, int fbytes, unsigned char* dirty,
-                                               unsigned char* rflag, unsigned char* aflag, int* srnd,
-                                               unsigned long long* Fs) {
+__device__ __forceinline__ void round1_body(int n, const int* __restrict__ rowptr,
+                                            const int* __restrict__ colidx, int* X, int* out,
+                                            int* wl1, Ctl* ctl, int sorted, int twave, int tsplit,
+                                            const int* seg, int* cstart1, int* owner1, unsigned* F, int nnz,
+                                            int rule, int jp, int* hint, int* llen, int* clen,
+                                            unsigned long long* lb1, int fbytes, unsigned char* dirty,
+                                            unsigned char* rflag, unsigned char* aflag, int* srnd,
+                                            unsigned long long* Fs) {
     constexpr int ITER = 4;
     __shared__ int buf[WAVES][NB][ITER * 64];
     __shared__ int wcnt[WAVES][NB];
@@ -280,7 +287,7 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
                     const int nch = split_chunks(end - beg);
                     const int p = atomicAdd(&ctl->cnt[1][BSPLIT], 1);
                     const int cs = atomicAdd(&ctl->ccnt[1], nch);
-                    wl1[seg.s[BSPLIT] + p] = v;
+                    wl1[seg[BSPLIT] + p] = v;
                     cstart1[p] = cs;
                     for (int k = 0; k < nch; ++k) owner1[cs + k] = p;
                     if (llen) {
@@ -342,11 +349,23 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        int* dst = wl1 + seg.s[b] + wbase[wv][b];
+        int* dst = wl1 + seg[b] + wbase[wv][b];
         for (int k = lane; k < cnt[b]; k += 64) dst[k] = buf[wv][b][k];
     }
 }
 
+
+__global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ rowptr,
+                                               const int* __restrict__ colidx, int* X, int* out,
+                                               int* wl1, Ctl* ctl, int sorted, int twave, int tsplit,
+                                               Seg seg, int* cstart1, int* owner1, unsigned* F, int nnz,
+                                               int rule, int jp, int* hint, int* llen, int* clen,
+                                               unsigned long long* lb1, int fbytes, unsigned char* dirty,
+                                               unsigned char* rflag, unsigned char* aflag, int* srnd,
+                                               unsigned long long* Fs) {
+    round1_body(n, rowptr, colidx, X, out, wl1, ctl, sorted, twave, tsplit, seg.s, cstart1, owner1, F, nnz,
+                rule, jp, hint, llen, clen, lb1, fbytes, dirty, rflag, aflag, srnd, Fs);
+}
 
 // Flag-scanning conflict test of the vertices of at most WAKE_DEG arcs, run by block
 // bid of nblk such blocks: every wavefront scans the test flags of its vpw
@@ -454,7 +473,7 @@ __global__ __launch_bounds__(WG) void k_concat(const MultiDesc* __restrict__ d, 
     const MultiDesc m = d[g];
     const long long stride = (long long)gridDim.x * WG;
     const long long t0 = (long long)blockIdx.x * WG + threadIdx.x;
-    if (t0 == 0 && (m.rowptr[0] != 0 || m.rowptr[m.n] != m.nnz)) atomicOr(&ctl->err, 32);
+    if (t0 == 0 && (m.rowptr[0] != 0 || m.rowptr[m.n] != m.nnz)) atomicOr(&ctl->err, ERR_MULTI);
     for (long long i = t0; i < m.n; i += stride) urowptr[m.voff + i] = m.rowptr[i] + (int)m.eoff;
     for (long long j = t0; j < m.nnz; j += stride) ucolidx[m.eoff + j] = m.colidx[j] + (int)m.voff;
     if (g == G - 1 && t0 == 0) urowptr[N] = (int)E;
@@ -472,7 +491,10 @@ __global__ __launch_bounds__(WG) void k_scatter(const MultiDesc* __restrict__ d,
 __global__ __launch_bounds__(WG) void k_validate_batch(int G, int n_total, const long long* __restrict__ voff,
                                                        const int* __restrict__ rowptr,
                                                        const int* __restrict__ colidx, Ctl* ctl) {
+    // rowptr already failed validation: its entries are not trustworthy bounds
+    if (ctl->err) return;
     int bad = 0;
+    const long long nnz = rowptr[n_total];
     for (int g = blockIdx.x; g < G; g += gridDim.x) {
         const long long v0 = voff[g], v1 = voff[g + 1];
         if ((g == 0 && v0 != 0) || v0 < 0 || v0 > n_total || v1 < v0 || v1 > n_total ||
@@ -480,13 +502,16 @@ __global__ __launch_bounds__(WG) void k_validate_batch(int G, int n_total, const
             bad = 1;
             continue;
         }
-        const long long e0 = rowptr[v0], e1 = rowptr[v1];
+        // the row pass checked 0 <= rowptr[v] <= rowptr[v+1] <= rowptr[n_total]; the
+        // clamp keeps the reads inside colidx even if it is ever skipped
+        const long long e0 = min(max((long long)rowptr[v0], 0ll), nnz);
+        const long long e1 = min(max((long long)rowptr[v1], e0), nnz);
         for (long long e = e0 + threadIdx.x; e < e1; e += WG) {
             const int w = colidx[e];
             if (w < v0 || w >= v1) bad = 1;
         }
     }
-    if (__ballot(bad) && __lane_id() == 0) atomicOr(&ctl->err, 16);
+    if (__ballot(bad) && __lane_id() == 0) atomicOr(&ctl->err, ERR_BATCH);
 }
 
 }  // namespace csrcolor

@@ -549,7 +549,7 @@ __device__ __forceinline__ int lookback_walk(unsigned long long* st, int u, int 
         // safety net: a unit that never publishes would be a bug; flag it (the host
         // then fails the call) rather than spin forever
         if (++spins > (1 << 22)) {
-            if (lane == 0) atomicOr(err, 16);
+            if (lane == 0) atomicOr(err, ERR_LOOKBACK);
             return -1;
         }
         const int k = base - lane;
@@ -1515,15 +1515,19 @@ __global__ __launch_bounds__(WG) void k_push(RoundArgs a) { push_split_phase<W>(
 
 // ---------------------------------------------------------------------------
 // Persistent mode (the kernel fusion of Sec. 3.3): every round of a colouring in
-// one cooperative launch, FirstFit and the conflict test separated by device-wide
-// barriers.  The barrier is two-level: blocks first meet on a counter of their XCD
-// group (blockIdx mod 8), the last of each group meets the others on a top counter,
-// and the last overall advances the generation all blocks wait for.  Counters only
-// grow within a run, so no reset is needed between barriers.  The agent-scope fences
-// on both sides make the colours and worklists written by one XCD visible to the
+// one launch, FirstFit and the conflict test separated by device-wide barriers.
+// The barrier is two-level: blocks first meet on a counter of their XCD group
+// (blockIdx mod 8), the last of each group meets the others on a top counter, and
+// the last overall advances the generation all blocks wait for.  Counters only grow
+// within a run, so no reset is needed between barriers.  The agent-scope fences on
+// both sides make the colours and worklists written by one XCD visible to the
 // others.
+// Every wait is bounded: a block that has waited `limit` wall-clock ticks sets
+// ERR_BARRIER and stops waiting, and every block leaves the round loop once that bit
+// is set, so a grid that is not fully resident (a plain launch sharing the device with
+// another persistent kernel) ends with an error instead of hanging.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void grid_sync(Ctl* ctl, int& gen) {
+__device__ __forceinline__ void grid_sync(Ctl* ctl, int& gen, long long limit) {
     __syncthreads();
     if (threadIdx.x == 0) {
         const int nblk = gridDim.x;
@@ -1540,8 +1544,14 @@ __device__ __forceinline__ void grid_sync(Ctl* ctl, int& gen) {
         }
         // spin with relaxed loads (an acquire load would invalidate the L2 on every poll),
         // then one acquire fence
-        while (__hip_atomic_load(&ctl->bar_gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
+        const long long t0 = wall_clock64();
+        while (__hip_atomic_load(&ctl->bar_gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(2);
+            if (wall_clock64() - t0 > limit) {
+                atomicOr(&ctl->err, ERR_BARRIER);
+                break;
+            }
+        }
         __threadfence();
     }
     gen += 1;
@@ -1550,51 +1560,58 @@ __device__ __forceinline__ void grid_sync(Ctl* ctl, int& gen) {
 
 // One round of the persistent kernel: FirstFit, barrier, conflict test, barrier, and
 // in push mode the split-hub push phase with its barrier.  Returns false when every
-// queue was empty (the colouring is complete).
+// queue was empty (the colouring is complete) or a barrier timed out.
 __device__ __forceinline__ bool persistent_round(const RoundArgs& a, RoundLds& s, int* boff, int& total,
-                                                 int& gen, int& cmax) {
+                                                 int& gen, int& cmax, long long limit) {
     if (threadIdx.x == 0) {
         int cnt[NB];
         for (int b = 0; b < NB; ++b) cnt[b] = ld_agent(&a.ctl->cnt[a.par_in][b]);
         cnt[BSPLIT] = ld_agent(&a.ctl->ccnt[a.par_in]);
         int t = 0;
         for (int b = 0; b < NB; ++b) t += cnt[b];
-        total = t;
+        total = (ld_agent(&a.ctl->err) & ERR_BARRIER) ? -1 : t;
         device_plan(cnt, gridDim.x, boff);
     }
     __syncthreads();
-    if (total == 0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->pdone = 1;
+    if (total <= 0) {
+        if (total == 0 && blockIdx.x == 0 && threadIdx.x == 0) a.ctl->pdone = 1;
         return false;
     }
     assign_phase(a, s, blockIdx.x, boff);
-    grid_sync(a.ctl, gen);
+    grid_sync(a.ctl, gen, limit);
     detect_phase<false>(a, s, blockIdx.x, boff, cmax);
-    grid_sync(a.ctl, gen);
+    grid_sync(a.ctl, gen, limit);
     if (a.pushff && boff[BSPLIT + 1] > boff[BSPLIT]) {
         push_split_phase<false>(a, blockIdx.x, gridDim.x);
-        grid_sync(a.ctl, gen);
+        grid_sync(a.ctl, gen, limit);
     }
     return true;
 }
 
 // a_odd / a_even: the same arguments with the worklist parities of odd / even round
-// indices, kept as two constant kernel arguments and used from separate branches
-// (selecting one into a private copy would spill its indexed arrays to scratch).
-__global__ __launch_bounds__(WG) void k_persistent(RoundArgs a_odd, RoundArgs a_even, int first_round,
-                                                   int max_rounds) {
+// indices, used from separate branches (selecting one into a private copy would spill
+// its indexed arrays to scratch).  They are constant kernel arguments when the host
+// knows every field, or blocks in device memory written by the on-device plan when
+// the setup results (bucket segments, row order, arc count) never reach the host.
+__device__ __forceinline__ void persistent_rounds(const RoundArgs& a_odd, const RoundArgs& a_even,
+                                                  int first_round, int max_rounds, long long limit) {
     __shared__ RoundLds s;
     __shared__ int boff[NB + 1];
     __shared__ int total;
     int gen = 0;
     int cmax = 0;
     for (int r = first_round; r < max_rounds; ++r) {
-        const bool more = (r & 1) ? persistent_round(a_odd, s, boff, total, gen, cmax)
-                                  : persistent_round(a_even, s, boff, total, gen, cmax);
+        const bool more = (r & 1) ? persistent_round(a_odd, s, boff, total, gen, cmax, limit)
+                                  : persistent_round(a_even, s, boff, total, gen, cmax, limit);
         if (!more) break;
     }
     cmax = block_max(cmax, s.red);
     if (threadIdx.x == 0 && cmax > 0) atomicMax(&a_odd.ctl->maxcolor, cmax);
+}
+
+__global__ __launch_bounds__(WG) void k_persistent(RoundArgs a_odd, RoundArgs a_even, int first_round,
+                                                   int max_rounds, long long limit) {
+    persistent_rounds(a_odd, a_even, first_round, max_rounds, limit);
 }
 
 }  // namespace csrcolor

@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_version_and_strerror(lib):
     assert lib.csrcolor_version() >= 100
-    for code in [L.OK, L.EINVAL, L.EBADCSR, L.ENOMEM, L.EHIP, L.EOVERFLOW, L.ENOTSYM, L.ELIMIT]:
+    for code in [L.OK, L.EINVAL, L.EBADCSR, L.ENOMEM, L.EHIP, L.EOVERFLOW, L.ENOTSYM, L.ELIMIT, L.ETIMEOUT]:
         assert lib.csrcolor_strerror(code)
     assert b"unknown" in lib.csrcolor_strerror(12345)
 
@@ -62,8 +62,11 @@ def test_empty_graph_is_host_only(lib):
     assert lib.csrcolor_color(0, None, None, None, ctypes.byref(nc), None) == L.OK
     assert nc.value == 0
     st = L.Stats()
-    assert lib.csrcolor_color_ex(0, None, None, None, ctypes.byref(nc), None, ctypes.byref(st), None) == L.OK
+    # the colour count of csrcolor_color_ex is a device pointer: none is passed here
+    assert lib.csrcolor_color_ex(0, None, None, None, None, None, ctypes.byref(st), None) == L.OK
     assert st.rounds == 0 and st.ncolors == 0
+    # the asynchronous (device-planned) form of an empty graph touches no memory either
+    assert lib.csrcolor_color_ex(0, None, None, None, None, None, None, None) == L.OK
 
 
 def test_algorithm_option_errors_without_device_work(lib):

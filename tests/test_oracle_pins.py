@@ -138,6 +138,74 @@ def test_invariants_workload_shapes(oracle_mod):
         _invariants(oracle_mod, g, res)
 
 
+# Hand-counted verdicts of the two checkers on known colourings (0-based colours).
+# conflicts = directed arcs (v, w), v != w, with equal colours: each monochromatic edge
+# counts twice.  non_grundy = vertices whose colour is not the smallest colour missing
+# among their neighbours.
+CHECKER_CASES = [
+    # name, n, edges, colours, conflicts, non_grundy
+    ("K3 proper", 3, [(0, 1), (1, 2), (2, 0)], [0, 1, 2], 0, 0),
+    ("K3 one clash", 3, [(0, 1), (1, 2), (2, 0)], [0, 0, 1], 2, 2),      # v0, v1: mex {0,1} = 2
+    ("K3 monochrome", 3, [(0, 1), (1, 2), (2, 0)], [0, 0, 0], 6, 3),     # every mex {0} = 1
+    ("C5 SGR result", 5, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 0)], [0, 1, 0, 2, 1], 0, 0),
+    ("C5 closing clash", 5, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 0)], [0, 1, 0, 1, 0], 2, 2),
+    # v0 neighbours {1, 0}: mex 2; v4 neighbours {1, 0}: mex 2
+    ("C5 swapped 3,4", 5, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 0)], [0, 1, 0, 1, 2], 0, 0),
+    # proper; v3 neighbours {0, 2}: mex 1 ok; v4 neighbours {1, 0}: mex 2 ok
+    ("P4 Grundy", 4, [(0, 1), (1, 2), (2, 3)], [0, 1, 0, 1], 0, 0),
+    ("P4 end one above mex", 4, [(0, 1), (1, 2), (2, 3)], [0, 1, 0, 2], 0, 1),   # v3: mex {0} = 1
+    ("P4 inner one above mex", 4, [(0, 1), (1, 2), (2, 3)], [0, 2, 0, 1], 0, 1),  # v1: mex {0} = 1
+    ("P4 colour below mex", 4, [(0, 1), (1, 2), (2, 3)], [0, 1, 1, 0], 2, 2),
+    # v1 {0, 1}: mex 2; v2 {1, 0}: mex 2; v3 {1}: mex 0 ok
+    ("star centre 2", 6, [(0, k) for k in range(1, 6)], [2, 0, 0, 0, 0, 0], 0, 1),  # centre: mex {0} = 1
+    ("star leaves 1", 6, [(0, k) for k in range(1, 6)], [0, 1, 1, 1, 1, 1], 0, 0),
+    ("edge both 1", 2, [(0, 1)], [1, 1], 2, 2),
+    ("edgeless all 1", 3, [], [1, 1, 1], 0, 3),                           # mex of nothing = 0
+]
+
+
+@pytest.mark.parametrize("case", CHECKER_CASES, ids=[c[0] for c in CHECKER_CASES])
+def test_checkers_on_known_colourings(oracle_mod, case):
+    """The proper and Grundy checkers that the invariant pins rely on give the exact
+    hand-counted numbers on good and bad colourings (a checker that always returned 0,
+    or took the mex one off, fails here)."""
+    _, n, edges, colours, n_conf, n_ng = case
+    g = gg.from_edges(n, edges)
+    c = np.array(colours, dtype=np.int32)
+    assert oracle_mod.conflicts(g.n, g.rowptr, g.colidx, c) == n_conf
+    assert oracle_mod.non_grundy(g.n, g.rowptr, g.colidx, c) == n_ng
+
+
+def test_checkers_ignore_self_loops_and_count_duplicates_per_arc(oracle_mod):
+    # a self-loop is not a conflict and is not a neighbour for the mex
+    g = gg.raw_csr(2, [[0, 1], [1, 0]])
+    c = np.array([0, 1], dtype=np.int32)
+    assert oracle_mod.conflicts(g.n, g.rowptr, g.colidx, c) == 0
+    assert oracle_mod.non_grundy(g.n, g.rowptr, g.colidx, c) == 0
+    # a duplicated arc is counted once per stored arc
+    g = gg.raw_csr(2, [[1, 1], [0]])
+    c = np.array([0, 0], dtype=np.int32)
+    assert oracle_mod.conflicts(g.n, g.rowptr, g.colidx, c) == 3
+    assert oracle_mod.non_grundy(g.n, g.rowptr, g.colidx, c) == 2
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_checkers_see_one_changed_vertex(oracle_mod, seed):
+    """Recolouring one vertex of an SGR result to a neighbour's colour creates exactly
+    two conflicting arcs per neighbour holding that colour and breaks the Grundy
+    property at that vertex at least."""
+    g = gg.erdos_renyi(400, 2400, seed + 11)
+    res = oracle_mod.sgr(g.n, g.rowptr, g.colidx)
+    rng = np.random.default_rng(seed)
+    for v in rng.choice(np.flatnonzero(g.degrees() > 0), 20, replace=False):
+        nb = g.colidx[g.rowptr[v]:g.rowptr[v + 1]]
+        c = res.colors.copy()
+        c[v] = c[nb[0]]
+        same = int(np.sum(c[nb] == c[v]))
+        assert oracle_mod.conflicts(g.n, g.rowptr, g.colidx, c) == 2 * same
+        assert oracle_mod.non_grundy(g.n, g.rowptr, g.colidx, c) >= 1
+
+
 def test_brute_force_all_graphs_n5(oracle_mod):
     """chi(G) <= ncolors <= Grundy(G) on every labelled graph with 5 vertices."""
     import itertools
