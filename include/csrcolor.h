@@ -61,9 +61,15 @@ typedef enum {
     CSRCOLOR_EOVERFLOW = -5,  /* sizes beyond int32 (batched totals) */
     CSRCOLOR_ENOTSYM = -6,    /* validate >= 1 and the CSR is not symmetric */
     CSRCOLOR_ELIMIT = -7,     /* round limit reached (cannot happen for a valid graph: rounds <= n) */
-    CSRCOLOR_ETIMEOUT = -8    /* a device-wide barrier of the persistent rounds waited more than 8 s:
+    CSRCOLOR_ETIMEOUT = -8,   /* a device-wide barrier of the persistent rounds waited more than 8 s:
                                  the grid was not resident (another persistent kernel held the device) */
+    CSRCOLOR_ETOOBIG = -9     /* csrcolor_color_noalloc: n or nnz above its fixed maxima */
 } csrcolor_status;
+
+/* Fixed maxima of csrcolor_color_noalloc and the size of its scratch array. */
+#define CSRCOLOR_NOALLOC_MAX_N       1048576     /* vertices */
+#define CSRCOLOR_NOALLOC_MAX_NNZ     33554432    /* arcs (directed entries of colidx) */
+#define CSRCOLOR_NOALLOC_SCRATCH_MIB 60          /* device memory per GPU, held until the process ends */
 
 /* How the rounds are driven.  Every mode gives the identical colouring. */
 typedef enum {
@@ -203,6 +209,31 @@ int csrcolor_color(int32_t n, const int32_t *rowptr, const int32_t *colidx,
 int csrcolor_color_ex(int32_t n, const int32_t *rowptr, const int32_t *colidx,
                       int32_t *colors_out, int32_t *ncolors_dev,
                       const csrcolor_opts *opts, csrcolor_stats *stats, hipStream_t stream);
+
+/* For callers that cannot allocate device or host memory (code under hipGraph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): csrcolor_color_ex's asynchronous
+ * (device-planned) colouring with default options, over a fixed scratch array that the
+ * library holds in device memory (CSRCOLOR_NOALLOC_SCRATCH_MIB MiB per GPU it runs on,
+ * from the library's load until the process ends) instead of a workspace it allocates.
+ * The call makes no allocation (no hipMalloc, hipHostMalloc, hipFree or allocating
+ * library routine), no host<->device copy and no wait: it enqueues the validation, the
+ * round-1 kernel, one persistent round kernel (a plain launch of no more workgroups than
+ * fit on the device at once) and the kernel that writes the count, so it can be captured
+ * into a hipGraph.  Live lists are off; the colouring is csrcolor_color_ex's (the same
+ * for every option).
+ *   n            number of vertices, 0 <= n <= CSRCOLOR_NOALLOC_MAX_N
+ *   nnz          number of arcs, 0 <= nnz <= CSRCOLOR_NOALLOC_MAX_NNZ; must equal rowptr[n]
+ *                (checked on the device before any colidx entry is read: EBADCSR)
+ *   rowptr       DEVICE int32[n+1];  colidx DEVICE int32[nnz];  colors_out DEVICE int32[n]
+ *   ncolors_dev  DEVICE int32* (may be NULL): the number of colours, or the negative status
+ *                the device found (EBADCSR, ETIMEOUT)
+ * Returns CSRCOLOR_ETOOBIG (nothing enqueued) when n or nnz exceed the maxima, EINVAL for
+ * bad arguments, EHIP when a launch fails.  Every call on one GPU shares that GPU's
+ * scratch array and leaves its contents there (each call clears what must start at
+ * zero): calls whose work overlaps on one GPU (different streams, or host threads
+ * without ordering) race and give undefined results; order them on one stream. */
+int csrcolor_color_noalloc(int32_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colidx,
+                           int32_t *colors_out, int32_t *ncolors_dev, hipStream_t stream);
 
 /* Colour G independent graphs stored as one block-diagonal CSR with global ids
  * (graph g owns vertices voff[g] .. voff[g+1]-1; its arcs must stay inside that

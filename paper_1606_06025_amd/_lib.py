@@ -22,6 +22,10 @@ EOVERFLOW = -5
 ENOTSYM = -6
 ELIMIT = -7
 ETIMEOUT = -8
+ETOOBIG = -9
+
+NOALLOC_MAX_N = 1048576
+NOALLOC_MAX_NNZ = 33554432
 
 RULE_ID = 0
 RULE_DEGREE = 1
@@ -36,7 +40,7 @@ MODE_PERSISTENT = 2
 MODE_GRAPH = 3
 
 EXPORTS = ["csrcolor_color", "csrcolor_color_ex", "csrcolor_color_batched", "csrcolor_color_multi",
-           "csrcolor_strerror", "csrcolor_release_workspace", "csrcolor_version"]
+           "csrcolor_color_noalloc", "csrcolor_strerror", "csrcolor_release_workspace", "csrcolor_version"]
 
 
 class Opts(ctypes.Structure):
@@ -84,6 +88,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     # the colour-count argument of csrcolor_color_ex is a DEVICE pointer
     lib.csrcolor_color_ex.argtypes = [I32, P, P, P, P, ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
     lib.csrcolor_color_ex.restype = ctypes.c_int
+    # csrcolor_color_noalloc: n, nnz, rowptr, colidx, colors_out, DEVICE colour count, stream
+    lib.csrcolor_color_noalloc.argtypes = [I32, ctypes.c_int64, P, P, P, P, P]
+    lib.csrcolor_color_noalloc.restype = ctypes.c_int
     lib.csrcolor_color_batched.argtypes = [I32, I32, P, P, P, P, P, ctypes.POINTER(Opts), P]
     lib.csrcolor_color_batched.restype = ctypes.c_int
     lib.csrcolor_color_multi.argtypes = [I32, P, P, P, P, P, P, ctypes.POINTER(Opts), P]

@@ -128,6 +128,25 @@ def color_async(rowptr: torch.Tensor, colidx: torch.Tensor, out: Optional[torch.
     return out[:n], ncolors
 
 
+def color_noalloc(rowptr: torch.Tensor, colidx: torch.Tensor, out: torch.Tensor, ncolors: torch.Tensor,
+                  nnz: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None) -> None:
+    """Colour one graph without any allocation by the library (csrcolor_color_noalloc:
+    the device-planned run over the library's fixed scratch array).  The caller passes
+    the outputs: `out` int32[n] and `ncolors` int32[1] on the device; `nnz` defaults to
+    colidx.numel().  Returns without waiting; ncolors[0] receives the colour count or a
+    negative status found on the device."""
+    lib = L.load()
+    n = _check_csr(rowptr, colidx)
+    if out.dtype != torch.int32 or out.numel() < n or not out.is_cuda:
+        raise ValueError("out must be an int32 device tensor with n entries")
+    if ncolors.dtype != torch.int32 or ncolors.numel() < 1 or not ncolors.is_cuda:
+        raise ValueError("ncolors must be an int32 device tensor")
+    m = colidx.numel() if nnz is None else int(nnz)
+    rc = lib.csrcolor_color_noalloc(n, m, rowptr.data_ptr(), colidx.data_ptr() if colidx.numel() else None,
+                                    out.data_ptr(), ncolors.data_ptr(), _stream_ptr(stream))
+    L.check(rc)
+
+
 def color_raw(n: int, rowptr_ptr: int, colidx_ptr: int, out_ptr: int,
               stream: Optional[torch.cuda.Stream] = None) -> int:
     """csrcolor_color on raw device pointers; returns the status code unchanged."""

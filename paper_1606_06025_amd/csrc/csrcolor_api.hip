@@ -447,6 +447,7 @@ struct Job {
     bool wake = false;       // the rounds ran with wake flags (statistics from settling rounds)
     int maxdeg = 0;
     long long nnz = 0;
+    long long expect_nnz = -1;   // the caller's arc count, checked against rowptr[n] (-1: none given)
 };
 
 // Host loop: k_assign + k_detect per round with a host-computed partition; the queue
@@ -961,48 +962,26 @@ long long barrier_limit(int dev) {
     return 8000LL * g_wall_khz[dev];
 }
 
-// Device-planned run (the rounds of Sec. 3.1 driven on the device, see sgr_plan.h):
-// everything is enqueued on the workspace stream.  The arc-sized buffers (push flags,
-// live lists, split-row scratch) are sized on the host from a read-back of rowptr[n]
-// when the call is synchronous (`sync`) or the workspace has never been sized for this
-// many vertices; otherwise the call makes no allocation, no copy and no wait, and the
-// plan kernel checks that the graph fits (ERR_NOMEM when it does not).  With `sync`
-// the call waits and fills J (colour count, rounds, statistics) or returns the status
-// the device found; `ncolors_dev` (device, may be null) receives the colour count, or
-// for G > 0 graphs one count per graph, or the negative status.
-int run_device(Workspace* w, Job& J, const long long* voff, int G, int* ncolors_dev, bool sync) {
+// Launches of a device-planned run over a workspace whose buffers are already sized
+// (every size the kernels rely on is checked again on the device by the plan kernel).
+// `plain` launches the persistent round kernel as an ordinary kernel of no more
+// workgroups than fit on the device at once (for stream capture and for the
+// allocation-free entry point; its barriers are bounded, so a grid that is not
+// resident ends with CSRCOLOR_ETIMEOUT), else cooperatively.  Makes no allocation,
+// no copy and no wait.
+int enqueue_device(Workspace* w, Job& J, const long long* voff, int G, int* ncolors_dev, KTimer& T, bool plain,
+                   int* vblocks_out) {
     const int n = J.n;
     hipStream_t st = w->stream;
     const Options& o = J.opt;
     const int st_cap = J.stats ? std::max(J.stats->cap, 0) : 0;
-    // the arc-sized buffers must cover every graph of at most cap_n vertices and arc_cap
-    // arcs (a host-driven call may have grown the vertex arrays since they were sized)
-    const bool covered = w->arc_cap > 0 && w->F_cap >= (w->cap_n + (size_t)w->arc_cap) / 4 + 4 &&
-                         w->split_cap >= (size_t)(w->arc_cap / 23 + 64) && w->live_cap >= (size_t)w->arc_cap;
-    const bool fresh = (size_t)n > w->cap_n || !w->ctl || !w->plan || !covered;
-    int rc = ensure_capacity(w, (size_t)n, st_cap);
-    if (rc) return rc;
-    if (!w->plan && hipMalloc(&w->plan, sizeof(DevPlan)) != hipSuccess) return CSRCOLOR_ENOMEM;
-    if (!w->sz_h && hipHostMalloc(&w->sz_h, sizeof(int), hipHostMallocDefault) != hipSuccess) return CSRCOLOR_ENOMEM;
-    if (sync || fresh) {
-        HIP_TRY(hipMemcpyAsync(w->sz_h, J.rowptr + n, sizeof(int), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        const long long arcs = std::max<long long>(std::max(*w->sz_h, 0), w->arc_cap);
-        // byte flags for every vertex and arc the workspace holds (the larger flag
-        // variant); split-row scratch for the most hubs and chunks that many arcs allow
-        // (a hub has more than 1024 arcs: 36 ints per hub, 5 per 2048-arc chunk)
-        if ((rc = ensure_F(w, (size_t)((w->cap_n + arcs) / 4 + 4)))) return rc;
-        if ((rc = ensure_split(w, (size_t)(arcs / 23 + 64)))) return rc;
-        if ((rc = ensure_live(w, (size_t)std::max<long long>(arcs, 1)))) return rc;
-        w->arc_cap = std::max<long long>(arcs, 1);
-    }
     const int cus = num_cus(w->device);
     const int budget = cus * o.blocks_per_cu;
     const int grid = persistent_grid(w->device, n, budget);
     const int r1blocks = (int)(((long long)n + 4 * WG - 1) / (4 * WG));
     unsigned long long* lb = nullptr;
     if (o.ordered) {
-        if ((rc = ensure_lb(w, std::max((size_t)NB * r1blocks, (size_t)grid + 2 * NB + 8)))) return rc;
+        if (!w->lb || w->lb_cap < std::max((size_t)NB * r1blocks, (size_t)grid + 2 * NB + 8)) return CSRCOLOR_EINVAL;
         lb = w->lb;
     }
 
@@ -1040,14 +1019,14 @@ int run_device(Workspace* w, Job& J, const long long* voff, int G, int* ncolors_
     c.split = w->split;
     c.lb1 = lb;
     c.lb1_ints = lb ? 2 * NB * r1blocks : 0;
-    c.want_live = o.live && o.rule == 0;
+    c.want_live = o.live && o.rule == 0 && w->live != nullptr;
 
-    KTimer T(w, J.stats && J.stats->time_kernels);
     T.run(0, [&] { k_init<<<1, WG, 0, st>>>(w->ctl); });
     const int vblocks = (int)std::min<long long>(((long long)n + WG - 1) / WG, (long long)cus * 4);
+    if (vblocks_out) *vblocks_out = vblocks;
     const int rblocks = (int)std::max<long long>(
         1, std::min<long long>(((long long)n + WG * VROWS - 1) / (WG * VROWS), (long long)cus * 4));
-    T.kern(0, k_validate_rows, rblocks, WG, n, J.rowptr, J.colidx, w->ctl, o.twave, o.tsplit);
+    T.kern(0, k_validate_rows, rblocks, WG, n, J.rowptr, J.colidx, w->ctl, o.twave, o.tsplit, J.expect_nnz);
     T.kern(0, k_validate_arcs, cus * 4, WG, n, J.rowptr, J.colidx, w->ctl);
     if (voff) k_validate_batch<<<std::min(G, cus * 16), WG, 0, st>>>(G, n, voff, J.rowptr, J.colidx, w->ctl);
     if (o.validate >= 1) k_check_symmetric<<<std::max(vblocks, 1), WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl);
@@ -1063,18 +1042,12 @@ int run_device(Workspace* w, Job& J, const long long* voff, int G, int* ncolors_
         k_round1_dev<<<std::max(r1blocks, 1), WG, 0, st>>>(w->plan);
     });
     HIP_TRY(hipGetLastError());
-    // every later round in one launch: cooperative (the runtime guarantees that every
-    // workgroup is resident) unless the stream is being captured into a graph, where a
-    // plain launch of no more workgroups than fit at once is used (its barriers are
-    // bounded, so a grid that is not resident ends with CSRCOLOR_ETIMEOUT)
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(st, &cs) != hipSuccess) cs = hipStreamCaptureStatusNone;
     const DevPlan* plan = w->plan;
     int maxr = n + 2;
     long long limit = barrier_limit(w->device);
     hipError_t e = hipSuccess;
     T.run(1, [&] {
-        if (cs == hipStreamCaptureStatusActive) {
+        if (plain) {
             k_persistent_dev<<<grid, WG, 0, st>>>(plan, maxr, limit);
             e = hipGetLastError();
         } else {
@@ -1088,6 +1061,57 @@ int run_device(Workspace* w, Job& J, const long long* voff, int G, int* ncolors_
         k_dev_finish<<<fg, WG, 0, st>>>(w->ctl, G, voff, J.colors_out, ncolors_dev);
         HIP_TRY(hipGetLastError());
     }
+    return CSRCOLOR_OK;
+}
+
+// Device-planned run (the rounds of Sec. 3.1 driven on the device, see sgr_plan.h):
+// everything is enqueued on the workspace stream.  The arc-sized buffers (push flags,
+// live lists, split-row scratch) are sized on the host from a read-back of rowptr[n]
+// when the call is synchronous (`sync`) or the workspace has never been sized for this
+// many vertices; otherwise the call makes no allocation, no copy and no wait, and the
+// plan kernel checks that the graph fits (ERR_NOMEM when it does not).  With `sync`
+// the call waits and fills J (colour count, rounds, statistics) or returns the status
+// the device found; `ncolors_dev` (device, may be null) receives the colour count, or
+// for G > 0 graphs one count per graph, or the negative status.
+int run_device(Workspace* w, Job& J, const long long* voff, int G, int* ncolors_dev, bool sync) {
+    const int n = J.n;
+    hipStream_t st = w->stream;
+    const Options& o = J.opt;
+    const int st_cap = J.stats ? std::max(J.stats->cap, 0) : 0;
+    // the arc-sized buffers must cover every graph of at most cap_n vertices and arc_cap
+    // arcs (a host-driven call may have grown the vertex arrays since they were sized)
+    const bool covered = w->arc_cap > 0 && w->F_cap >= (w->cap_n + (size_t)w->arc_cap) / 4 + 4 &&
+                         w->split_cap >= (size_t)(w->arc_cap / 23 + 64) && w->live_cap >= (size_t)w->arc_cap;
+    const bool fresh = (size_t)n > w->cap_n || !w->ctl || !w->plan || !covered;
+    int rc = ensure_capacity(w, (size_t)n, st_cap);
+    if (rc) return rc;
+    if (!w->plan && hipMalloc(&w->plan, sizeof(DevPlan)) != hipSuccess) return CSRCOLOR_ENOMEM;
+    if (!w->sz_h && hipHostMalloc(&w->sz_h, sizeof(int), hipHostMallocDefault) != hipSuccess) return CSRCOLOR_ENOMEM;
+    if (sync || fresh) {
+        HIP_TRY(hipMemcpyAsync(w->sz_h, J.rowptr + n, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const long long arcs = std::max<long long>(std::max(*w->sz_h, 0), w->arc_cap);
+        // byte flags for every vertex and arc the workspace holds (the larger flag
+        // variant); split-row scratch for the most hubs and chunks that many arcs allow
+        // (a hub has more than 1024 arcs: 36 ints per hub, 5 per 2048-arc chunk)
+        if ((rc = ensure_F(w, (size_t)((w->cap_n + arcs) / 4 + 4)))) return rc;
+        if ((rc = ensure_split(w, (size_t)(arcs / 23 + 64)))) return rc;
+        if ((rc = ensure_live(w, (size_t)std::max<long long>(arcs, 1)))) return rc;
+        w->arc_cap = std::max<long long>(arcs, 1);
+    }
+    if (o.ordered) {
+        const int cus = num_cus(w->device);
+        const int grid = persistent_grid(w->device, n, cus * o.blocks_per_cu);
+        const int r1blocks = (int)(((long long)n + 4 * WG - 1) / (4 * WG));
+        if ((rc = ensure_lb(w, std::max((size_t)NB * r1blocks, (size_t)grid + 2 * NB + 8)))) return rc;
+    }
+    // every later round in one launch: cooperative (the runtime guarantees that every
+    // workgroup is resident) unless the stream is being captured into a graph
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) cs = hipStreamCaptureStatusNone;
+    KTimer T(w, J.stats && J.stats->time_kernels);
+    int vblocks = 0;
+    if ((rc = enqueue_device(w, J, voff, G, ncolors_dev, T, cs == hipStreamCaptureStatusActive, &vblocks))) return rc;
     if (!sync) return CSRCOLOR_OK;
     if ((rc = read_ctl(w))) return rc;
     if ((rc = status_of(w->ctl_h))) return rc;
@@ -1112,7 +1136,7 @@ int run_job(Workspace* w, Job& J, const long long* voff, int G) {
     const int vblocks = (int)std::min<long long>(((long long)n + WG - 1) / WG, (long long)cus * 4);
     const int rblocks = (int)std::max<long long>(
         1, std::min<long long>(((long long)n + WG * VROWS - 1) / (WG * VROWS), (long long)cus * 4));
-    T.kern(0, k_validate_rows, rblocks, WG, n, J.rowptr, J.colidx, w->ctl, twave, J.opt.tsplit);
+    T.kern(0, k_validate_rows, rblocks, WG, n, J.rowptr, J.colidx, w->ctl, twave, J.opt.tsplit, -1LL);
     // the arc pass skips itself when the vertex pass found an error, so one read-back
     // covers both
     T.kern(0, k_validate_arcs, cus * 4, WG, n, J.rowptr, J.colidx, w->ctl);
@@ -1147,6 +1171,81 @@ int run_job(Workspace* w, Job& J, const long long* voff, int G) {
     }
     if (rc) return rc;
     return finish_job(w, J, st_cap, T, vblocks);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free colouring (csrcolor_color_noalloc): the device-planned run over a
+// fixed scratch array in the library's own device memory, for callers that cannot
+// allocate.  Layout (byte offsets, each part 256-byte aligned): control block, plan
+// block, colour state, two worklists, conflict hints, live-list lengths (split rows'
+// chunk bases), dirty bytes, byte flags of the forbidden colours for every vertex and
+// arc, split-row scratch.  Live lists are off (they would need 4 bytes per arc more).
+// ---------------------------------------------------------------------------
+constexpr size_t na_align(size_t x) { return (x + 255) / 256 * 256; }
+constexpr size_t NA_N = CSRCOLOR_NOALLOC_MAX_N;
+constexpr size_t NA_E = CSRCOLOR_NOALLOC_MAX_NNZ;
+constexpr size_t NA_F_WORDS = (NA_N + NA_E) / 4 + 4;
+constexpr size_t NA_SPLIT_INTS = NA_E / 23 + 64;
+constexpr size_t NA_CTL = 0;
+constexpr size_t NA_PLAN = na_align(sizeof(Ctl));
+constexpr size_t NA_X = NA_PLAN + na_align(sizeof(DevPlan));
+constexpr size_t NA_WL0 = NA_X + na_align(4 * NA_N);
+constexpr size_t NA_WL1 = NA_WL0 + na_align(4 * NA_N);
+constexpr size_t NA_HINT = NA_WL1 + na_align(4 * NA_N);
+constexpr size_t NA_LLEN = NA_HINT + na_align(4 * NA_N);
+constexpr size_t NA_DIRTY = NA_LLEN + na_align(4 * NA_N);
+constexpr size_t NA_F = NA_DIRTY + na_align(NA_N + 16);
+constexpr size_t NA_SPLIT = NA_F + na_align(4 * NA_F_WORDS);
+constexpr size_t NA_BYTES = NA_SPLIT + na_align(4 * NA_SPLIT_INTS);
+static_assert(NA_BYTES <= ((size_t)CSRCOLOR_NOALLOC_SCRATCH_MIB << 20), "scratch layout exceeds its stated size");
+
+// One copy per device, held from the code object's load until the process ends.  In
+// host code this name is only a stand-in for the symbol: kernels receive the device
+// address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+struct NoAllocDev {
+    bool ready = false;
+    unsigned char* ptr = nullptr;   // this device's address of `scratch`
+    Workspace ws;                   // views into it; never freed
+};
+NoAllocDev g_na[64];
+std::mutex g_na_mu;
+
+// The workspace of the allocation-free entry point on device `dev` (the current
+// device): on the first call, looks up this device's address of the scratch array
+// and lays the buffers out in it.
+Workspace* noalloc_ws(int dev, int* rc) {
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    NoAllocDev& d = g_na[dev];
+    if (!d.ready) {
+        unsigned char* ptr = nullptr;
+        if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            *rc = CSRCOLOR_EHIP;
+            return nullptr;
+        }
+        Workspace& w = d.ws;
+        w.device = dev;
+        w.cap_n = NA_N;
+        w.ctl = reinterpret_cast<Ctl*>(ptr + NA_CTL);
+        w.plan = reinterpret_cast<DevPlan*>(ptr + NA_PLAN);
+        w.X = reinterpret_cast<int*>(ptr + NA_X);
+        w.wl[0] = reinterpret_cast<int*>(ptr + NA_WL0);
+        w.wl[1] = reinterpret_cast<int*>(ptr + NA_WL1);
+        w.hint = reinterpret_cast<int*>(ptr + NA_HINT);
+        w.llen = reinterpret_cast<int*>(ptr + NA_LLEN);
+        w.dirty = ptr + NA_DIRTY;
+        w.F = reinterpret_cast<unsigned*>(ptr + NA_F);
+        w.F_cap = NA_F_WORDS;
+        w.split = reinterpret_cast<int*>(ptr + NA_SPLIT);
+        w.split_cap = NA_SPLIT_INTS;
+        w.live = nullptr;
+        w.live_cap = 0;
+        w.arc_cap = (long long)NA_E;
+        d.ptr = ptr;
+        d.ready = true;
+    }
+    return &d.ws;
 }
 
 }  // namespace
@@ -1248,6 +1347,39 @@ int csrcolor_color(int32_t n, const int32_t* rowptr, const int32_t* colidx, int3
                    int32_t* ncolors, hipStream_t stream) {
     if (!ncolors) return CSRCOLOR_EINVAL;
     return color_host(n, rowptr, colidx, colors_out, ncolors, nullptr, nullptr, stream);
+}
+
+int csrcolor_color_noalloc(int32_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx,
+                           int32_t* colors_out, int32_t* ncolors_dev, hipStream_t stream) {
+    if (n < 0 || nnz < 0) return CSRCOLOR_EINVAL;
+    if ((size_t)n > NA_N || (size_t)nnz > NA_E) return CSRCOLOR_ETOOBIG;
+    if (n == 0) {
+        if (ncolors_dev) {
+            k_fill<<<1, 64, 0, stream>>>(ncolors_dev, 1, 0);
+            if (hipGetLastError() != hipSuccess) return CSRCOLOR_EHIP;
+        }
+        return CSRCOLOR_OK;
+    }
+    if (!rowptr || !colors_out || (nnz > 0 && !colidx)) return CSRCOLOR_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return CSRCOLOR_EHIP;
+    if (dev < 0 || dev >= 64) return CSRCOLOR_EINVAL;
+    int rc = CSRCOLOR_OK;
+    Workspace* w = noalloc_ws(dev, &rc);
+    if (!w) return rc;
+    std::lock_guard<std::mutex> lk(w->mu);
+    w->stream = stream;
+    Job J;
+    J.n = n;
+    J.rowptr = rowptr;
+    J.colidx = colidx;
+    J.colors_out = colors_out;
+    J.opt.mode = CSRCOLOR_MODE_PERSISTENT;
+    J.opt.live = 0;
+    J.stats = nullptr;
+    J.expect_nnz = nnz;
+    KTimer T(w, false);
+    return enqueue_device(w, J, nullptr, 0, ncolors_dev, T, true, nullptr);
 }
 
 int csrcolor_color_batched(int32_t G, int32_t n_total, const int64_t* voff, const int32_t* rowptr,
@@ -1377,6 +1509,7 @@ const char* csrcolor_strerror(int status) {
         case CSRCOLOR_ENOTSYM: return "CSR is not symmetric";
         case CSRCOLOR_ELIMIT: return "round limit exceeded";
         case CSRCOLOR_ETIMEOUT: return "a device-wide barrier timed out (the persistent grid was not resident)";
+        case CSRCOLOR_ETOOBIG: return "graph larger than the fixed scratch of the allocation-free entry point";
         default: return "unknown status";
     }
 }

@@ -18,9 +18,11 @@ __global__ void k_init(Ctl* ctl) {
 
 // ---------------------------------------------------------------------------
 // Structural validation, degree histogram and row-order detection, two launches.
-// Vertex pass: rowptr[0] == 0, 0 <= rowptr[v] <= rowptr[v+1] <= rowptr[n]; degree
-// histogram, largest degree, arcs of the rows longer than WAKE_DEG; counts descents
-// colidx[e] < colidx[e-1] at positions e that start a non-empty row.
+// Vertex pass: rowptr[0] == 0, 0 <= rowptr[v] <= rowptr[v+1] <= rowptr[n], and
+// rowptr[n] equal to the caller's arc count when one is given (expect_nnz >= 0; on a
+// mismatch no colidx entry is read); degree histogram, largest degree, arcs of the
+// rows longer than WAKE_DEG; counts descents colidx[e] < colidx[e-1] at positions e
+// that start a non-empty row.
 // Arc pass, only once the vertex pass found rowptr consistent (so [0, rowptr[n]) is
 // the caller's colidx extent): colidx[e] in [0, n); counts all descents.  Rows are
 // sorted iff both descent counts agree.
@@ -30,9 +32,10 @@ constexpr int VQUADS = 4;  // 16-byte quads of colidx per lane and loop pass of 
 
 __global__ __launch_bounds__(WG) void k_validate_rows(int n, const int* __restrict__ rowptr,
                                                       const int* __restrict__ colidx, Ctl* ctl, int twave,
-                                                      int tsplit) {
+                                                      int tsplit, long long expect_nnz) {
     const int nnz = rowptr[n];
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->nnz = nnz;
+    const bool stated = expect_nnz < 0 || (long long)nnz == expect_nnz;
     int mydeg = 0;
     int hist[NB] = {};
     int bad = 0, desc = 0, chunks = 0;
@@ -50,7 +53,7 @@ __global__ __launch_bounds__(WG) void k_validate_rows(int n, const int* __restri
                 beg[k] = rowptr[v];
                 end[k] = rowptr[v + 1];
             }
-            ok[k] = beg[k] >= 0 && beg[k] <= end[k] && end[k] <= nnz && (v != 0 || beg[k] == 0);
+            ok[k] = stated && beg[k] >= 0 && beg[k] <= end[k] && end[k] <= nnz && (v != 0 || beg[k] == 0);
         }
 #pragma unroll
         for (int k = 0; k < VROWS; ++k) {
@@ -78,7 +81,7 @@ __global__ __launch_bounds__(WG) void k_validate_rows(int n, const int* __restri
             }
         }
     }
-    if (nnz < 0 || (colidx == nullptr && nnz != 0)) bad = 1;
+    if (nnz < 0 || !stated || (colidx == nullptr && nnz != 0)) bad = 1;
     __shared__ int red[WAVES];
     bad = block_max(bad, red);
     mydeg = block_max(mydeg, red);

@@ -45,6 +45,10 @@ struct DevPlan {
 __global__ void k_dev_plan(RoundArgs t, DevCaps c, DevPlan* p) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     Ctl* ctl = t.ctl;
+    // the kernels after the plan find the control block (and its error bits) here, also
+    // when the plan stops early; the rest of the block is only read once no error is set
+    p->odd.ctl = ctl;
+    p->even.ctl = ctl;
     if (ctl->err) return;
     const int n = t.n;
     const int nnz = ctl->nnz;

@@ -38,7 +38,8 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_version_and_strerror(lib):
     assert lib.csrcolor_version() >= 100
-    for code in [L.OK, L.EINVAL, L.EBADCSR, L.ENOMEM, L.EHIP, L.EOVERFLOW, L.ENOTSYM, L.ELIMIT, L.ETIMEOUT]:
+    for code in [L.OK, L.EINVAL, L.EBADCSR, L.ENOMEM, L.EHIP, L.EOVERFLOW, L.ENOTSYM, L.ELIMIT, L.ETIMEOUT,
+                 L.ETOOBIG]:
         assert lib.csrcolor_strerror(code)
     assert b"unknown" in lib.csrcolor_strerror(12345)
 
@@ -112,3 +113,23 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(L.Stats) == 4 * 4 + 8 + 2 * 4 + 2 * 8 + 3 * 8 + 2 * 4 + 8
     assert _header_struct_fields("csrcolor_opts") == [f[0] for f in L.Opts._fields_]
     assert _header_struct_fields("csrcolor_stats") == [f[0] for f in L.Stats._fields_]
+
+
+def test_noalloc_limits_without_device_work(lib):
+    """The allocation-free entry point refuses sizes above its fixed maxima, and bad
+    arguments, before it touches the device; an empty graph with no count slot is a
+    no-op."""
+    assert lib.csrcolor_color_noalloc(L.NOALLOC_MAX_N + 1, 0, 1, 1, 1, None, None) == L.ETOOBIG
+    assert lib.csrcolor_color_noalloc(3, L.NOALLOC_MAX_NNZ + 1, 1, 1, 1, None, None) == L.ETOOBIG
+    assert lib.csrcolor_color_noalloc(-1, 0, None, None, None, None, None) == L.EINVAL
+    assert lib.csrcolor_color_noalloc(3, -1, 1, 1, 1, None, None) == L.EINVAL
+    assert lib.csrcolor_color_noalloc(3, 4, None, 1, 1, None, None) == L.EINVAL
+    assert lib.csrcolor_color_noalloc(3, 4, 1, None, 1, None, None) == L.EINVAL
+    assert lib.csrcolor_color_noalloc(3, 4, 1, 1, None, None, None) == L.EINVAL
+    assert lib.csrcolor_color_noalloc(0, 0, None, None, None, None, None) == L.OK
+
+
+def test_noalloc_limits_match_header():
+    txt = open(HEADER).read()
+    assert re.search(r"#define CSRCOLOR_NOALLOC_MAX_N\s+%d\b" % L.NOALLOC_MAX_N, txt)
+    assert re.search(r"#define CSRCOLOR_NOALLOC_MAX_NNZ\s+%d\b" % L.NOALLOC_MAX_NNZ, txt)
