@@ -19,6 +19,7 @@ natural-order FirstFit on the same graph and the host CPU model.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -442,6 +443,18 @@ def bench_batched(args, dev) -> int:
     same = all(np.array_equal(colors_b[b.voff[i]:b.voff[i + 1]], dev_parts[i][2].cpu().numpy())
                and int(ncol[i]) == int(dev_parts[i][2].max().item()) + 1 for i in range(len(parts)))
     log(f"one graph per launch: {ms_single:.2f} ms for all {len(parts)} graphs; identical colourings: {same}")
+    # the batched colouring against the oracle's, per graph (digests stored by
+    # tests/golden/make_golden.py for the 2048-graph set of seed 1)
+    oracle_match = None
+    gpath = os.path.join(ROOT, "tests", "golden", f"batched_s{args.seed}.json")
+    if os.path.exists(gpath):
+        gold = json.load(open(gpath))
+        if gold.get("G") == b.G and gold.get("nnz") == b.nnz:
+            oracle_match = all(
+                hashlib.sha256(np.ascontiguousarray(colors_b[b.voff[i]:b.voff[i + 1]], dtype=np.int32)
+                               .tobytes()).hexdigest()[:16] == gold["colors_sha256_16"][i]
+                and int(ncol[i]) == gold["ncolors"][i] for i in range(b.G))
+            log(f"batched colourings equal the oracle's stored digests: {oracle_match}")
     rec = {
         "metric": "arcs/s per round-complete coloring (batched)",
         "value": b.nnz / (ms_batched * 1e-3),
@@ -460,12 +473,13 @@ def bench_batched(args, dev) -> int:
                    "one_graph_per_launch_arcs_per_s": b.nnz / (ms_single * 1e-3),
                    "batched_speedup": ms_single / ms_batched,
                    "identical_colourings": bool(same),
+                   "equals_oracle_digests": oracle_match,
                    **{k: v for k, v in tuned.items() if v}},
         "roofline": None,
         "cpu_baseline": None,
     }
     print(json.dumps(rec), flush=True)
-    return 0 if same else 1
+    return 0 if same and oracle_match is not False else 1
 
 
 def bench_serve(args, dev) -> int:

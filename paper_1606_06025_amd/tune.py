@@ -26,7 +26,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "csrcolor", "tun
 KNOBS: List[Tuple[str, Sequence[int]]] = [
     ("wake", (0, 1, -1)),
     ("firstfit", (3, 2, 1)),
-    ("mode", (1, 3)),
+    ("mode", (1, 3, 2)),
     ("t_wave", (1024, 256, 128)),
     ("t_split", (2048, 8192, 1024)),
     ("blocks_per_cu", (6, 4, 8)),

@@ -53,10 +53,14 @@ def test_color_multi_rejects_bad_graph(dev):
 
 
 def test_server_alone_vs_mix(dev):
-    """Also the regression case of the first multi-graph call on fresh streams (each
-    slot's workspace starts empty and grows while the union is being built)."""
+    """Every served result is the CPU oracle's colouring, and the one the graph gets
+    alone (tolerance 0).  Also the regression case of the first multi-graph call on
+    fresh streams (each slot's workspace starts empty and grows while the union is
+    being built)."""
+    import oracle
     from paper_1606_06025_amd import api, serve
     gs = _mix(24, 7)
+    refs = [oracle.sgr(g.n, g.rowptr, g.colidx) for g in gs]
     # alone: one library call per graph
     alone = []
     for g in gs:
@@ -72,6 +76,7 @@ def test_server_alone_vs_mix(dev):
             assert r.wait(timeout=60)
         assert srv.peak_bytes <= budget
     assert max(r.batch_size for r in reqs) > 1
-    for (c, nc), r in zip(alone, reqs):
+    for (c, nc), r, ref in zip(alone, reqs, refs):
         assert r.error is None
+        assert np.array_equal(r.colors, ref.colors) and r.ncolors == ref.ncolors
         assert np.array_equal(r.colors, c) and r.ncolors == nc
