@@ -69,7 +69,7 @@ typedef enum {
 /* Fixed maxima of csrcolor_color_noalloc and the size of its scratch array. */
 #define CSRCOLOR_NOALLOC_MAX_N       1048576     /* vertices */
 #define CSRCOLOR_NOALLOC_MAX_NNZ     33554432    /* arcs (directed entries of colidx) */
-#define CSRCOLOR_NOALLOC_SCRATCH_MIB 60          /* device memory per GPU, held until the process ends */
+#define CSRCOLOR_NOALLOC_SCRATCH_MIB 81          /* device memory per GPU, held until the process ends */
 
 /* How the rounds are driven.  Every mode gives the identical colouring. */
 typedef enum {
@@ -118,8 +118,11 @@ typedef struct {
     int32_t sync_every;     /* LOOP/GRAPH: rounds enqueued between worklist-size read-backs (default 8) */
     int32_t lane_assign;    /* bit b (b < 4): low-degree bucket b runs FirstFit one lane per vertex;
                                0 = default; -1 = none (all use 2/4/8/16 lanes per vertex) */
-    int32_t lane_detect;    /* the same for the conflict test; by default none: L lanes per vertex, over
-                               only the vertices their conflict hint did not decide */
+    int32_t lane_detect;    /* conflict test of the buckets of rows <= 61 arcs: 0 = default: lane-streamed
+                               (id rule, unordered compaction: every lane tests its own vertex and takes the
+                               next worklist entry as soon as it is decided; otherwise L lanes per vertex);
+                               -1 = L lanes per vertex; bit b (b < 4): bucket b one lane per vertex, the
+                               wavefront moving on when all 64 are decided (other buckets L lanes) */
     int32_t firstfit;       /* 0: default (push, byte flags); 1: rescan: every FirstFit gathers all neighbour
                                colours (as printed in the paper); 2: push: a vertex that settles marks its
                                colour in per-neighbour flags (bits, set by atomic OR) and FirstFit reads its

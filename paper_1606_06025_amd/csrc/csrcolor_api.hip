@@ -36,6 +36,8 @@ struct Workspace {
     int* wl[2] = {nullptr, nullptr};
     int* hint = nullptr;         // conflict hints: a neighbour that beat the vertex
     int* llen = nullptr;         // live-list lengths (or a split row's chunk-slot base)
+    int* lpos = nullptr;         // live lists: resume positions in the rows
+    unsigned char* Fq = nullptr; // push FirstFit, byte flags: KQ flag bytes per vertex (colours 1..KQ)
     unsigned char* dirty = nullptr;   // push FirstFit: flags changed since the last FirstFit
     unsigned char* rflag = nullptr;   // wake flags: recolour this round (padded to whole scans)
     unsigned char* aflag = nullptr;   // wake flags: test this round (padded likewise)
@@ -218,6 +220,9 @@ void free_vertex_arrays(Workspace* w) {
     if (w->wl[1]) (void)hipFree(w->wl[1]);
     if (w->hint) (void)hipFree(w->hint);
     if (w->llen) (void)hipFree(w->llen);
+    if (w->lpos) (void)hipFree(w->lpos);
+    if (w->Fq) (void)hipFree(w->Fq);
+    w->Fq = nullptr;
     if (w->dirty) (void)hipFree(w->dirty);
     if (w->rflag) (void)hipFree(w->rflag);
     if (w->aflag) (void)hipFree(w->aflag);
@@ -226,7 +231,7 @@ void free_vertex_arrays(Workspace* w) {
     w->rflag = w->aflag = nullptr;
     w->srnd = nullptr;
     w->Fs = nullptr;
-    w->X = w->wl[0] = w->wl[1] = w->hint = w->llen = nullptr;
+    w->X = w->wl[0] = w->wl[1] = w->hint = w->llen = w->lpos = nullptr;
     w->dirty = nullptr;
     w->cap_n = 0;
 }
@@ -268,6 +273,8 @@ int ensure_capacity(Workspace* w, size_t n, int st_cap) {
             hipMalloc(&w->wl[1], want * sizeof(int)) != hipSuccess ||
             hipMalloc(&w->hint, want * sizeof(int)) != hipSuccess ||
             hipMalloc(&w->llen, want * sizeof(int)) != hipSuccess ||
+            hipMalloc(&w->lpos, want * sizeof(int)) != hipSuccess ||
+            hipMalloc(&w->Fq, want * KQ) != hipSuccess ||
             hipMalloc(&w->rflag, flag_bytes(want)) != hipSuccess ||
             hipMalloc(&w->aflag, flag_bytes(want)) != hipSuccess ||
             hipMalloc(&w->srnd, want * sizeof(int)) != hipSuccess ||
@@ -354,7 +361,9 @@ struct Options {
     int sync_every = 8;
     int tsplit = 2048;
     int lane_assign = 0;      // tile buckets run with 2/4/8/16 lanes per vertex
-    int lane_detect = 0;      // tiled conflict test (L lanes per untested vertex) in every tile bucket
+    int lane_detect = 0;      // conflict test of the tile buckets: 0 lane-streamed (id rule); with bit 4
+                              // set, L lanes per untested vertex, or for the buckets of bits 0-3 one
+                              // lane per vertex without refill
     int pushff = 2;           // FirstFit: 0 rescan, 1 push with bit flags, 2 push with byte flags
     int hints = 1;            // conflict hints (id rule)
     int live = 1;             // live lists for degree > 61 (id rule)
@@ -393,7 +402,7 @@ Options parse_opts(const csrcolor_opts* o) {
     if (o->t_split > 0) r.tsplit = std::max(o->t_split, TSPLIT_MIN);
     r.tsplit = std::max(r.tsplit, r.twave);
     if (o->lane_assign) r.lane_assign = o->lane_assign < 0 ? 0 : (o->lane_assign & 0xF);
-    if (o->lane_detect) r.lane_detect = o->lane_detect < 0 ? 0 : (o->lane_detect & 0xF);
+    if (o->lane_detect) r.lane_detect = o->lane_detect < 0 ? 0x10 : (0x10 | (o->lane_detect & 0xF));
     if (o->firstfit) r.pushff = o->firstfit - 1;
     if (o->hints) r.hints = o->hints > 0;
     if (o->live_lists) r.live = o->live_lists > 0;
@@ -683,7 +692,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     const bool use_live = J.opt.live && J.opt.rule == 0 && J.opt.algo == CSRCOLOR_ALGO_SGR &&
                           hist[NTILE] + hist[NTILE + 1] + hist[BSPLIT] > 0;
     const size_t split_ints = 2 * (size_t)nhub + 2 * (size_t)nchunk + (size_t)nhub * (HW + 2) +
-                              (use_live ? (size_t)nchunk : 0) + 2 * (size_t)nchunk;
+                              (use_live ? 2 * (size_t)nchunk : 0) + 2 * (size_t)nchunk;
     if ((rc = ensure_split(w, split_ints))) return rc;
     int* cstart0 = w->split;
     int* cstart1 = cstart0 + nhub;
@@ -695,7 +704,8 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
         k_fill<<<std::min((cnt + WG - 1) / WG, cus * 4), WG, 0, st>>>(hubflags, cnt, 0);
     }
     int* clen = use_live ? hubflags + (size_t)nhub * (HW + 2) : nullptr;   // per-chunk live lengths
-    int* settled = hubflags + (size_t)nhub * (HW + 2) + (use_live ? (size_t)nchunk : 0);
+    int* cpos = use_live ? clen + nchunk : nullptr;                          // and resume positions
+    int* settled = hubflags + (size_t)nhub * (HW + 2) + (use_live ? 2 * (size_t)nchunk : 0);
     if (use_live && (rc = ensure_live(w, std::max<size_t>((size_t)w->ctl_h->nnz, 1)))) return rc;
 
     // conflict hints serve the id rule (the degree rule would need the neighbour's degree too)
@@ -743,6 +753,15 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
             T.run(0, [&] {
                 k_fill<<<std::min((dwords + WG - 1) / WG, cus * 8), WG, 0, st>>>(reinterpret_cast<int*>(w->dirty),
                                                                                     dwords, 0);
+                if (J.opt.pushff == 2) {
+                    // the small-colour flag slots, KQ bytes per vertex
+                    const size_t qw = (size_t)n * (KQ / 4);
+                    for (size_t off = 0; off < qw; off += (size_t)1 << 30) {
+                        const int cnt = (int)std::min<size_t>(qw - off, (size_t)1 << 30);
+                        k_fill<<<std::min((cnt + WG - 1) / WG, cus * 8), WG, 0, st>>>(
+                            reinterpret_cast<int*>(w->Fq) + off, cnt, 0);
+                    }
+                }
             });
         }
     }
@@ -768,7 +787,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
                                           use_live ? w->llen : nullptr, clen, lb, J.opt.pushff == 2,
                                           (F && !use_wake) ? w->dirty : nullptr,
                                           use_wake ? w->rflag : nullptr, w->aflag, use_wake ? w->srnd : nullptr,
-                                          w->Fs);
+                                          w->Fs, (J.opt.pushff == 2 && !use_wake) ? w->Fq : nullptr);
     });
     HIP_TRY(hipGetLastError());
 
@@ -798,6 +817,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     a.pushff = J.opt.pushff;
     a.F = F;
     a.dirty = (F && !use_wake) ? w->dirty : nullptr;
+    a.Fq = (J.opt.pushff == 2 && !use_wake) ? w->Fq : nullptr;
     if (use_wake) {
         a.rflag = w->rflag;
         a.aflag = w->aflag;
@@ -816,6 +836,8 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     a.live = use_live ? w->live : nullptr;
     a.llen = use_live ? w->llen : nullptr;
     a.clen = clen;
+    a.lpos = use_live ? w->lpos : nullptr;
+    a.cpos = cpos;
     a.st_cap = st_cap;
     a.st_wsize = st_cap ? w->st_wsize : nullptr;
     a.st_arcs = st_cap ? w->st_arcs : nullptr;
@@ -1007,6 +1029,8 @@ int enqueue_device(Workspace* w, Job& J, const long long* voff, int G, int* ncol
     t.hint = (o.hints && o.rule == 0) ? w->hint : nullptr;
     t.live = w->live;
     t.llen = w->llen;
+    t.lpos = w->lpos;
+    t.Fq = w->Fq;
     t.lbs = lb;
     t.lbs_n = grid;
     t.st_cap = st_cap;
@@ -1081,7 +1105,7 @@ int run_device(Workspace* w, Job& J, const long long* voff, int G, int* ncolors_
     // the arc-sized buffers must cover every graph of at most cap_n vertices and arc_cap
     // arcs (a host-driven call may have grown the vertex arrays since they were sized)
     const bool covered = w->arc_cap > 0 && w->F_cap >= (w->cap_n + (size_t)w->arc_cap) / 4 + 4 &&
-                         w->split_cap >= (size_t)(w->arc_cap / 23 + 64) && w->live_cap >= (size_t)w->arc_cap;
+                         w->split_cap >= (size_t)(w->arc_cap / 21 + 64) && w->live_cap >= (size_t)w->arc_cap;
     const bool fresh = (size_t)n > w->cap_n || !w->ctl || !w->plan || !covered;
     int rc = ensure_capacity(w, (size_t)n, st_cap);
     if (rc) return rc;
@@ -1093,9 +1117,9 @@ int run_device(Workspace* w, Job& J, const long long* voff, int G, int* ncolors_
         const long long arcs = std::max<long long>(std::max(*w->sz_h, 0), w->arc_cap);
         // byte flags for every vertex and arc the workspace holds (the larger flag
         // variant); split-row scratch for the most hubs and chunks that many arcs allow
-        // (a hub has more than 1024 arcs: 36 ints per hub, 5 per 2048-arc chunk)
+        // (a hub has more than 1024 arcs: 36 ints per hub, 6 per 2048-arc chunk)
         if ((rc = ensure_F(w, (size_t)((w->cap_n + arcs) / 4 + 4)))) return rc;
-        if ((rc = ensure_split(w, (size_t)(arcs / 23 + 64)))) return rc;
+        if ((rc = ensure_split(w, (size_t)(arcs / 21 + 64)))) return rc;
         if ((rc = ensure_live(w, (size_t)std::max<long long>(arcs, 1)))) return rc;
         w->arc_cap = std::max<long long>(arcs, 1);
     }
@@ -1178,14 +1202,15 @@ int run_job(Workspace* w, Job& J, const long long* voff, int G) {
 // fixed scratch array in the library's own device memory, for callers that cannot
 // allocate.  Layout (byte offsets, each part 256-byte aligned): control block, plan
 // block, colour state, two worklists, conflict hints, live-list lengths (split rows'
-// chunk bases), dirty bytes, byte flags of the forbidden colours for every vertex and
-// arc, split-row scratch.  Live lists are off (they would need 4 bytes per arc more).
+// chunk bases), live-list resume positions, dirty bytes, small-colour flag slots, byte
+// flags of the forbidden colours for every vertex and arc, split-row scratch.  Live
+// lists are off (they would need 4 bytes per arc more).
 // ---------------------------------------------------------------------------
 constexpr size_t na_align(size_t x) { return (x + 255) / 256 * 256; }
 constexpr size_t NA_N = CSRCOLOR_NOALLOC_MAX_N;
 constexpr size_t NA_E = CSRCOLOR_NOALLOC_MAX_NNZ;
 constexpr size_t NA_F_WORDS = (NA_N + NA_E) / 4 + 4;
-constexpr size_t NA_SPLIT_INTS = NA_E / 23 + 64;
+constexpr size_t NA_SPLIT_INTS = NA_E / 21 + 64;
 constexpr size_t NA_CTL = 0;
 constexpr size_t NA_PLAN = na_align(sizeof(Ctl));
 constexpr size_t NA_X = NA_PLAN + na_align(sizeof(DevPlan));
@@ -1193,8 +1218,10 @@ constexpr size_t NA_WL0 = NA_X + na_align(4 * NA_N);
 constexpr size_t NA_WL1 = NA_WL0 + na_align(4 * NA_N);
 constexpr size_t NA_HINT = NA_WL1 + na_align(4 * NA_N);
 constexpr size_t NA_LLEN = NA_HINT + na_align(4 * NA_N);
-constexpr size_t NA_DIRTY = NA_LLEN + na_align(4 * NA_N);
-constexpr size_t NA_F = NA_DIRTY + na_align(NA_N + 16);
+constexpr size_t NA_LPOS = NA_LLEN + na_align(4 * NA_N);
+constexpr size_t NA_DIRTY = NA_LPOS + na_align(4 * NA_N);
+constexpr size_t NA_FQ = NA_DIRTY + na_align(NA_N + 16);
+constexpr size_t NA_F = NA_FQ + na_align(KQ * NA_N);
 constexpr size_t NA_SPLIT = NA_F + na_align(4 * NA_F_WORDS);
 constexpr size_t NA_BYTES = NA_SPLIT + na_align(4 * NA_SPLIT_INTS);
 static_assert(NA_BYTES <= ((size_t)CSRCOLOR_NOALLOC_SCRATCH_MIB << 20), "scratch layout exceeds its stated size");
@@ -1234,7 +1261,9 @@ Workspace* noalloc_ws(int dev, int* rc) {
         w.wl[1] = reinterpret_cast<int*>(ptr + NA_WL1);
         w.hint = reinterpret_cast<int*>(ptr + NA_HINT);
         w.llen = reinterpret_cast<int*>(ptr + NA_LLEN);
+        w.lpos = reinterpret_cast<int*>(ptr + NA_LPOS);
         w.dirty = ptr + NA_DIRTY;
+        w.Fq = ptr + NA_FQ;
         w.F = reinterpret_cast<unsigned*>(ptr + NA_F);
         w.F_cap = NA_F_WORDS;
         w.split = reinterpret_cast<int*>(ptr + NA_SPLIT);

@@ -70,9 +70,16 @@ __device__ __forceinline__ bool conflict(int rule, const int* __restrict__ rowpt
 // a short row; every other requeued vertex is awake (tested every round).
 constexpr int WAKE_DEG = 61;
 
+// Push FirstFit with byte flags keeps the forbidden colours 1..KQ of every vertex in a
+// slot of KQ bytes of its own (Fq[v*KQ + c-1]): a push of such a colour is a single
+// store, with no read of the neighbour's row bounds, and FirstFit reads the slot in one
+// 16-byte load.  Higher colours use the flags at rowptr[v]+v+c-1 of F.
+constexpr int KQ = 16;
+
 // Where a settling vertex pushes its colour (push-mode FirstFit).
 struct PushCtx {
     unsigned* F;                  // forbidden-colour flags (bits, or bytes when `bytes`)
+    unsigned char* Fq;            // byte flags: the slots of colours 1..KQ (nullptr: off)
     const int* rowptr;
     const int* colidx;
     int nnz;
@@ -116,7 +123,8 @@ __device__ __forceinline__ void push_flag(const PushCtx& P, int u, int c, int ub
 // else its rowptr pair) and then writes its flags.  The two halves are separate so that
 // a lane pushing to several neighbours issues all the reads before any write: a read
 // that follows a write waits for the write too (the vector memory counter covers both),
-// and the writes are atomics or stores that go to memory.
+// and the writes are atomics or stores that go to memory.  (With small-colour slots
+// push_quad does its own reads.)
 struct PushRead {
     int a;   // wake flags (not round 1): u's colour word; else rowptr[u]
     int b;   // rowptr[u + 1] (not read with wake flags)
@@ -167,9 +175,7 @@ __device__ __forceinline__ void push_write(const PushCtx& P, int u, int c, PushR
     }
     push_flag(P, u, c, ub, ue);
 }
-__device__ __forceinline__ void push_colour(const PushCtx& P, int u, int c) {
-    push_write(P, u, c, push_read(P, u));
-}
+
 // Holds the wavefront here until x is loaded.  Placed after a group of reads and before
 // the writes that use them, it makes the one wait cover every read of the group: the
 // compiler otherwise waits again before each later use inside the writes' branches, and
@@ -177,8 +183,38 @@ __device__ __forceinline__ void push_colour(const PushCtx& P, int u, int c) {
 __device__ __forceinline__ void reads_done(int x) { asm volatile("" ::"v"(x)); }
 
 // Pushes colour c of v to the neighbours w[0..3] (entries -1 and v itself are skipped),
-// all four reads first.
+// all four reads first.  With small-colour slots a colour <= KQ is one store per
+// neighbour; a higher one reads the neighbours' colour words first and only the
+// uncoloured ones' row bounds (a settled neighbour never runs FirstFit again, so its
+// flags are not needed).
 __device__ __forceinline__ void push_quad(const PushCtx& P, const int* w, int v, int c) {
+    if (P.Fq && !P.rflag) {
+        bool go[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) go[k] = w[k] >= 0 && w[k] != v;
+        if (c <= KQ) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (go[k]) P.Fq[(size_t)w[k] * KQ + c - 1] = 1;
+            return;
+        }
+        int x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[k] = go[k] ? P.X[w[k]] : 1;
+        reads_done(x[0] | x[1] | x[2] | x[3]);
+        int ub[4], ue[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            go[k] = go[k] && x[k] <= 0;
+            ub[k] = go[k] ? P.rowptr[w[k]] : 0;
+            ue[k] = go[k] ? P.rowptr[w[k] + 1] : 0;
+        }
+        reads_done(ub[0] | ub[1] | ub[2] | ub[3] | ue[0] | ue[1] | ue[2] | ue[3]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (go[k]) push_flag(P, w[k], c, ub[k], ue[k]);
+        return;
+    }
     PushRead r[4];
     int all = 0;
 #pragma unroll
@@ -292,12 +328,19 @@ struct RoundArgs {
     // longer conflicts
     int* hint;
     // live lists (id rule; nullptr = off): for a vertex of degree > 61 the lower
-    // neighbours still uncoloured when last seen, packed at live[rowptr[v] ...];
-    // llen[v] = their number (-1: not built yet) or, for a split row, the base of its
-    // per-chunk lengths clen[llen[v] + k] (-1: chunk not built yet)
+    // neighbours found still uncoloured when last seen, packed at live[rowptr[v] ...];
+    // llen[v] = their number (-1: nothing examined yet) and lpos[v] = the first row
+    // entry no test has examined; for a split row llen[v] is instead the base of its
+    // per-chunk lengths clen[llen[v] + k] (-1: nothing examined yet) and resume
+    // positions cpos[llen[v] + k]
     int* live;
     int* llen;
     int* clen;
+    int* lpos;
+    int* cpos;
+    // push FirstFit with byte flags (not with wake flags): per vertex KQ bytes for the
+    // forbidden colours 1..KQ (nullptr = off)
+    unsigned char* Fq;
     // ordered compaction (nullptr = off): one look-back status word per block of the
     // grid, cleared by the FirstFit launch of the round
     unsigned long long* lbs;

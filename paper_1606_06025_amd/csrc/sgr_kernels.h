@@ -199,7 +199,7 @@ __device__ __forceinline__ void round1_body(int n, const int* __restrict__ rowpt
                                             int rule, int jp, int* hint, int* llen, int* clen,
                                             unsigned long long* lb1, int fbytes, unsigned char* dirty,
                                             unsigned char* rflag, unsigned char* aflag, int* srnd,
-                                            unsigned long long* Fs) {
+                                            unsigned long long* Fs, unsigned char* Fq) {
     constexpr int ITER = 4;
     __shared__ int buf[WAVES][NB][ITER * 64];
     __shared__ int wcnt[WAVES][NB];
@@ -217,6 +217,7 @@ __device__ __forceinline__ void round1_body(int n, const int* __restrict__ rowpt
     P.nnz = nnz;
     P.bytes = fbytes != 0;
     P.dirty = dirty;
+    P.Fq = rflag ? nullptr : Fq;
     P.X = X;
     P.rflag = rflag;
     P.Fs = Fs;
@@ -365,9 +366,9 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
                                                int rule, int jp, int* hint, int* llen, int* clen,
                                                unsigned long long* lb1, int fbytes, unsigned char* dirty,
                                                unsigned char* rflag, unsigned char* aflag, int* srnd,
-                                               unsigned long long* Fs) {
+                                               unsigned long long* Fs, unsigned char* Fq) {
     round1_body(n, rowptr, colidx, X, out, wl1, ctl, sorted, twave, tsplit, seg.s, cstart1, owner1, F, nnz,
-                rule, jp, hint, llen, clen, lb1, fbytes, dirty, rflag, aflag, srnd, Fs);
+                rule, jp, hint, llen, clen, lb1, fbytes, dirty, rflag, aflag, srnd, Fs, Fq);
 }
 
 // Flag-scanning conflict test of the vertices of at most WAKE_DEG arcs, run by block

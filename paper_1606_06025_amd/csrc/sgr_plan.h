@@ -38,6 +38,7 @@ struct DevPlan {
     int hub_ints;              // split-row merge state to clear (bitmaps, done counters, lost flags)
     int dirty_words;           // dirty bytes to clear, as 4-byte words
     int lb1_ints;
+    long long fq_words;        // small-colour flag slots to clear, as 4-byte words
 };
 
 // `t` holds everything the host knows (arrays, options; wl_in = wl[1], wl_out = wl[0]);
@@ -71,7 +72,7 @@ __global__ void k_dev_plan(RoundArgs t, DevCaps c, DevPlan* p) {
         fw = a.pushff == 2 ? flags / 4 + 4 : flags / 32 + 2;
     }
     const long long split_ints = 2LL * nhub + 2LL * nchunk + (long long)nhub * (HW + 2) +
-                                 (use_live ? (long long)nchunk : 0) + 2LL * nchunk;
+                                 (use_live ? 2LL * nchunk : 0) + 2LL * nchunk;
     if (fw > c.f_words || split_ints > c.split_ints) {
         atomicOr(&ctl->err, ERR_NOMEM);
         return;
@@ -82,7 +83,8 @@ __global__ void k_dev_plan(RoundArgs t, DevCaps c, DevPlan* p) {
     int* owner1 = owner0 + nchunk;
     int* hubflags = owner1 + nchunk;   // HW bitmap words per hub, then done counters, then lost flags
     int* clen = use_live ? hubflags + (size_t)nhub * (HW + 2) : nullptr;
-    int* settled = hubflags + (size_t)nhub * (HW + 2) + (use_live ? nchunk : 0);
+    int* cpos = use_live ? clen + nchunk : nullptr;
+    int* settled = hubflags + (size_t)nhub * (HW + 2) + (use_live ? 2 * nchunk : 0);
     a.cstart[0] = cstart0;
     a.cstart[1] = cstart1;
     a.owner[0] = owner0;
@@ -95,10 +97,13 @@ __global__ void k_dev_plan(RoundArgs t, DevCaps c, DevPlan* p) {
     a.live = use_live ? t.live : nullptr;
     a.llen = use_live ? t.llen : nullptr;
     a.clen = clen;
+    a.lpos = use_live ? t.lpos : nullptr;
+    a.cpos = cpos;
     if (!a.pushff) {
         a.F = nullptr;
         a.dirty = nullptr;
     }
+    if (a.pushff != 2) a.Fq = nullptr;
     RoundArgs e = a;
     a.par_in = 1;
     a.par_out = 0;
@@ -113,10 +118,12 @@ __global__ void k_dev_plan(RoundArgs t, DevCaps c, DevPlan* p) {
     p->f_words = fw;
     p->hub_ints = nhub * (HW + 2);
     p->dirty_words = a.pushff ? n / 4 + 1 : 0;
+    p->fq_words = a.Fq ? (long long)n * (KQ / 4) : 0;
 }
 
 // Zeroes what the plan asks for: the push flags, the split-row merge state, the dirty
-// bytes and the round-1 look-back words (a kernel, not a memset, so it can be captured).
+// bytes, the round-1 look-back words and the small-colour flag slots (a kernel, not a
+// memset, so it can be captured).
 __global__ __launch_bounds__(WG) void k_dev_clear(const DevPlan* __restrict__ p) {
     const RoundArgs& a = p->odd;
     if (a.ctl->err) return;
@@ -124,17 +131,20 @@ __global__ __launch_bounds__(WG) void k_dev_clear(const DevPlan* __restrict__ p)
     const long long hw = p->hub_ints;
     const long long dw = p->dirty_words;
     const long long lw = p->lb1_ints;
-    const long long tot = fw + hw + dw + lw;
+    const long long qw = p->fq_words;
+    const long long tot = fw + hw + dw + lw + qw;
     const long long stride = (long long)gridDim.x * WG;
     int* F = reinterpret_cast<int*>(a.F);
     int* hub = reinterpret_cast<int*>(a.hubbm);
     int* dirty = reinterpret_cast<int*>(a.dirty);
     int* lb = reinterpret_cast<int*>(p->lb1);
+    int* fq = reinterpret_cast<int*>(a.Fq);
     for (long long i = (long long)blockIdx.x * WG + threadIdx.x; i < tot; i += stride) {
         if (i < fw) F[i] = 0;
         else if (i < fw + hw) hub[i - fw] = 0;
         else if (i < fw + hw + dw) dirty[i - fw - hw] = 0;
-        else lb[i - fw - hw - dw] = 0;
+        else if (i < fw + hw + dw + lw) lb[i - fw - hw - dw] = 0;
+        else fq[i - fw - hw - dw - lw] = 0;
     }
 }
 
@@ -145,7 +155,7 @@ __global__ __launch_bounds__(WG) void k_round1_dev(const DevPlan* __restrict__ p
     if (a.ctl->err) return;
     round1_body(a.n, a.rowptr, a.colidx, a.X, a.out, const_cast<int*>(a.wl_in), a.ctl, a.sorted, a.twave,
                 a.tsplit, a.seg, a.cstart[1], a.owner[1], a.F, a.nnz, a.rule, 0, a.hint, a.llen, a.clen, p->lb1,
-                a.pushff == 2, a.dirty, nullptr, nullptr, nullptr, nullptr);
+                a.pushff == 2, a.dirty, nullptr, nullptr, nullptr, nullptr, a.Fq);
 }
 
 // Every round after the first in one launch (persistent_rounds), arguments from the plan.

@@ -31,6 +31,7 @@ struct RoundLds {
     int sh[4];
     int lpre[WAVES];                  // live lists: per-wavefront kept counts of a block scan
     int lsh[4];                       // live lists: block-uniform verdicts of a split chunk
+    int wbuf[WAVES * 4 * 128];        // detect stream: per-wavefront winners staged for their pushes
 };
 
 // Bucket of block `bid` under the partition boff, its index j inside the bucket and
@@ -124,6 +125,18 @@ __device__ __forceinline__ void load_quad(const int* __restrict__ colidx, int nn
         if (qs + k < beg || qs + k >= end) w[k] = -1;
 }
 
+// First position (relative to beg) after the quads 0 .. q-1 of src[beg, ...).
+__device__ __forceinline__ int quad_end(const int* src, int beg, int q) {
+    const int mis = (int)((reinterpret_cast<uintptr_t>(src) >> 2) & 3);
+    return ((beg + mis) & ~3) - mis + 4 * q - beg;
+}
+
+// Quads of src[beg, end) (0 if the range is empty).
+__device__ __forceinline__ int quad_count(const int* src, int beg, int end) {
+    const int mis = (int)((reinterpret_cast<uintptr_t>(src) >> 2) & 3);
+    return end > beg ? (((end - 1 + mis) >> 2) - ((beg + mis) >> 2) + 1) : 0;
+}
+
 // Contiguous slice [wlo, whi) of [lo, hi) for the calling wavefront.
 __device__ __forceinline__ void wave_slice(int lo, int hi, int& wlo, int& whi) {
     const int wv = threadIdx.x >> 6;
@@ -197,6 +210,7 @@ __device__ __forceinline__ PushCtx push_ctx(const RoundArgs& a) {
     P.nnz = a.nnz;
     P.bytes = a.pushff == 2;
     P.dirty = a.dirty;
+    P.Fq = W ? nullptr : a.Fq;
     P.X = a.X;
     P.rflag = W ? a.rflag : nullptr;
     P.Fs = W ? a.Fs : nullptr;
@@ -217,7 +231,9 @@ __device__ __forceinline__ void push_rows_wave(const RoundArgs& a, bool win, int
 
 // Push-mode FirstFit for any bucket: one lane per vertex finds the first clear bit
 // of the vertex's bitmap (bits below its start count as set); the scan stops at the
-// first clear bit, which exists within deg(v)+1 bits.
+// first clear bit, which exists within deg(v)+1 bits.  Flags are only ever set, so
+// the smallest free colour never decreases from one round to the next: the scan
+// starts at the vertex's previous tentative colour (every colour below it is taken).
 __device__ __forceinline__ void assign_push(const RoundArgs& a, const int* list, int lo, int hi, long long& arcs) {
     // four worklist entries per lane at a time, each step's loads issued together so
     // their latencies overlap
@@ -233,25 +249,68 @@ __device__ __forceinline__ void assign_push(const RoundArgs& a, const int* list,
             const int t = t0 + 64 * i + lane;
             v[i] = t < whi ? list[t] : -1;
         }
-        // a vertex none of whose flags changed since its last FirstFit keeps its colour
         bool need[U];
+        int beg[U], c0[U];
+        if (a.Fq) {
+            // small-colour slots: a vertex whose previous colour is at most KQ reads its
+            // slot; one above KQ has every colour <= KQ forbidden already and, when none of
+            // its flags changed since its last FirstFit, keeps its colour
+            int4 sq[U];
+            int dq[U];
 #pragma unroll
-        for (int i = 0; i < U; ++i) need[i] = v[i] >= 0 && (!a.dirty || a.dirty[v[i]] != 0);
-        int beg[U];
+            for (int i = 0; i < U; ++i) {
+                if (v[i] >= 0) {
+                    c0[i] = max(a.X[v[i]] & CMASK, 1);
+                    sq[i] = *reinterpret_cast<const int4*>(a.Fq + (size_t)v[i] * KQ);
+                    beg[i] = a.rowptr[v[i]];
+                    dq[i] = a.dirty ? a.dirty[v[i]] : 1;
+                }
+            }
 #pragma unroll
-        for (int i = 0; i < U; ++i) beg[i] = need[i] ? a.rowptr[v[i]] : 0;
+            for (int i = 0; i < U; ++i) {
+                need[i] = false;
+                if (v[i] < 0) continue;
+                if (c0[i] <= KQ) {
+                    const unsigned q4[4] = {(unsigned)sq[i].x, (unsigned)sq[i].y, (unsigned)sq[i].z, (unsigned)sq[i].w};
+                    int col = 0;
+#pragma unroll
+                    for (int k = 3; k >= 0; --k) {
+                        const unsigned z = (q4[k] - 0x01010101u) & ~q4[k] & 0x80808080u;
+                        if (z) col = 4 * k + (__ffs(z) - 1) / 8 + 1;   // first zero byte of word k
+                    }
+                    if (col > 0) {
+                        a.X[v[i]] = FLAG | col;
+                        continue;
+                    }
+                    c0[i] = KQ + 1;                   // every colour <= KQ is taken
+                } else if (dq[i] == 0) {
+                    continue;
+                }
+                need[i] = true;
+            }
+        } else {
+            // a vertex none of whose flags changed since its last FirstFit keeps its colour
+#pragma unroll
+            for (int i = 0; i < U; ++i) need[i] = v[i] >= 0 && (!a.dirty || a.dirty[v[i]] != 0);
+#pragma unroll
+            for (int i = 0; i < U; ++i) {
+                beg[i] = need[i] ? a.rowptr[v[i]] : 0;
+                c0[i] = need[i] ? max(a.X[v[i]] & CMASK, 1) : 1;
+            }
+        }
         long long wi[U];
         unsigned wd[U];
 #pragma unroll
         for (int i = 0; i < U; ++i) {
-            const long long bit = (long long)beg[i] + v[i];
+            const long long bit = (long long)beg[i] + v[i] + c0[i] - 1;
             wi[i] = bytes ? bit >> 2 : bit >> 5;
             wd[i] = need[i] ? a.F[wi[i]] : 0u;
         }
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             if (!need[i]) continue;
-            const long long bit = (long long)beg[i] + v[i];
+            const long long base = (long long)beg[i] + v[i];   // flag of colour 1
+            const long long bit = base + c0[i] - 1;
             long long pos;
             if (bytes) {
                 // byte flags: the first zero byte at or after `bit` (bytes before it count as set)
@@ -270,7 +329,7 @@ __device__ __forceinline__ void assign_push(const RoundArgs& a, const int* list,
                 pos = k * 32 + __ffs(~w) - 1;
             }
             if (a.dirty) a.dirty[v[i]] = 0;
-            a.X[v[i]] = FLAG | (int)(pos - bit + 1);
+            a.X[v[i]] = FLAG | (int)(pos - base + 1);
         }
         if (a.st_arcs) {
 #pragma unroll
@@ -880,6 +939,170 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
     }
 }
 
+// Lane-streamed conflict test (id rule; rows of at most 61 arcs).  Every lane runs its
+// own vertex through the steps of the test and takes the next worklist entry as soon
+// as that vertex is decided, so the wavefront keeps 64 independent chains of
+// dependent loads in flight instead of waiting for its slowest vertex.  A loop pass
+// waits once for the loads the previous pass issued, advances every lane by one step
+// and issues the loads of its next step:
+//   meta:   the vertex's colour word, hint and row bounds (and the lane's next entry)
+//   hint:   the hint's colour word and the row's first quad
+//   gather: the colour words of the quad's lower entries, and the row's next quad
+// A vertex loses at a hint that still conflicts (see hint_hit) or at the first lower
+// neighbour holding its tentative colour, and wins when its row (for sorted rows, the
+// lower part) is exhausted.  Winners are staged per wavefront and push their rows 64
+// at a time; losers go to the wavefront's buffer (in the order they are decided).
+template <bool W>
+__device__ __forceinline__ void detect_stream(const RoundArgs& a, const int* list, int lo, int hi, RoundLds& s,
+                                              int* outl, int* cnt_out, int& cmax, unsigned long long* ust, int unit) {
+    constexpr int S_IDLE = 0, S_META = 1, S_HINT = 2, S_GATHER = 3;
+    const int lane = __lane_id();
+    const int wv = threadIdx.x >> 6;
+    int* mybuf = s.lbuf + wv * WAVE_CAP;
+    int* wb = s.wbuf + wv * (4 * 128);
+    const int hf = W ? a.hflag : 0;
+    for (int s0 = lo; s0 < hi; s0 += SUB) {
+        const int s1 = min(s0 + SUB, hi);
+        int wlo, whi;
+        wave_slice(s0, s1, wlo, whi);
+        int wc = 0;               // losers in mybuf
+        int nwin = 0;             // winners staged in wb
+        int next = wlo + 64;      // first worklist entry no lane has claimed
+        int vn = wlo + lane < whi ? list[wlo + lane] : -1;   // the lane's next vertex
+        int st = S_IDLE;
+        bool fresh = true;        // first pass: every lane with an entry starts it
+        int v = -1, cv = 0, h = -1, beg = 0, end = 0, nq = 0, qi = 0;
+        int cur[4] = {-1, -1, -1, -1}, nxt[4] = {-1, -1, -1, -1};
+        int rX = 0, rH = -1, rB = 0, rE = 0, rHX = 0;
+        int rG[4] = {0, 0, 0, 0};
+        for (;;) {
+            // consume the loads of the previous pass and take one step
+            bool lose = false, win = false, doHint = false, doQuad = false, doGather = false;
+            int qload = 0;
+            if (st == S_META) {
+                cv = rX & CMASK;
+                beg = rB;
+                end = rE;
+                h = (rH != -1 && (rH & IDMASK) < v) ? (rH & IDMASK) : -1;
+                nq = quad_count(a.colidx, beg, end);
+                qi = 0;
+                if (nq == 0) {
+                    win = true;
+                } else {
+                    doHint = h >= 0;
+                    doQuad = true;
+                    qload = 0;
+                    st = S_HINT;
+                }
+            } else if (st == S_HINT) {
+                if (h >= 0 && (rHX & CMASK) == cv) {
+                    lose = true;
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) cur[k] = nxt[k];
+                    doGather = true;
+                    doQuad = qi + 1 < nq;
+                    qload = qi + 1;
+                    st = S_GATHER;
+                }
+            } else if (st == S_GATHER) {
+                int found = -1;
+                bool stop = false;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (cur[k] >= 0) {
+                        if (cur[k] < v) {
+                            if ((rG[k] & CMASK) == cv) found = cur[k];
+                        } else {
+                            stop |= a.sorted != 0;     // sorted rows: no lower entries further on
+                        }
+                    }
+                }
+                if (found >= 0) {
+                    lose = true;
+                    if (a.hint) a.hint[v] = found | hf;    // any conflicting neighbour will do
+                } else if (stop || qi + 1 >= nq) {
+                    win = true;
+                } else {
+                    ++qi;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) cur[k] = nxt[k];
+                    doGather = true;
+                    doQuad = qi + 1 < nq;
+                    qload = qi + 1;
+                }
+            }
+            if (win) settle<W>(a, v, cv, cmax);
+            const unsigned long long lm = __ballot(lose);
+            if (lose) mybuf[wc + __popcll(lm & lanemask_lt())] = v;
+            wc += __popcll(lm);
+            if (a.pushff) {
+                const unsigned long long wm = __ballot(win);
+                if (win) {
+                    const int p = 4 * (nwin + __popcll(wm & lanemask_lt()));
+                    wb[p] = v;
+                    wb[p + 1] = cv;
+                    wb[p + 2] = beg;
+                    wb[p + 3] = end;
+                }
+                nwin += __popcll(wm);
+                if (nwin >= 64) {
+                    __builtin_amdgcn_wave_barrier();
+                    push_rows_wave<W>(a, true, wb[4 * lane], wb[4 * lane + 1], wb[4 * lane + 2], wb[4 * lane + 3]);
+                    const int rest = nwin - 64;
+                    int t[4] = {0, 0, 0, 0};
+                    if (lane < rest) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) t[k] = wb[4 * (64 + lane) + k];
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    if (lane < rest) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) wb[4 * lane + k] = t[k];
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    nwin = rest;
+                }
+            }
+            // a decided lane (or, in the first pass, every lane) starts its next vertex
+            const bool take = (win || lose || (fresh && st == S_IDLE)) && vn >= 0;
+            if (win || lose) st = S_IDLE;
+            fresh = false;
+            bool doMeta = false;
+            if (take) {
+                v = vn;
+                st = S_META;
+                doMeta = true;
+            }
+            const unsigned long long cm = __ballot(take);
+            const int tn = next + __popcll(cm & lanemask_lt());
+            next += __popcll(cm);
+            if (__ballot(st != S_IDLE) == 0) break;
+            // issue the loads of the next step
+            if (take) vn = tn < whi ? list[tn] : -1;
+            if (doMeta) {
+                rX = a.X[v];
+                rH = a.hint ? a.hint[v] : -1;
+                rB = a.rowptr[v];
+                rE = a.rowptr[v + 1];
+            }
+            if (doHint) rHX = a.X[h];
+            if (doQuad) load_quad(a.colidx, a.nnz, beg, end, qload, nxt);
+            if (doGather) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) rG[k] = (cur[k] >= 0 && cur[k] < v) ? a.X[cur[k]] : 0;
+            }
+        }
+        if (a.pushff && nwin > 0) {
+            __builtin_amdgcn_wave_barrier();
+            const bool on = lane < nwin;
+            push_rows_wave<W>(a, on, on ? wb[4 * lane] : 0, on ? wb[4 * lane + 1] : 0, on ? wb[4 * lane + 2] : 0,
+                              on ? wb[4 * lane + 3] : 0);
+        }
+        flush_losers(s, wc, outl, cnt_out, ust, unit, &a.ctl->err);
+    }
+}
+
 // Lane-per-vertex conflict test for the tile buckets: every lane walks the lower part
 // of its own row quad by quad and stops at its first conflict (or, for sorted rows,
 // at its first w >= v); the wavefront moves on when all its lanes have stopped.
@@ -939,23 +1162,27 @@ __device__ __forceinline__ void detect_lanes(const RoundArgs& a, const int* list
 }
 
 // ---------------------------------------------------------------------------
-// Live lists (id rule).  A vertex of degree > 61 may stay on the worklist for many
-// rounds, and most of its lower neighbours settle early; once settled, a neighbour
-// can never conflict with it again (FirstFit excluded its colour).  So the first
-// conflict test of such a vertex copies its lower, still uncoloured neighbours into
-// its live list (same offsets as its row, in a separate array), and every later test
-// scans that list instead of the row, dropping the entries it finds settled: packed
-// to the front as it goes; when the scan stops early at a conflict, the gap left in
-// the scanned part is filled from the end of the list, so the list stays contiguous
-// and the unscanned entries are kept.  Entries are tested before they are dropped, so
-// a neighbour settling in this very round is still compared.
+// Live lists (id rule), built lazily.  A vertex of degree > 61 may stay on the
+// worklist for many rounds, and most of its lower neighbours settle early; once
+// settled, a neighbour can never conflict with it again (FirstFit excluded its
+// colour).  So each test of such a vertex keeps the lower neighbours it finds still
+// uncoloured in a live list (same offsets as its row, in a separate array): a test
+// scans the list first, dropping the entries it finds settled (packed to the front as
+// it goes), and then the row entries no test has examined yet, from a resume
+// position, appending the lower uncoloured ones.  Every scan stops at the step that
+// finds a conflict: when the list part stops early, the gap left in its scanned part
+// is filled from the end of the list, so the list stays contiguous and its unscanned
+// entries are kept; when the row part stops early, the resume position marks the
+// first entry not examined.  Entries are tested before they are dropped, so a
+// neighbour settling in this very round is still compared.  A split row keeps a
+// list and a resume position per chunk.
 // ---------------------------------------------------------------------------
 
-// Scan step shared by the wavefront and workgroup versions: reads entries of
-// src[beg, end) (quad q of the range), tests them against v and returns the lower
-// neighbours still uncoloured in keep/w.
+// Scan step: reads the entries of src[beg, end) in quad q of the range, tests them
+// against v and returns the lower neighbours still uncoloured in keep/w.  `row`: the
+// entries come from v's row (for sorted rows an entry >= v ends the lower part).
 __device__ __forceinline__ void live_step(const RoundArgs& a, const int* src, int beg, int end, int q, int v,
-                                          int cv, bool build, int w[4], unsigned& keep, bool& hit, bool& stop,
+                                          int cv, bool row, int w[4], unsigned& keep, bool& hit, bool& stop,
                                           int hf) {
     load_quad(src, a.nnz, beg, end, q, w);
     keep = 0;
@@ -968,7 +1195,7 @@ __device__ __forceinline__ void live_step(const RoundArgs& a, const int* src, in
             if ((x & CMASK) == cv) found = w[k];
             if (x <= 0) keep |= 1u << k;
         } else {
-            stop |= build && a.sorted;     // sorted rows: no lower entries further on
+            stop |= row && a.sorted;       // sorted rows: no lower entries further on
         }
     }
     if (found >= 0) {
@@ -977,122 +1204,105 @@ __device__ __forceinline__ void live_step(const RoundArgs& a, const int* src, in
     }
 }
 
-// First position (relative to beg) after the quads 0 .. q-1 of src[beg, ...).
-__device__ __forceinline__ int quad_end(const int* src, int beg, int q) {
-    const int mis = (int)((reinterpret_cast<uintptr_t>(src) >> 2) & 3);
-    return ((beg + mis) & ~3) - mis + 4 * q - beg;
-}
-
-// The whole wavefront runs the conflict test of v (tentative colour cv, row
-// [rb, re)) on its live list of length len (-1: build it from the row).  Updates the
-// list and its length *lenp; returns whether v is requeued.  Every lane must call.
-__device__ __forceinline__ bool live_test_wave(const RoundArgs& a, int v, int cv, int rb, int re, int len,
-                                               int* lenp, int hf) {
+// The whole wavefront runs the conflict test of v (tentative colour cv) over the
+// range [rb, re) of its row (the whole row, or a chunk of a split row): its live list
+// live[rb, rb + len), then the unexamined entries colidx[p, re) (len < 0: nothing
+// examined yet, i.e. len = 0 and p = rb).  Stores the new length and resume position
+// at *lenp and *posp; returns whether a conflict was found.  Every lane must call.
+__device__ __forceinline__ bool live_test_wave(const RoundArgs& a, int v, int cv, int rb, int re, int len, int p,
+                                               int* lenp, int* posp, int hf) {
     const int lane = __lane_id();
-    const bool build = len < 0;
-    const int* src = build ? a.colidx : a.live;
-    const int send = build ? re : rb + len;
-    const int mis = (int)((reinterpret_cast<uintptr_t>(src) >> 2) & 3);
-    const int nq = send > rb ? (((send - 1 + mis) >> 2) - ((rb + mis) >> 2) + 1) : 0;
+    if (len < 0) {
+        len = 0;
+        p = rb;
+    }
     int K = 0;                 // entries kept so far, packed at live[rb ...]
-    int p = send - rb;         // list positions scanned
     bool lost = false;
-    for (int q0 = 0; q0 < nq; q0 += 64) {
-        int w[4];
-        unsigned keep;
-        bool hit = false, stop = false;
-        live_step(a, src, rb, send, q0 + lane, v, cv, build, w, keep, hit, stop, hf);
-        int tot;
-        int pos = rb + K + wave_excl(__popc(keep), tot);
-        const int qs = rb + quad_end(src, rb, q0 + lane);   // position of w[0] in src
+    if (len > 0) {
+        const int send = rb + len;
+        const int nq = quad_count(a.live, rb, send);
+        int scanned = len;     // list positions scanned
+        for (int q0 = 0; q0 < nq; q0 += 64) {
+            int w[4];
+            unsigned keep;
+            bool hit = false, stop = false;
+            live_step(a, a.live, rb, send, q0 + lane, v, cv, false, w, keep, hit, stop, hf);
+            int tot;
+            int pos = rb + K + wave_excl(__popc(keep), tot);
+            const int qs = rb + quad_end(a.live, rb, q0 + lane);   // position of w[0]
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (keep >> k & 1) {
-                if (build || pos != qs + k) a.live[pos] = w[k];   // an entry already in place stays
-                ++pos;
+            for (int k = 0; k < 4; ++k) {
+                if (keep >> k & 1) {
+                    if (pos != qs + k) a.live[pos] = w[k];   // an entry already in place stays
+                    ++pos;
+                }
+            }
+            K += tot;
+            if (__ballot(hit) != 0) {
+                lost = true;
+                scanned = min(len, quad_end(a.live, rb, q0 + 64));
+                break;
             }
         }
-        K += tot;
-        const bool anyhit = __ballot(hit) != 0;
-        lost |= anyhit;
-        if (anyhit && !build) {
-            p = min(send - rb, quad_end(src, rb, q0 + 64));
-            break;
-        }
-        if (__ballot(stop) != 0) break;
-    }
-    int newlen = K;
-    if (!build) {
-        // fill the gap [K, p) from the end of the unscanned part [p, len)
-        const int m = min(p - K, len - p);
+        // fill the gap [K, scanned) from the end of the unscanned part [scanned, len)
+        const int m = min(scanned - K, len - scanned);
         for (int i = lane; i < m; i += 64) a.live[rb + K + i] = a.live[rb + len - m + i];
-        newlen = len - (p - K);
+        K = len - (scanned - K);
     }
-    if (lane == 0) *lenp = newlen;
+    if (!lost && p < re) {
+        const int nq = quad_count(a.colidx, p, re);
+        int np = re;           // resume position after this scan
+        for (int q0 = 0; q0 < nq; q0 += 64) {
+            int w[4];
+            unsigned keep;
+            bool hit = false, stop = false;
+            live_step(a, a.colidx, p, re, q0 + lane, v, cv, true, w, keep, hit, stop, hf);
+            int tot;
+            int pos = rb + K + wave_excl(__popc(keep), tot);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (keep >> k & 1) a.live[pos++] = w[k];
+            }
+            K += tot;
+            const bool anyhit = __ballot(hit) != 0;
+            lost |= anyhit;
+            if (__ballot(stop) != 0) break;       // sorted: the lower part is complete
+            if (anyhit) {
+                np = min(re, p + quad_end(a.colidx, p, q0 + 64));
+                break;
+            }
+        }
+        p = np;
+    }
+    if (lane == 0) {
+        *lenp = K;
+        *posp = p;
+    }
     return lost;
 }
 
-// Workgroup version of live_test_wave (every thread must call with the same
-// arguments): the list of v at live[rb ...] (or, when len < 0, its row part
-// colidx[rb, re)) is scanned, compacted, and its new length stored at *lenp.  With
-// `early` the scan of a built list stops at the first conflict; the returned verdict
-// is the same in every thread.
-__device__ __forceinline__ bool live_test_wg(const RoundArgs& a, int v, int cv, int rb, int re, int len,
-                                             int* lenp, bool early, RoundLds& s, int hf) {
-    const int tid = threadIdx.x;
-    const int lane = __lane_id();
-    const int wv = tid >> 6;
-    const bool build = len < 0;
-    const int* src = build ? a.colidx : a.live;
-    const int send = build ? re : rb + len;
-    const int mis = (int)((reinterpret_cast<uintptr_t>(src) >> 2) & 3);
-    const int nq = send > rb ? (((send - 1 + mis) >> 2) - ((rb + mis) >> 2) + 1) : 0;
-    int K = 0;
-    int p = send - rb;
-    bool lost = false;
-    for (int q0 = 0; q0 < nq; q0 += WG) {
-        int w[4];
-        unsigned keep;
-        bool hit = false, stop = false;
-        live_step(a, src, rb, send, q0 + tid, v, cv, build, w, keep, hit, stop, hf);
-        int wtot;
-        const int wex = wave_excl(__popc(keep), wtot);
-        if (lane == 0) s.lpre[wv] = wtot;
-        __syncthreads();
-        int before = 0, tot = 0;
-#pragma unroll
-        for (int k = 0; k < WAVES; ++k) {
-            before += k < wv ? s.lpre[k] : 0;
-            tot += s.lpre[k];
-        }
-        int pos = rb + K + before + wex;
-        const int qs = rb + quad_end(src, rb, q0 + tid);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (keep >> k & 1) {
-                if (build || pos != qs + k) a.live[pos] = w[k];
-                ++pos;
-            }
-        }
-        K += tot;
-        const int anyhit = __syncthreads_or(hit);
-        const int anystop = __syncthreads_or(stop);
-        lost |= anyhit != 0;
-        if (anyhit && !build && early) {
-            p = min(send - rb, quad_end(src, rb, q0 + WG));
-            break;
-        }
-        if (anystop) break;
+// Lane-parallel first look at a live-list test (every lane its own vertex or chunk):
+// the first quad of the list, or of the unexamined row entries when the list is
+// empty.  Reads only.  Returns 1 if that quad holds a conflicting neighbour, -1 if
+// nothing is left to examine (no lower uncoloured neighbour remains: no conflict), 0
+// otherwise (the full test decides).
+__device__ __forceinline__ int live_probe(const RoundArgs& a, int v, int cv, int rb, int re, int len, int p,
+                                          int hf) {
+    if (len < 0) {
+        len = 0;
+        p = rb;
     }
-    int newlen = K;
-    if (!build) {
-        const int m = min(p - K, len - p);
-        for (int i = tid; i < m; i += WG) a.live[rb + K + i] = a.live[rb + len - m + i];
-        newlen = len - (p - K);
-    }
-    if (tid == 0) *lenp = newlen;
-    __syncthreads();
-    return lost;
+    if (len == 0 && p >= re) return -1;
+    int w[4];
+    if (len > 0) load_quad(a.live, a.nnz, rb, rb + len, 0, w);
+    else load_quad(a.colidx, a.nnz, p, re, 0, w);
+    int found = -1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (w[k] >= 0 && w[k] < v && (a.X[w[k]] & CMASK) == cv) found = w[k];
+    if (found < 0) return 0;
+    if (a.hint) a.hint[v] = found | hf;
+    return 1;
 }
 
 // Wavefront bucket: metadata for 64 vertices at a time, then the wavefront scans the
@@ -1112,16 +1322,27 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
         for (int t0 = wlo; t0 < whi; t0 += 64) {
             const int nv = min(64, whi - t0);
             const int v_l = lane < nv ? list[t0 + lane] : -1;
-            int beg_l = 0, end_l = 0, cv_l = 0, len_l = -1;
-            bool lost_l = false;
+            int beg_l = 0, end_l = 0, cv_l = 0, len_l = -1, pos_l = 0;
+            bool lost_l = false, done_l = v_l < 0;
             if (v_l >= 0) {
                 cv_l = tentative(a, v_l);
                 lost_l = hint_hit(a, v_l, cv_l);
                 beg_l = a.rowptr[v_l];
                 end_l = a.rowptr[v_l + 1];
-                if (a.live && !lost_l) len_l = a.llen[v_l];
+                if (a.live && !lost_l) {
+                    len_l = a.llen[v_l];
+                    pos_l = len_l >= 0 ? a.lpos[v_l] : beg_l;
+                }
             }
-            unsigned long long todo = __ballot(v_l >= 0 && !lost_l);
+            if (a.live && v_l >= 0 && !lost_l) {
+                // every lane looks at the first quad of its own vertex's list (or unexamined
+                // row): most tests end there, the rest get the whole wavefront below
+                const int pr = live_probe(a, v_l, cv_l, beg_l, end_l, len_l, pos_l, W ? a.hflag : 0);
+                lost_l = pr > 0;
+                done_l = pr != 0;
+            }
+            done_l = done_l || lost_l;
+            unsigned long long todo = __ballot(!done_l);
             while (todo) {
                 const int j = __ffsll((long long)todo) - 1;
                 todo &= todo - 1;
@@ -1131,7 +1352,8 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
                 const int cv = __builtin_amdgcn_readlane(cv_l, j);
                 if (a.live) {
                     const bool lost = live_test_wave(a, v, cv, beg, end, __builtin_amdgcn_readlane(len_l, j),
-                                                     &a.llen[v], W ? a.hflag : 0);
+                                                     __builtin_amdgcn_readlane(pos_l, j), &a.llen[v], &a.lpos[v],
+                                                     W ? a.hflag : 0);
                     if (lane == j) lost_l = lost;
                     continue;
                 }
@@ -1174,19 +1396,16 @@ __device__ __forceinline__ void detect_wg(const RoundArgs& a, const int* list, i
             const int i0 = atomicAdd(&a.ctl->dyn[1][5], 1);
             s.sh[0] = i0;
             s.sh[1] = i0 < cnt ? (int)hint_hit(a, list[i0], tentative(a, list[i0])) : 0;
-            s.sh[2] = (i0 < cnt && a.live) ? a.llen[list[i0]] : -1;
         }
         __syncthreads();
         const int i = s.sh[0];
         bool lost = s.sh[1] != 0;
-        const int len = s.sh[2];
         __syncthreads();
         if (i >= cnt) break;
         const int v = list[i];
         const int beg = a.rowptr[v], end = a.rowptr[v + 1];
         const int cv = tentative(a, v);
-        if (a.live && !lost) lost = live_test_wg(a, v, cv, beg, end, len, &a.llen[v], true, s, W ? a.hflag : 0);
-        const int nq = (lost || a.live) ? 0 : ((end - beg) + 3 + 3) / 4 + 1;
+        const int nq = lost ? 0 : ((end - beg) + 3 + 3) / 4 + 1;
         for (int q0 = 0; q0 < nq; q0 += WG) {
             int w[4];
             load_quad(a.colidx, a.nnz, beg, end, q0 + (int)threadIdx.x, w);
@@ -1239,34 +1458,9 @@ __device__ __forceinline__ void detect_split(const RoundArgs& a, const int* list
         const int nch = split_chunks(re - rb);
         const int beg = rb + k * SPLIT_CH, end = min(beg + SPLIT_CH, re);
         const int cv = tentative(a, v);
-        bool hit = false;
-        if (a.live) {
-            // thread 0 decides for the block: hint, a sibling's verdict, the chunk's list
-            if (tid == 0) {
-                const bool h = hint_hit(a, v, cv);
-                const int ci = a.llen[v] + k;
-                int cl = a.clen[ci];
-                const bool sk = h || ld_agent(&a.hublost[p]) != 0;
-                if (!sk && cl < 0 && a.sorted && a.colidx[beg] >= v) {
-                    cl = 0;                    // a sorted chunk above v has no lower entries
-                    a.clen[ci] = 0;
-                }
-                s.lsh[0] = h;
-                s.lsh[1] = sk;
-                s.lsh[2] = cl;
-                s.lsh[3] = ci;
-            }
-            __syncthreads();
-            hit = s.lsh[0] != 0;
-            const bool sk = s.lsh[1] != 0;
-            const int cl = s.lsh[2];
-            const int ci = s.lsh[3];
-            __syncthreads();
-            if (!sk && cl != 0) hit = live_test_wg(a, v, cv, beg, end, cl, &a.clen[ci], false, s, W ? a.hflag : 0);
-        }
         // the remembered neighbour decides for every chunk of the hub at once
-        if (!a.live) hit = hint_hit(a, v, cv);
-        const bool skip = a.live || hit || ld_agent(&a.hublost[p]) != 0 ||
+        bool hit = hint_hit(a, v, cv);
+        const bool skip = hit || ld_agent(&a.hublost[p]) != 0 ||
                           (a.rule == 0 && a.sorted && a.colidx[beg] >= v);
         if (!skip) {
             const int nq = ((end - beg) + 3 + 3) / 4 + 1;
@@ -1323,9 +1517,13 @@ __device__ __forceinline__ void detect_split(const RoundArgs& a, const int* list
     }
 }
 
-// Split bucket with live lists: the lists of a hub's chunks shrink quickly, so one
-// wavefront (not a workgroup) handles a chunk, four chunks per block at a time.  The
-// merge of the verdicts is that of detect_split, done by lane 0.
+// Split bucket with live lists.  Each wavefront takes a batch of up to 64 chunks, one
+// lane per chunk: the lanes load their chunk's hub, row range, tentative colour, hint
+// and list state together, and look at the first quad of their lists (live_probe);
+// only the chunks still undecided then get the whole wavefront, one after another
+// (skipped once a sibling chunk has found a conflict).  Each lane merges its chunk's
+// verdict into the hub's lost flag and counts the chunk done; the chunk that completes
+// the count settles the hub or requeues it with a fresh chunk range.
 template <bool W>
 __device__ __forceinline__ void detect_split_wave(const RoundArgs& a, const int* list, int nchunks, int j,
                                                   int nbk, int* outl, int* cnt_out, int& cmax) {
@@ -1334,65 +1532,86 @@ __device__ __forceinline__ void detect_split_wave(const RoundArgs& a, const int*
     int* cstart_out = a.cstart[a.par_out];
     int* owner_out = a.owner[a.par_out];
     const int lane = __lane_id();
-    const int wv = threadIdx.x >> 6;
-    for (int t = j * WAVES + wv; t < nchunks; t += nbk * WAVES) {
-        const int p = owner[t];
-        const int v = list[p];
-        const int k = t - cstart[p];
-        const int rb = a.rowptr[v], re = a.rowptr[v + 1];
-        const int nch = split_chunks(re - rb);
-        const int beg = rb + k * SPLIT_CH, end = min(beg + SPLIT_CH, re);
-        const int cv = tentative(a, v);
-        const int ci = a.llen[v] + k;
-        int h = 0, sk = 0, cl = 0;
-        if (lane == 0) {
-            h = hint_hit(a, v, cv);
-            cl = a.clen[ci];
-            sk = h || ld_agent(&a.hublost[p]) != 0;
-            if (!sk && cl < 0 && a.sorted && a.colidx[beg] >= v) {
-                cl = 0;                        // a sorted chunk above v has no lower entries
-                a.clen[ci] = 0;
+    const int nw = nbk * WAVES;                      // wavefronts of the bucket
+    const int gw = j * WAVES + (threadIdx.x >> 6);   // this one's index among them
+    // chunks per batch: spread over the wavefronts of the bucket, at least 16 (their
+    // set-up loads overlap, and most chunks need no scan), at most 64
+    const int B = min(64, max(16, (nchunks + nw - 1) / nw));
+    const int hf = W ? a.hflag : 0;
+    for (int t0 = gw * B; t0 < nchunks; t0 += nw * B) {
+        const int t = t0 + lane;
+        const bool on = lane < B && t < nchunks;
+        int p = 0, v = 0, rb = 0, re = 0, cv = 0, ci = 0, cl = -1, cp = 0, beg = 0, end = 0, nch = 0;
+        bool hit = false, done = !on;
+        if (on) {
+            p = owner[t];
+            v = list[p];
+            const int k = t - cstart[p];
+            rb = a.rowptr[v];
+            re = a.rowptr[v + 1];
+            cv = tentative(a, v);
+            ci = a.llen[v] + k;
+            nch = split_chunks(re - rb);
+            beg = rb + k * SPLIT_CH;
+            end = min(beg + SPLIT_CH, re);
+            hit = hint_hit(a, v, cv);
+            if (!hit) {
+                cl = a.clen[ci];
+                cp = cl >= 0 ? a.cpos[ci] : beg;
+                done = ld_agent(&a.hublost[p]) != 0;     // a sibling chunk already decided
             }
+            if (!hit && !done) {
+                const int pr = live_probe(a, v, cv, beg, end, cl, cp, hf);
+                hit = pr > 0;
+                done = pr != 0;
+            }
+            done = done || hit;
         }
-        h = __builtin_amdgcn_readfirstlane(h);
-        sk = __builtin_amdgcn_readfirstlane(sk);
-        cl = __builtin_amdgcn_readfirstlane(cl);
-        bool hit = h != 0;
-        if (!sk && cl != 0) hit = live_test_wave(a, v, cv, beg, end, cl, &a.clen[ci], W ? a.hflag : 0);
+        unsigned long long todo = __ballot(!done);
+        while (todo) {
+            const int jj = __ffsll((long long)todo) - 1;
+            todo &= todo - 1;
+            const int pj = __builtin_amdgcn_readlane(p, jj);
+            // a chunk that another wavefront has already decided for the hub is skipped
+            int sk = 0;
+            if (lane == 0) sk = ld_agent(&a.hublost[pj]) != 0;
+            if (__builtin_amdgcn_readfirstlane(sk)) continue;
+            const int vj = __builtin_amdgcn_readlane(v, jj);
+            const int cij = __builtin_amdgcn_readlane(ci, jj);
+            const bool h = live_test_wave(a, vj, __builtin_amdgcn_readlane(cv, jj), __builtin_amdgcn_readlane(beg, jj),
+                                          __builtin_amdgcn_readlane(end, jj), __builtin_amdgcn_readlane(cl, jj),
+                                          __builtin_amdgcn_readlane(cp, jj), &a.clen[cij], &a.cpos[cij], hf);
+            if (lane == jj) hit = h;
+        }
+        // merge: the verdict first, then the done count (ordered by waiting for the
+        // returned value of the verdict's atomic)
         int decide = 0;
-        if (lane == 0) {
+        if (on) {
             unsigned old = 0;
             if (hit) old = or_agent(reinterpret_cast<unsigned*>(&a.hublost[p]), 1u);
             wait_on(old);
             decide = add_agent(&a.hubdone[p], 1) == nch - 1;
         }
-        decide = __builtin_amdgcn_readfirstlane(decide);
         if (decide) {
             // the last chunk to finish settles the hub or requeues it with fresh chunks
-            int qn = -1, cs = 0;
-            if (lane == 0) {
-                const bool lost = ld_agent(&a.hublost[p]) != 0;
-                st_agent(&a.hublost[p], 0);
-                st_agent(&a.hubdone[p], 0);
-                if (lost) {
-                    qn = atomicAdd(cnt_out, 1);
-                    cs = atomicAdd(&a.ctl->ccnt[a.par_out], nch);
-                    outl[qn] = v;
-                    cstart_out[qn] = cs;
-                } else {
-                    settle<W>(a, v, cv, cmax);
-                    cs = a.settled ? atomicAdd(&a.ctl->nsettled, nch) : 0;
-                }
-            }
-            qn = __builtin_amdgcn_readfirstlane(qn);
-            cs = __builtin_amdgcn_readfirstlane(cs);
-            if (qn >= 0) {
-                for (int i = lane; i < nch; i += 64) owner_out[cs + i] = qn;
-            } else if (a.settled) {
-                // one push task per chunk of the settled row
-                for (int i = lane; i < nch; i += 64) {
-                    a.settled[cs + i] = p;
-                    a.settled_k[cs + i] = i;
+            const bool lost = ld_agent(&a.hublost[p]) != 0;
+            st_agent(&a.hublost[p], 0);
+            st_agent(&a.hubdone[p], 0);
+            if (lost) {
+                const int qn = atomicAdd(cnt_out, 1);
+                const int cs = atomicAdd(&a.ctl->ccnt[a.par_out], nch);
+                outl[qn] = v;
+                cstart_out[qn] = cs;
+                for (int i = 0; i < nch; ++i) owner_out[cs + i] = qn;
+            } else {
+                settle<W>(a, v, cv, cmax);
+                if (a.settled) {
+                    // one push task per chunk of the settled row
+                    const int cs = atomicAdd(&a.ctl->nsettled, nch);
+                    for (int i = 0; i < nch; ++i) {
+                        a.settled[cs + i] = p;
+                        a.settled_k[cs + i] = i;
+                    }
                 }
             }
         }
@@ -1441,7 +1660,9 @@ __device__ __forceinline__ void detect_phase(const RoundArgs& a, RoundLds& s, in
         if (threadIdx.x < 64) lookback(ust, j, 0, &a.ctl->err);
         return;
     }
-    if (b < NTILE && (a.lane_mode_detect >> b & 1)) {
+    if (b < NTILE && a.rule == 0 && !ust && !(a.lane_mode_detect >> 4 & 1)) {
+        detect_stream<W>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j);
+    } else if (b < NTILE && (a.lane_mode_detect >> b & 1)) {
         detect_lanes<W>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j);
     } else {
         switch (b) {
