@@ -939,170 +939,6 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
     }
 }
 
-// Lane-streamed conflict test (id rule; rows of at most 61 arcs).  Every lane runs its
-// own vertex through the steps of the test and takes the next worklist entry as soon
-// as that vertex is decided, so the wavefront keeps 64 independent chains of
-// dependent loads in flight instead of waiting for its slowest vertex.  A loop pass
-// waits once for the loads the previous pass issued, advances every lane by one step
-// and issues the loads of its next step:
-//   meta:   the vertex's colour word, hint and row bounds (and the lane's next entry)
-//   hint:   the hint's colour word and the row's first quad
-//   gather: the colour words of the quad's lower entries, and the row's next quad
-// A vertex loses at a hint that still conflicts (see hint_hit) or at the first lower
-// neighbour holding its tentative colour, and wins when its row (for sorted rows, the
-// lower part) is exhausted.  Winners are staged per wavefront and push their rows 64
-// at a time; losers go to the wavefront's buffer (in the order they are decided).
-template <bool W>
-__device__ __forceinline__ void detect_stream(const RoundArgs& a, const int* list, int lo, int hi, RoundLds& s,
-                                              int* outl, int* cnt_out, int& cmax, unsigned long long* ust, int unit) {
-    constexpr int S_IDLE = 0, S_META = 1, S_HINT = 2, S_GATHER = 3;
-    const int lane = __lane_id();
-    const int wv = threadIdx.x >> 6;
-    int* mybuf = s.lbuf + wv * WAVE_CAP;
-    int* wb = s.wbuf + wv * (4 * 128);
-    const int hf = W ? a.hflag : 0;
-    for (int s0 = lo; s0 < hi; s0 += SUB) {
-        const int s1 = min(s0 + SUB, hi);
-        int wlo, whi;
-        wave_slice(s0, s1, wlo, whi);
-        int wc = 0;               // losers in mybuf
-        int nwin = 0;             // winners staged in wb
-        int next = wlo + 64;      // first worklist entry no lane has claimed
-        int vn = wlo + lane < whi ? list[wlo + lane] : -1;   // the lane's next vertex
-        int st = S_IDLE;
-        bool fresh = true;        // first pass: every lane with an entry starts it
-        int v = -1, cv = 0, h = -1, beg = 0, end = 0, nq = 0, qi = 0;
-        int cur[4] = {-1, -1, -1, -1}, nxt[4] = {-1, -1, -1, -1};
-        int rX = 0, rH = -1, rB = 0, rE = 0, rHX = 0;
-        int rG[4] = {0, 0, 0, 0};
-        for (;;) {
-            // consume the loads of the previous pass and take one step
-            bool lose = false, win = false, doHint = false, doQuad = false, doGather = false;
-            int qload = 0;
-            if (st == S_META) {
-                cv = rX & CMASK;
-                beg = rB;
-                end = rE;
-                h = (rH != -1 && (rH & IDMASK) < v) ? (rH & IDMASK) : -1;
-                nq = quad_count(a.colidx, beg, end);
-                qi = 0;
-                if (nq == 0) {
-                    win = true;
-                } else {
-                    doHint = h >= 0;
-                    doQuad = true;
-                    qload = 0;
-                    st = S_HINT;
-                }
-            } else if (st == S_HINT) {
-                if (h >= 0 && (rHX & CMASK) == cv) {
-                    lose = true;
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) cur[k] = nxt[k];
-                    doGather = true;
-                    doQuad = qi + 1 < nq;
-                    qload = qi + 1;
-                    st = S_GATHER;
-                }
-            } else if (st == S_GATHER) {
-                int found = -1;
-                bool stop = false;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if (cur[k] >= 0) {
-                        if (cur[k] < v) {
-                            if ((rG[k] & CMASK) == cv) found = cur[k];
-                        } else {
-                            stop |= a.sorted != 0;     // sorted rows: no lower entries further on
-                        }
-                    }
-                }
-                if (found >= 0) {
-                    lose = true;
-                    if (a.hint) a.hint[v] = found | hf;    // any conflicting neighbour will do
-                } else if (stop || qi + 1 >= nq) {
-                    win = true;
-                } else {
-                    ++qi;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) cur[k] = nxt[k];
-                    doGather = true;
-                    doQuad = qi + 1 < nq;
-                    qload = qi + 1;
-                }
-            }
-            if (win) settle<W>(a, v, cv, cmax);
-            const unsigned long long lm = __ballot(lose);
-            if (lose) mybuf[wc + __popcll(lm & lanemask_lt())] = v;
-            wc += __popcll(lm);
-            if (a.pushff) {
-                const unsigned long long wm = __ballot(win);
-                if (win) {
-                    const int p = 4 * (nwin + __popcll(wm & lanemask_lt()));
-                    wb[p] = v;
-                    wb[p + 1] = cv;
-                    wb[p + 2] = beg;
-                    wb[p + 3] = end;
-                }
-                nwin += __popcll(wm);
-                if (nwin >= 64) {
-                    __builtin_amdgcn_wave_barrier();
-                    push_rows_wave<W>(a, true, wb[4 * lane], wb[4 * lane + 1], wb[4 * lane + 2], wb[4 * lane + 3]);
-                    const int rest = nwin - 64;
-                    int t[4] = {0, 0, 0, 0};
-                    if (lane < rest) {
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) t[k] = wb[4 * (64 + lane) + k];
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                    if (lane < rest) {
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) wb[4 * lane + k] = t[k];
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                    nwin = rest;
-                }
-            }
-            // a decided lane (or, in the first pass, every lane) starts its next vertex
-            const bool take = (win || lose || (fresh && st == S_IDLE)) && vn >= 0;
-            if (win || lose) st = S_IDLE;
-            fresh = false;
-            bool doMeta = false;
-            if (take) {
-                v = vn;
-                st = S_META;
-                doMeta = true;
-            }
-            const unsigned long long cm = __ballot(take);
-            const int tn = next + __popcll(cm & lanemask_lt());
-            next += __popcll(cm);
-            if (__ballot(st != S_IDLE) == 0) break;
-            // issue the loads of the next step
-            if (take) vn = tn < whi ? list[tn] : -1;
-            if (doMeta) {
-                rX = a.X[v];
-                rH = a.hint ? a.hint[v] : -1;
-                rB = a.rowptr[v];
-                rE = a.rowptr[v + 1];
-            }
-            if (doHint) rHX = a.X[h];
-            if (doQuad) load_quad(a.colidx, a.nnz, beg, end, qload, nxt);
-            if (doGather) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) rG[k] = (cur[k] >= 0 && cur[k] < v) ? a.X[cur[k]] : 0;
-            }
-        }
-        if (a.pushff && nwin > 0) {
-            __builtin_amdgcn_wave_barrier();
-            const bool on = lane < nwin;
-            push_rows_wave<W>(a, on, on ? wb[4 * lane] : 0, on ? wb[4 * lane + 1] : 0, on ? wb[4 * lane + 2] : 0,
-                              on ? wb[4 * lane + 3] : 0);
-        }
-        flush_losers(s, wc, outl, cnt_out, ust, unit, &a.ctl->err);
-    }
-}
-
 // Lane-per-vertex conflict test for the tile buckets: every lane walks the lower part
 // of its own row quad by quad and stops at its first conflict (or, for sorted rows,
 // at its first w >= v); the wavefront moves on when all its lanes have stopped.
@@ -1303,6 +1139,265 @@ __device__ __forceinline__ int live_probe(const RoundArgs& a, int v, int cv, int
     if (found < 0) return 0;
     if (a.hint) a.hint[v] = found | hf;
     return 1;
+}
+
+// Lane-streamed conflict test (id rule, unordered compaction).  Every lane runs its
+// own vertex through the steps of the test and takes the next worklist entry as soon
+// as that vertex is decided, so the wavefront keeps 64 independent chains of
+// dependent loads in flight instead of waiting for its slowest vertex.  A loop pass
+// waits once for the loads the previous pass issued, advances every lane by one step
+// and issues the loads of its next step:
+//   meta:   the vertex's colour word, hint and row bounds (LONG: and its live-list
+//           length and resume position), and the lane's next worklist entry
+//   hint:   the hint's colour word and the first quad to examine
+//   gather: the colour words of the quad's lower entries, and the next quad
+// The quads examined are the row's (rows of at most 61 arcs) or, with LONG (rows with
+// live lists), the live list's and then the unexamined row entries' (see the live
+// lists below); this walk only reads.  A vertex loses at a hint that still conflicts
+// (see hint_hit) or at the first lower neighbour holding its tentative colour, and
+// wins when nothing is left to examine (sorted rows: no lower entry).  A LONG vertex
+// still undecided after DEFER_QUADS quads is deferred: after the stream the wavefront
+// tests the deferred ones together (live_test_wave, which also updates their lists).
+// Winners are staged per wavefront and push their rows 64 at a time; losers go to the
+// wavefront's buffer in the order they are decided, deferred vertices to its other end.
+constexpr int DEFER_QUADS = 16;
+
+template <bool W, bool LONG>
+__device__ __forceinline__ void detect_stream(const RoundArgs& a, const int* list, int lo, int hi, RoundLds& s,
+                                              int* outl, int* cnt_out, int& cmax, unsigned long long* ust, int unit) {
+    constexpr int S_IDLE = 0, S_META = 1, S_HINT = 2, S_GATHER = 3;
+    const int lane = __lane_id();
+    const int wv = threadIdx.x >> 6;
+    int* mybuf = s.lbuf + wv * WAVE_CAP;
+    int* wb = s.wbuf + wv * (4 * 128);
+    const int hf = W ? a.hflag : 0;
+    for (int s0 = lo; s0 < hi; s0 += SUB) {
+        const int s1 = min(s0 + SUB, hi);
+        int wlo, whi;
+        wave_slice(s0, s1, wlo, whi);
+        int wc = 0;               // losers at mybuf[0 .. wc)
+        int nd = 0;               // deferred vertices at mybuf[WAVE_CAP - nd .. WAVE_CAP)
+        int nwin = 0;             // winners staged in wb
+        int next = wlo + 64;      // first worklist entry no lane has claimed
+        int vn = wlo + lane < whi ? list[wlo + lane] : -1;   // the lane's next vertex
+        int st = S_IDLE;
+        bool fresh = true;        // first pass: every lane with an entry starts it
+        int v = -1, cv = 0, h = -1, beg = 0, end = 0;
+        int len = 0, p = 0;       // LONG: list length and resume position
+        int seg = 1, qi = 0, nqL = 0, nqR = 0, walked = 0;
+        int cur[4] = {-1, -1, -1, -1}, nxt[4] = {-1, -1, -1, -1};
+        int rX = 0, rH = -1, rB = 0, rE = 0, rL = -1, rP = 0, rHX = 0;
+        int rG[4] = {0, 0, 0, 0};
+        for (;;) {
+            // consume the loads of the previous pass and take one step
+            bool lose = false, win = false, defer = false, doHint = false, doQuad = false, doGather = false;
+            int qseg = 1, qload = 0;  // the quad to load: segment (0 list, 1 row) and index
+            if (st == S_META) {
+                cv = rX & CMASK;
+                beg = rB;
+                end = rE;
+                h = (rH != -1 && (rH & IDMASK) < v) ? (rH & IDMASK) : -1;
+                len = 0;
+                p = beg;
+                if (LONG && rL >= 0) {
+                    len = rL;
+                    p = rP;
+                }
+                nqL = LONG ? quad_count(a.live, beg, beg + len) : 0;
+                nqR = quad_count(a.colidx, p, end);
+                walked = 0;
+                if (nqL + nqR == 0) {
+                    win = true;
+                } else {
+                    seg = nqL > 0 ? 0 : 1;
+                    qi = 0;
+                    doHint = h >= 0;
+                    doQuad = true;
+                    qseg = seg;
+                    qload = 0;
+                    st = S_HINT;
+                }
+            } else if (st == S_HINT || st == S_GATHER) {
+                bool stop = false;
+                if (st == S_HINT) {
+                    lose = h >= 0 && (rHX & CMASK) == cv;
+                } else {
+                    int found = -1;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        if (cur[k] >= 0) {
+                            if (cur[k] < v) {
+                                if ((rG[k] & CMASK) == cv) found = cur[k];
+                            } else {
+                                stop |= seg == 1 && a.sorted != 0;   // sorted rows: no lower entries further on
+                            }
+                        }
+                    }
+                    if (found >= 0) {
+                        lose = true;
+                        if (a.hint) a.hint[v] = found | hf;     // any conflicting neighbour will do
+                    }
+                    ++walked;
+                }
+                if (!lose) {
+                    // the quad to examine next: the one loaded last pass (at S_HINT: the first)
+                    int ns = seg, nqi = qi;
+                    bool have = true;
+                    if (st == S_GATHER) {
+                        if (stop) {
+                            have = false;
+                        } else if (seg == 0 && qi + 1 < nqL) {
+                            nqi = qi + 1;
+                        } else if (seg == 0 && nqR > 0) {
+                            ns = 1;
+                            nqi = 0;
+                        } else if (seg == 1 && qi + 1 < nqR) {
+                            nqi = qi + 1;
+                        } else {
+                            have = false;
+                        }
+                    }
+                    if (!have) {
+                        win = true;
+                    } else if (LONG && walked >= DEFER_QUADS) {
+                        defer = true;
+                    } else {
+                        seg = ns;
+                        qi = nqi;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) cur[k] = nxt[k];
+                        doGather = true;
+                        // and the quad after it
+                        if (seg == 0 && qi + 1 < nqL) {
+                            doQuad = true;
+                            qseg = 0;
+                            qload = qi + 1;
+                        } else if (seg == 0 && nqR > 0) {
+                            doQuad = true;
+                            qseg = 1;
+                            qload = 0;
+                        } else if (seg == 1 && qi + 1 < nqR) {
+                            doQuad = true;
+                            qseg = 1;
+                            qload = qi + 1;
+                        }
+                        st = S_GATHER;
+                    }
+                }
+            }
+            if (win) settle<W>(a, v, cv, cmax);
+            const unsigned long long lm = __ballot(lose);
+            if (lose) mybuf[wc + __popcll(lm & lanemask_lt())] = v;
+            wc += __popcll(lm);
+            if (LONG) {
+                const unsigned long long dm = __ballot(defer);
+                if (defer) mybuf[WAVE_CAP - 1 - nd - __popcll(dm & lanemask_lt())] = v;
+                nd += __popcll(dm);
+            }
+            if (a.pushff) {
+                const unsigned long long wm = __ballot(win);
+                if (win) {
+                    const int q = 4 * (nwin + __popcll(wm & lanemask_lt()));
+                    wb[q] = v;
+                    wb[q + 1] = cv;
+                    wb[q + 2] = beg;
+                    wb[q + 3] = end;
+                }
+                nwin += __popcll(wm);
+                if (nwin >= 64) {
+                    __builtin_amdgcn_wave_barrier();
+                    push_rows_wave<W>(a, true, wb[4 * lane], wb[4 * lane + 1], wb[4 * lane + 2], wb[4 * lane + 3]);
+                    const int rest = nwin - 64;
+                    int t[4] = {0, 0, 0, 0};
+                    if (lane < rest) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) t[k] = wb[4 * (64 + lane) + k];
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    if (lane < rest) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) wb[4 * lane + k] = t[k];
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    nwin = rest;
+                }
+            }
+            // a decided lane (or, in the first pass, every lane) starts its next vertex
+            const bool take = (win || lose || defer || (fresh && st == S_IDLE)) && vn >= 0;
+            if (win || lose || defer) st = S_IDLE;
+            fresh = false;
+            bool doMeta = false;
+            if (take) {
+                v = vn;
+                st = S_META;
+                doMeta = true;
+            }
+            const unsigned long long cm = __ballot(take);
+            const int tn = next + __popcll(cm & lanemask_lt());
+            next += __popcll(cm);
+            if (__ballot(st != S_IDLE) == 0) break;
+            // issue the loads of the next step
+            if (take) vn = tn < whi ? list[tn] : -1;
+            if (doMeta) {
+                rX = a.X[v];
+                rH = a.hint ? a.hint[v] : -1;
+                rB = a.rowptr[v];
+                rE = a.rowptr[v + 1];
+                if (LONG) {
+                    rL = a.llen[v];
+                    rP = a.lpos[v];
+                }
+            }
+            if (doHint) rHX = a.X[h];
+            if (doQuad) {
+                if (LONG && qseg == 0) load_quad(a.live, a.nnz, beg, beg + len, qload, nxt);
+                else load_quad(a.colidx, a.nnz, p, end, qload, nxt);
+            }
+            if (doGather) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) rG[k] = (cur[k] >= 0 && cur[k] < v) ? a.X[cur[k]] : 0;
+            }
+        }
+        if (a.pushff && nwin > 0) {
+            __builtin_amdgcn_wave_barrier();
+            const bool on = lane < nwin;
+            push_rows_wave<W>(a, on, on ? wb[4 * lane] : 0, on ? wb[4 * lane + 1] : 0, on ? wb[4 * lane + 2] : 0,
+                              on ? wb[4 * lane + 3] : 0);
+        }
+        if (LONG) {
+            // the deferred vertices, 64 at a time: the whole wavefront tests one after
+            // another (updating their lists), then winners push and losers are listed
+            for (int d0 = 0; d0 < nd; d0 += 64) {
+                const bool on = d0 + lane < nd;
+                __builtin_amdgcn_wave_barrier();
+                const int vd = on ? mybuf[WAVE_CAP - 1 - d0 - lane] : -1;
+                __builtin_amdgcn_wave_barrier();
+                int bd = 0, ed = 0, cd = 0, ld = -1, pd = 0;
+                if (on) {
+                    cd = a.X[vd] & CMASK;
+                    bd = a.rowptr[vd];
+                    ed = a.rowptr[vd + 1];
+                    ld = a.llen[vd];
+                    pd = a.lpos[vd];
+                }
+                bool lost_l = false;
+                unsigned long long todo = __ballot(on);
+                while (todo) {
+                    const int j = __ffsll((long long)todo) - 1;
+                    todo &= todo - 1;
+                    const int vj = __builtin_amdgcn_readlane(vd, j);
+                    const bool l = live_test_wave(a, vj, __builtin_amdgcn_readlane(cd, j), __builtin_amdgcn_readlane(bd, j),
+                                                  __builtin_amdgcn_readlane(ed, j), __builtin_amdgcn_readlane(ld, j),
+                                                  __builtin_amdgcn_readlane(pd, j), &a.llen[vj], &a.lpos[vj], hf);
+                    if (lane == j) lost_l = l;
+                }
+                if (on && !lost_l) settle<W>(a, vd, cd, cmax);
+                if (a.pushff) push_rows_wave<W>(a, on && !lost_l, vd, cd, bd, ed);
+                push_losers(vd, on && lost_l, mybuf, wc);
+            }
+        }
+        flush_losers(s, wc, outl, cnt_out, ust, unit, &a.ctl->err);
+    }
 }
 
 // Wavefront bucket: metadata for 64 vertices at a time, then the wavefront scans the
@@ -1534,9 +1629,9 @@ __device__ __forceinline__ void detect_split_wave(const RoundArgs& a, const int*
     const int lane = __lane_id();
     const int nw = nbk * WAVES;                      // wavefronts of the bucket
     const int gw = j * WAVES + (threadIdx.x >> 6);   // this one's index among them
-    // chunks per batch: spread over the wavefronts of the bucket, at least 16 (their
-    // set-up loads overlap, and most chunks need no scan), at most 64
-    const int B = min(64, max(16, (nchunks + nw - 1) / nw));
+    // chunks per batch: spread over every wavefront of the bucket, at most 64 (most
+    // chunks need no scan, but the ones that do are scanned one after another)
+    const int B = min(64, max(1, (nchunks + nw - 1) / nw));
     const int hf = W ? a.hflag : 0;
     for (int t0 = gw * B; t0 < nchunks; t0 += nw * B) {
         const int t = t0 + lane;
@@ -1661,7 +1756,13 @@ __device__ __forceinline__ void detect_phase(const RoundArgs& a, RoundLds& s, in
         return;
     }
     if (b < NTILE && a.rule == 0 && !ust && !(a.lane_mode_detect >> 4 & 1)) {
-        detect_stream<W>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j);
+        detect_stream<W, false>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j);
+    } else if ((b == NTILE || b == NTILE + 1) && a.live && !ust && !(a.lane_mode_detect >> 5 & 1) &&
+               hi - lo >= 64 * WAVES) {
+        // long rows, at least 64 per wavefront (the early rounds, whose lists are new and
+        // whose conflicts come early): lane-streamed; fewer, with longer lists that the
+        // cooperative test keeps compact: detect_wave
+        detect_stream<W, true>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j);
     } else if (b < NTILE && (a.lane_mode_detect >> b & 1)) {
         detect_lanes<W>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j);
     } else {
