@@ -474,7 +474,7 @@ int drive_loop(Workspace* w, Job& J, RoundArgs& a, int ub[NB], int budget, KTime
         if (tot == 0) break;
         make_plan(ub, budget, a.boff);
         const int grid = a.boff[NB];
-        a.lbs_n = grid;
+        a.lbs_n = budget;      // the conflict test runs on the whole budget (device partition)
         // push-mode FirstFit does little per entry (mostly a dirty-byte check), so it runs
         // on a smaller grid: fewer blocks to dispatch, more entries in flight per wavefront
         int aboff[NB + 1];
@@ -494,7 +494,14 @@ int drive_loop(Workspace* w, Job& J, RoundArgs& a, int ub[NB], int budget, KTime
                 for (int b = 0; b <= NB; ++b) aa.boff[b] = aboff[b];
                 T.kern(1, k_assign, agrid, WG, aa);
             }
-            T.kern(2, k_detect<false>, grid, WG, a);
+            {
+                // the conflict test partitions its grid by the exact queue sizes on the
+                // device (the host only has upper bounds from earlier read-backs)
+                RoundArgs ad = a;
+                ad.dev_plan = 1;
+                ad.lbs_n = budget;
+                T.kern(2, k_detect<false>, budget, WG, ad);
+            }
             if (a.pushff && ub[BSPLIT] > 0) {
                 const int pg = std::min(ub[BSPLIT], budget);
                 T.kern(2, k_push<false>, pg, WG, a);

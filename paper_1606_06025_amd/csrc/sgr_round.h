@@ -60,10 +60,15 @@ __device__ __forceinline__ void block_bucket(const int* boff, int bid, int& b, i
     }
 }
 
-// Per-bucket cost weights (arc work per queued unit) and the most blocks a bucket can
-// use per unit, shared by the host plan and the device plan.
+// Per-bucket cost weights (time per queued unit: a worklist vertex, or a chunk of a
+// split row) and the most blocks a bucket can use per unit, shared by the host plan
+// and the device plan.  The weights follow the block time per unit measured on MI355X
+// for the default tests (R-MAT scale 23, rounds 2 to 300: about 0.25 block-us per
+// vertex of at most 61 arcs, 0.5-1 per vertex of 62-1024 arcs, 2-3 per vertex of
+// 1025-2048 arcs, 1.6-4 per 2048-arc chunk): live lists and hints make the tests cost
+// per vertex rather than per arc.
 __host__ __device__ inline int plan_cost(int b) {
-    constexpr int c[NB] = {4, 10, 22, 45, 200, 1500, 2048};
+    constexpr int c[NB] = {50, 60, 60, 60, 200, 600, 450};
     return c[b];
 }
 __host__ __device__ inline int plan_units_per_block(int b) {
