@@ -698,21 +698,25 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     // neighbours (id rule, worklist SGR only)
     const bool use_live = J.opt.live && J.opt.rule == 0 && J.opt.algo == CSRCOLOR_ALGO_SGR &&
                           hist[NTILE] + hist[NTILE + 1] + hist[BSPLIT] > 0;
-    const size_t split_ints = 2 * (size_t)nhub + 2 * (size_t)nchunk + (size_t)nhub * (HW + 2) +
+    // with live lists the chunk records come first (16-byte aligned)
+    const size_t recs = use_live ? 8 * (size_t)nchunk : 0;
+    const size_t split_ints = recs + 2 * (size_t)nhub + 2 * (size_t)nchunk + (size_t)nhub * (HW + 4) +
                               (use_live ? 2 * (size_t)nchunk : 0) + 2 * (size_t)nchunk;
     if ((rc = ensure_split(w, split_ints))) return rc;
-    int* cstart0 = w->split;
+    int4* crec0 = use_live ? reinterpret_cast<int4*>(w->split) : nullptr;
+    int4* crec1 = use_live ? crec0 + nchunk : nullptr;
+    int* cstart0 = w->split + recs;
     int* cstart1 = cstart0 + nhub;
     int* owner0 = cstart1 + nhub;
     int* owner1 = owner0 + nchunk;
-    int* hubflags = owner1 + nchunk;   // HW bitmap words + done + lost per hub
+    int* hubflags = owner1 + nchunk;   // HW bitmap words + done + lost + 64-bit merge word per hub
     if (nhub > 0) {
-        const int cnt = nhub * (HW + 2);
+        const int cnt = nhub * (HW + 4);
         k_fill<<<std::min((cnt + WG - 1) / WG, cus * 4), WG, 0, st>>>(hubflags, cnt, 0);
     }
-    int* clen = use_live ? hubflags + (size_t)nhub * (HW + 2) : nullptr;   // per-chunk live lengths
+    int* clen = use_live ? hubflags + (size_t)nhub * (HW + 4) : nullptr;   // per-chunk live lengths
     int* cpos = use_live ? clen + nchunk : nullptr;                          // and resume positions
-    int* settled = hubflags + (size_t)nhub * (HW + 2) + (use_live ? 2 * (size_t)nchunk : 0);
+    int* settled = hubflags + (size_t)nhub * (HW + 4) + (use_live ? 2 * (size_t)nchunk : 0);
     if (use_live && (rc = ensure_live(w, std::max<size_t>((size_t)w->ctl_h->nnz, 1)))) return rc;
 
     // conflict hints serve the id rule (the degree rule would need the neighbour's degree too)
@@ -794,7 +798,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
                                           use_live ? w->llen : nullptr, clen, lb, J.opt.pushff == 2,
                                           (F && !use_wake) ? w->dirty : nullptr,
                                           use_wake ? w->rflag : nullptr, w->aflag, use_wake ? w->srnd : nullptr,
-                                          w->Fs, (J.opt.pushff == 2 && !use_wake) ? w->Fq : nullptr);
+                                          w->Fs, (J.opt.pushff == 2 && !use_wake) ? w->Fq : nullptr, crec1);
     });
     HIP_TRY(hipGetLastError());
 
@@ -819,6 +823,9 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     a.hubbm = reinterpret_cast<unsigned*>(hubflags);
     a.hubdone = hubflags + (size_t)nhub * HW;
     a.hublost = a.hubdone + nhub;
+    a.hubst = reinterpret_cast<unsigned long long*>(a.hublost + nhub);
+    a.crec[0] = crec0;
+    a.crec[1] = crec1;
     a.settled = (J.opt.pushff && nhub > 0) ? settled : nullptr;
     a.settled_k = settled + nchunk;
     a.pushff = J.opt.pushff;
@@ -1112,7 +1119,7 @@ int run_device(Workspace* w, Job& J, const long long* voff, int G, int* ncolors_
     // the arc-sized buffers must cover every graph of at most cap_n vertices and arc_cap
     // arcs (a host-driven call may have grown the vertex arrays since they were sized)
     const bool covered = w->arc_cap > 0 && w->F_cap >= (w->cap_n + (size_t)w->arc_cap) / 4 + 4 &&
-                         w->split_cap >= (size_t)(w->arc_cap / 21 + 64) && w->live_cap >= (size_t)w->arc_cap;
+                         w->split_cap >= (size_t)(w->arc_cap / 16 + 64) && w->live_cap >= (size_t)w->arc_cap;
     const bool fresh = (size_t)n > w->cap_n || !w->ctl || !w->plan || !covered;
     int rc = ensure_capacity(w, (size_t)n, st_cap);
     if (rc) return rc;
@@ -1124,9 +1131,9 @@ int run_device(Workspace* w, Job& J, const long long* voff, int G, int* ncolors_
         const long long arcs = std::max<long long>(std::max(*w->sz_h, 0), w->arc_cap);
         // byte flags for every vertex and arc the workspace holds (the larger flag
         // variant); split-row scratch for the most hubs and chunks that many arcs allow
-        // (a hub has more than 1024 arcs: 36 ints per hub, 6 per 2048-arc chunk)
+        // (a hub has more than 1024 arcs: 38 ints per hub, 14 per 2048-arc chunk)
         if ((rc = ensure_F(w, (size_t)((w->cap_n + arcs) / 4 + 4)))) return rc;
-        if ((rc = ensure_split(w, (size_t)(arcs / 21 + 64)))) return rc;
+        if ((rc = ensure_split(w, (size_t)(arcs / 16 + 64)))) return rc;
         if ((rc = ensure_live(w, (size_t)std::max<long long>(arcs, 1)))) return rc;
         w->arc_cap = std::max<long long>(arcs, 1);
     }
@@ -1217,7 +1224,7 @@ constexpr size_t na_align(size_t x) { return (x + 255) / 256 * 256; }
 constexpr size_t NA_N = CSRCOLOR_NOALLOC_MAX_N;
 constexpr size_t NA_E = CSRCOLOR_NOALLOC_MAX_NNZ;
 constexpr size_t NA_F_WORDS = (NA_N + NA_E) / 4 + 4;
-constexpr size_t NA_SPLIT_INTS = NA_E / 21 + 64;
+constexpr size_t NA_SPLIT_INTS = NA_E / 21 + 64;   // without live lists: 38 ints per hub, 4 per chunk
 constexpr size_t NA_CTL = 0;
 constexpr size_t NA_PLAN = na_align(sizeof(Ctl));
 constexpr size_t NA_X = NA_PLAN + na_align(sizeof(DevPlan));

@@ -355,6 +355,11 @@ struct RoundArgs {
     unsigned* hubbm;
     int* hubdone;
     int* hublost;
+    // split bucket with live lists: per chunk its record {queue entry, hub, chunk index,
+    // list slot}; per queue entry one word holding the finished-chunk count (low half)
+    // and the number of chunks that found a conflict (high half)
+    int4* crec[2];
+    unsigned long long* hubst;
     int* settled;       // push tasks of the split rows that settled this round: queue entry
     int* settled_k;     // and chunk index
     // wake flags (rflag != nullptr): a requeued vertex of at most WAKE_DEG arcs is

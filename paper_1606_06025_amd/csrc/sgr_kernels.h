@@ -199,7 +199,7 @@ __device__ __forceinline__ void round1_body(int n, const int* __restrict__ rowpt
                                             int rule, int jp, int* hint, int* llen, int* clen,
                                             unsigned long long* lb1, int fbytes, unsigned char* dirty,
                                             unsigned char* rflag, unsigned char* aflag, int* srnd,
-                                            unsigned long long* Fs, unsigned char* Fq) {
+                                            unsigned long long* Fs, unsigned char* Fq, int4* crec1) {
     constexpr int ITER = 4;
     __shared__ int buf[WAVES][NB][ITER * 64];
     __shared__ int wcnt[WAVES][NB];
@@ -300,6 +300,8 @@ __device__ __forceinline__ void round1_body(int n, const int* __restrict__ rowpt
                         llen[v] = cs;
                         for (int k = 0; k < nch; ++k) clen[cs + k] = -1;
                     }
+                    if (crec1)
+                        for (int k = 0; k < nch; ++k) crec1[cs + k] = make_int4(p, v, k, cs + k);
                     bkt = -1;
                 }
             } else {
@@ -366,9 +368,9 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
                                                int rule, int jp, int* hint, int* llen, int* clen,
                                                unsigned long long* lb1, int fbytes, unsigned char* dirty,
                                                unsigned char* rflag, unsigned char* aflag, int* srnd,
-                                               unsigned long long* Fs, unsigned char* Fq) {
+                                               unsigned long long* Fs, unsigned char* Fq, int4* crec1) {
     round1_body(n, rowptr, colidx, X, out, wl1, ctl, sorted, twave, tsplit, seg.s, cstart1, owner1, F, nnz,
-                rule, jp, hint, llen, clen, lb1, fbytes, dirty, rflag, aflag, srnd, Fs, Fq);
+                rule, jp, hint, llen, clen, lb1, fbytes, dirty, rflag, aflag, srnd, Fs, Fq, crec1);
 }
 
 // Flag-scanning conflict test of the vertices of at most WAKE_DEG arcs, run by block

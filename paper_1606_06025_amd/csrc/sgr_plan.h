@@ -71,20 +71,25 @@ __global__ void k_dev_plan(RoundArgs t, DevCaps c, DevPlan* p) {
         const long long flags = (long long)nnz + n;
         fw = a.pushff == 2 ? flags / 4 + 4 : flags / 32 + 2;
     }
-    const long long split_ints = 2LL * nhub + 2LL * nchunk + (long long)nhub * (HW + 2) +
+    // (the same layout as the host-driven runs: chunk records first, 16-byte aligned)
+    const long long recs = use_live ? 8LL * nchunk : 0;
+    const long long split_ints = recs + 2LL * nhub + 2LL * nchunk + (long long)nhub * (HW + 4) +
                                  (use_live ? 2LL * nchunk : 0) + 2LL * nchunk;
     if (fw > c.f_words || split_ints > c.split_ints) {
         atomicOr(&ctl->err, ERR_NOMEM);
         return;
     }
-    int* cstart0 = c.split;
+    int4* crec0 = use_live ? reinterpret_cast<int4*>(c.split) : nullptr;
+    int4* crec1 = use_live ? crec0 + nchunk : nullptr;
+    int* cstart0 = c.split + recs;
     int* cstart1 = cstart0 + nhub;
     int* owner0 = cstart1 + nhub;
     int* owner1 = owner0 + nchunk;
-    int* hubflags = owner1 + nchunk;   // HW bitmap words per hub, then done counters, then lost flags
-    int* clen = use_live ? hubflags + (size_t)nhub * (HW + 2) : nullptr;
+    // per hub: HW bitmap words, then done counters, lost flags and 64-bit merge words
+    int* hubflags = owner1 + nchunk;
+    int* clen = use_live ? hubflags + (size_t)nhub * (HW + 4) : nullptr;
     int* cpos = use_live ? clen + nchunk : nullptr;
-    int* settled = hubflags + (size_t)nhub * (HW + 2) + (use_live ? 2 * nchunk : 0);
+    int* settled = hubflags + (size_t)nhub * (HW + 4) + (use_live ? 2 * nchunk : 0);
     a.cstart[0] = cstart0;
     a.cstart[1] = cstart1;
     a.owner[0] = owner0;
@@ -92,6 +97,9 @@ __global__ void k_dev_plan(RoundArgs t, DevCaps c, DevPlan* p) {
     a.hubbm = reinterpret_cast<unsigned*>(hubflags);
     a.hubdone = hubflags + (size_t)nhub * HW;
     a.hublost = a.hubdone + nhub;
+    a.hubst = reinterpret_cast<unsigned long long*>(a.hublost + nhub);
+    a.crec[0] = crec0;
+    a.crec[1] = crec1;
     a.settled = (a.pushff && nhub > 0) ? settled : nullptr;
     a.settled_k = settled + nchunk;
     a.live = use_live ? t.live : nullptr;
@@ -116,7 +124,7 @@ __global__ void k_dev_plan(RoundArgs t, DevCaps c, DevPlan* p) {
     p->lb1 = c.lb1;
     p->lb1_ints = c.lb1 ? c.lb1_ints : 0;
     p->f_words = fw;
-    p->hub_ints = nhub * (HW + 2);
+    p->hub_ints = nhub * (HW + 4);
     p->dirty_words = a.pushff ? n / 4 + 1 : 0;
     p->fq_words = a.Fq ? (long long)n * (KQ / 4) : 0;
 }
@@ -155,7 +163,7 @@ __global__ __launch_bounds__(WG) void k_round1_dev(const DevPlan* __restrict__ p
     if (a.ctl->err) return;
     round1_body(a.n, a.rowptr, a.colidx, a.X, a.out, const_cast<int*>(a.wl_in), a.ctl, a.sorted, a.twave,
                 a.tsplit, a.seg, a.cstart[1], a.owner[1], a.F, a.nnz, a.rule, 0, a.hint, a.llen, a.clen, p->lb1,
-                a.pushff == 2, a.dirty, nullptr, nullptr, nullptr, nullptr, a.Fq);
+                a.pushff == 2, a.dirty, nullptr, nullptr, nullptr, nullptr, a.Fq, a.crec[1]);
 }
 
 // Every round after the first in one launch (persistent_rounds), arguments from the plan.

@@ -1618,19 +1618,22 @@ __device__ __forceinline__ void detect_split(const RoundArgs& a, const int* list
 }
 
 // Split bucket with live lists.  Each wavefront takes a batch of up to 64 chunks, one
-// lane per chunk: the lanes load their chunk's hub, row range, tentative colour, hint
-// and list state together, and look at the first quad of their lists (live_probe);
-// only the chunks still undecided then get the whole wavefront, one after another
-// (skipped once a sibling chunk has found a conflict).  Each lane merges its chunk's
-// verdict into the hub's lost flag and counts the chunk done; the chunk that completes
-// the count settles the hub or requeues it with a fresh chunk range.
+// lane per chunk.  A lane reads its chunk's record (queue entry, hub, chunk index and
+// list slot), then in one step the hub's row bounds, colour word and hint, the chunk's
+// list state and the hub's merge word, then the hint's colour word together with the
+// first quad of the chunk's list (or unexamined row), and last that quad's colour
+// words (live_probe's look, fused).  Only the chunks still undecided then get the
+// whole wavefront, one after another (skipped once a sibling chunk has found a
+// conflict).  Each lane merges its chunk into the hub's merge word with one 64-bit
+// atomic add (the chunk count and, when it found a conflict, one in the high half);
+// the chunk that completes the count settles the hub or requeues it with fresh chunks.
 template <bool W>
 __device__ __forceinline__ void detect_split_wave(const RoundArgs& a, const int* list, int nchunks, int j,
                                                   int nbk, int* outl, int* cnt_out, int& cmax) {
-    const int* cstart = a.cstart[a.par_in];
-    const int* owner = a.owner[a.par_in];
+    const int4* crec = a.crec[a.par_in];
     int* cstart_out = a.cstart[a.par_out];
     int* owner_out = a.owner[a.par_out];
+    int4* crec_out = a.crec[a.par_out];
     const int lane = __lane_id();
     const int nw = nbk * WAVES;                      // wavefronts of the bucket
     const int gw = j * WAVES + (threadIdx.x >> 6);   // this one's index among them
@@ -1641,76 +1644,102 @@ __device__ __forceinline__ void detect_split_wave(const RoundArgs& a, const int*
     for (int t0 = gw * B; t0 < nchunks; t0 += nw * B) {
         const int t = t0 + lane;
         const bool on = lane < B && t < nchunks;
-        int p = 0, v = 0, rb = 0, re = 0, cv = 0, ci = 0, cl = -1, cp = 0, beg = 0, end = 0, nch = 0;
-        bool hit = false, done = !on;
+        int p = 0, v = 0, k = 0, ci = 0;
         if (on) {
-            p = owner[t];
-            v = list[p];
-            const int k = t - cstart[p];
+            const int4 r = crec[t];
+            p = r.x;
+            v = r.y;
+            k = r.z;
+            ci = r.w;
+        }
+        int rb = 0, re = 0, xv = 0, hh = -1, cl = -1, cp = 0;
+        unsigned long long hs = 0;
+        if (on) {
             rb = a.rowptr[v];
             re = a.rowptr[v + 1];
-            cv = tentative(a, v);
-            ci = a.llen[v] + k;
-            nch = split_chunks(re - rb);
-            beg = rb + k * SPLIT_CH;
-            end = min(beg + SPLIT_CH, re);
-            hit = hint_hit(a, v, cv);
-            if (!hit) {
-                cl = a.clen[ci];
-                cp = cl >= 0 ? a.cpos[ci] : beg;
-                done = ld_agent(&a.hublost[p]) != 0;     // a sibling chunk already decided
-            }
-            if (!hit && !done) {
-                const int pr = live_probe(a, v, cv, beg, end, cl, cp, hf);
-                hit = pr > 0;
-                done = pr != 0;
-            }
-            done = done || hit;
+            xv = a.X[v];
+            hh = a.hint ? a.hint[v] : -1;
+            cl = a.clen[ci];
+            cp = a.cpos[ci];
+            hs = ld_agent(&a.hubst[p]);
         }
+        const int cv = xv & CMASK;
+        const int nch = split_chunks(re - rb);
+        const int beg = rb + k * SPLIT_CH;
+        const int end = min(beg + SPLIT_CH, re);
+        const int h = (hh != -1 && (hh & IDMASK) < v) ? (hh & IDMASK) : -1;
+        const bool fresh = cl < 0;                       // nothing examined yet
+        const int len = fresh ? 0 : cl;
+        const int pos = fresh ? beg : cp;
+        const bool empty = len == 0 && pos >= end;        // nothing left to examine
+        bool done = !on || (hs >> 32) != 0;              // a sibling chunk found a conflict
+        int hx = 0;
+        int w[4] = {-1, -1, -1, -1};
+        if (!done && h >= 0) hx = a.X[h];
+        if (!done && !empty) {
+            if (len > 0) load_quad(a.live, a.nnz, beg, beg + len, 0, w);
+            else load_quad(a.colidx, a.nnz, pos, end, 0, w);
+        }
+        bool hit = !done && h >= 0 && (hx & CMASK) == cv;
+        int g[4] = {0, 0, 0, 0};
+        if (!done && !hit) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) g[q] = (w[q] >= 0 && w[q] < v) ? a.X[w[q]] : 0;
+        }
+        if (!done && !hit) {
+            int found = -1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (w[q] >= 0 && w[q] < v && (g[q] & CMASK) == cv) found = w[q];
+            if (found >= 0) {
+                hit = true;
+                if (a.hint) a.hint[v] = found | hf;
+            }
+        }
+        done = done || hit || empty;
         unsigned long long todo = __ballot(!done);
         while (todo) {
             const int jj = __ffsll((long long)todo) - 1;
             todo &= todo - 1;
             const int pj = __builtin_amdgcn_readlane(p, jj);
-            // a chunk that another wavefront has already decided for the hub is skipped
+            // a chunk whose hub another chunk has already decided is skipped
             int sk = 0;
-            if (lane == 0) sk = ld_agent(&a.hublost[pj]) != 0;
+            if (lane == 0) sk = (ld_agent(&a.hubst[pj]) >> 32) != 0;
             if (__builtin_amdgcn_readfirstlane(sk)) continue;
             const int vj = __builtin_amdgcn_readlane(v, jj);
             const int cij = __builtin_amdgcn_readlane(ci, jj);
-            const bool h = live_test_wave(a, vj, __builtin_amdgcn_readlane(cv, jj), __builtin_amdgcn_readlane(beg, jj),
-                                          __builtin_amdgcn_readlane(end, jj), __builtin_amdgcn_readlane(cl, jj),
-                                          __builtin_amdgcn_readlane(cp, jj), &a.clen[cij], &a.cpos[cij], hf);
-            if (lane == jj) hit = h;
+            const bool hj = live_test_wave(a, vj, __builtin_amdgcn_readlane(cv, jj), __builtin_amdgcn_readlane(beg, jj),
+                                           __builtin_amdgcn_readlane(end, jj), __builtin_amdgcn_readlane(cl, jj),
+                                           __builtin_amdgcn_readlane(cp, jj), &a.clen[cij], &a.cpos[cij], hf);
+            if (lane == jj) hit = hj;
         }
-        // merge: the verdict first, then the done count (ordered by waiting for the
-        // returned value of the verdict's atomic)
-        int decide = 0;
+        // merge: one atomic adds the finished chunk and, with a conflict, a hit
         if (on) {
-            unsigned old = 0;
-            if (hit) old = or_agent(reinterpret_cast<unsigned*>(&a.hublost[p]), 1u);
-            wait_on(old);
-            decide = add_agent(&a.hubdone[p], 1) == nch - 1;
-        }
-        if (decide) {
-            // the last chunk to finish settles the hub or requeues it with fresh chunks
-            const bool lost = ld_agent(&a.hublost[p]) != 0;
-            st_agent(&a.hublost[p], 0);
-            st_agent(&a.hubdone[p], 0);
-            if (lost) {
-                const int qn = atomicAdd(cnt_out, 1);
-                const int cs = atomicAdd(&a.ctl->ccnt[a.par_out], nch);
-                outl[qn] = v;
-                cstart_out[qn] = cs;
-                for (int i = 0; i < nch; ++i) owner_out[cs + i] = qn;
-            } else {
-                settle<W>(a, v, cv, cmax);
-                if (a.settled) {
-                    // one push task per chunk of the settled row
-                    const int cs = atomicAdd(&a.ctl->nsettled, nch);
+            const unsigned long long old =
+                atomicAdd(&a.hubst[p], 1ull + (hit ? (1ull << 32) : 0ull));
+            if ((int)(old & 0xffffffffull) + 1 == nch) {
+                // the last chunk to finish settles the hub or requeues it with fresh chunks
+                const bool lost = hit || (old >> 32) != 0;
+                st_agent(&a.hubst[p], 0ull);
+                const int base = ci - k;                 // the hub's chunk slots
+                if (lost) {
+                    const int qn = atomicAdd(cnt_out, 1);
+                    const int cs = atomicAdd(&a.ctl->ccnt[a.par_out], nch);
+                    outl[qn] = v;
+                    cstart_out[qn] = cs;
                     for (int i = 0; i < nch; ++i) {
-                        a.settled[cs + i] = p;
-                        a.settled_k[cs + i] = i;
+                        owner_out[cs + i] = qn;
+                        crec_out[cs + i] = make_int4(qn, v, i, base + i);
+                    }
+                } else {
+                    settle<W>(a, v, cv, cmax);
+                    if (a.settled) {
+                        // one push task per chunk of the settled row
+                        const int cs = atomicAdd(&a.ctl->nsettled, nch);
+                        for (int i = 0; i < nch; ++i) {
+                            a.settled[cs + i] = p;
+                            a.settled_k[cs + i] = i;
+                        }
                     }
                 }
             }
