@@ -299,6 +299,18 @@ def traffic_summary(workload: str, fetch_dir: str, write_dir: str, cfetch_dir: s
                              "write_kib_per_dispatch": wd["per_dispatch"],
                              "fetch_bytes_per_launch": fd["per_dispatch"] * 1024.0 / ff,
                              "write_bytes_per_launch": wd["per_dispatch"] * 1024.0 / wf}
+    # the conflict-test phase of the worklist rounds: k_detect and, on graphs with split
+    # rows, k_push, timed together (bench reports its launches as both kernels' dispatches)
+    ks = out["kernels"]
+    if "k_detect" in ks and "k_push" in ks:
+        d, p = ks["k_detect"], ks["k_push"]
+        nd = d["dispatches"] + p["dispatches"]
+        ks["k_detect+k_push"] = {
+            "dispatches": nd,
+            "fetch_bytes_per_launch": (d["fetch_bytes_per_launch"] * d["dispatches"] +
+                                       p["fetch_bytes_per_launch"] * p["dispatches"]) / nd,
+            "write_bytes_per_launch": (d["write_bytes_per_launch"] * d["dispatches"] +
+                                       p["write_bytes_per_launch"] * p["dispatches"]) / nd}
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as f:

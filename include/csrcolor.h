@@ -145,6 +145,11 @@ typedef struct {
                                unordered compaction): a requeued vertex is tested again only once its tentative
                                colour or that of the neighbour that requeued it has changed; every other one
                                loses again without being read (same colouring and rounds) */
+    int32_t tile_limits;    /* 0: default.  Largest degrees of the tile buckets 0, 1, 2 (2, 4, 8 lanes per vertex
+                               in the tiled kernels; bucket 3, 16 lanes, ends at 61 arcs) packed one per byte,
+                               t0 | t1 << 8 | t2 << 16 with t0 <= t1 <= t2 and t0 <= 5, t1 <= 13, t2 <= 29 (the
+                               defaults 5, 13, 29 are the most each width holds in one quad per lane); smaller
+                               values move vertices to wider tiles (same colouring) */
 } csrcolor_opts;
 
 /* Optional run statistics (HOST struct).  Set `cap`, `time_kernels` and the array

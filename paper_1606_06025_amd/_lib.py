@@ -51,7 +51,7 @@ class Opts(ctypes.Structure):
                 ("rule", ctypes.c_int32), ("algorithm", ctypes.c_int32), ("seed_lo", ctypes.c_uint32),
                 ("seed_hi", ctypes.c_uint32), ("hints", ctypes.c_int32),
                 ("live_lists", ctypes.c_int32), ("ordered", ctypes.c_int32),
-                ("wake", ctypes.c_int32)]
+                ("wake", ctypes.c_int32), ("tile_limits", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

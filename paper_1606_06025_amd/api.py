@@ -31,7 +31,7 @@ def make_opts(mode: int = 0, validate: int = 0, t_wave: int = 0, t_split: int = 
               blocks_per_cu: int = 0, sync_every: int = 0, lane_assign: int = 0,
               lane_detect: int = 0, firstfit: int = 0, rule: int = 0, algorithm: int = 0,
               seed: int = 0, hints: int = 0, live_lists: int = 0, ordered: int = 0,
-              wake: int = 0) -> L.Opts:
+              wake: int = 0, tile_limits: int = 0) -> L.Opts:
     o = L.Opts()
     o.mode, o.validate, o.t_wave, o.t_split = mode, validate, t_wave, t_split
     o.blocks_per_cu, o.sync_every = blocks_per_cu, sync_every
@@ -41,6 +41,7 @@ def make_opts(mode: int = 0, validate: int = 0, t_wave: int = 0, t_split: int = 
     o.live_lists = live_lists
     o.ordered = ordered
     o.wake = wake
+    o.tile_limits = tile_limits
     seed &= (1 << 64) - 1
     o.seed_lo, o.seed_hi = seed & 0xFFFFFFFF, seed >> 32
     return o

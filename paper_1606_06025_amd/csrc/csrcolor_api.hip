@@ -357,6 +357,7 @@ struct Options {
     int mode = CSRCOLOR_MODE_LOOP;
     int validate = 0;
     int twave = 1024;
+    int tiles = TILES_DEFAULT;
     int blocks_per_cu = 6;
     int sync_every = 8;
     int tsplit = 2048;
@@ -387,6 +388,10 @@ bool opts_valid(const csrcolor_opts* o, bool single) {
         return false;
     if (o->algorithm != CSRCOLOR_ALGO_SGR && (o->mode == CSRCOLOR_MODE_PERSISTENT || o->mode == CSRCOLOR_MODE_GRAPH))
         return false;
+    if (o->tile_limits) {
+        const int t0 = o->tile_limits & 0xff, t1 = (o->tile_limits >> 8) & 0xff, t2 = (o->tile_limits >> 16) & 0xff;
+        if ((o->tile_limits >> 24) != 0 || t0 > 5 || t1 > 13 || t2 > 29 || t0 > t1 || t1 > t2) return false;
+    }
     if (!single && o->algorithm == CSRCOLOR_ALGO_JP) return false;
     return true;
 }
@@ -400,6 +405,7 @@ Options parse_opts(const csrcolor_opts* o) {
     if (o->blocks_per_cu > 0) r.blocks_per_cu = std::min(o->blocks_per_cu, 32);
     if (o->sync_every > 0) r.sync_every = std::min(o->sync_every, 256);
     if (o->t_split > 0) r.tsplit = std::max(o->t_split, TSPLIT_MIN);
+    if (o->tile_limits) r.tiles = o->tile_limits;
     r.tsplit = std::max(r.tsplit, r.twave);
     if (o->lane_assign) r.lane_assign = o->lane_assign < 0 ? 0 : (o->lane_assign & 0xF);
     if (o->lane_detect) r.lane_detect = o->lane_detect < 0 ? 0x10 : (0x10 | (o->lane_detect & 0xF));
@@ -798,7 +804,8 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
                                           use_live ? w->llen : nullptr, clen, lb, J.opt.pushff == 2,
                                           (F && !use_wake) ? w->dirty : nullptr,
                                           use_wake ? w->rflag : nullptr, w->aflag, use_wake ? w->srnd : nullptr,
-                                          w->Fs, (J.opt.pushff == 2 && !use_wake) ? w->Fq : nullptr, crec1);
+                                          w->Fs, (J.opt.pushff == 2 && !use_wake) ? w->Fq : nullptr, crec1,
+                                          J.opt.tiles);
     });
     HIP_TRY(hipGetLastError());
 
@@ -811,6 +818,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     a.out = J.colors_out;
     a.ctl = w->ctl;
     a.twave = twave;
+    a.tiles = J.opt.tiles;
     a.sorted = J.sorted;
     a.nnz = w->ctl_h->nnz;
     a.lane_mode_assign = J.opt.lane_assign;
@@ -1032,6 +1040,7 @@ int enqueue_device(Workspace* w, Job& J, const long long* voff, int G, int* ncol
     t.wl_in = w->wl[1];
     t.wl_out = w->wl[0];
     t.twave = o.twave;
+    t.tiles = o.tiles;
     t.tsplit = o.tsplit;
     t.lane_mode_assign = o.lane_assign;
     t.lane_mode_detect = o.lane_detect;
@@ -1064,7 +1073,8 @@ int enqueue_device(Workspace* w, Job& J, const long long* voff, int G, int* ncol
     if (vblocks_out) *vblocks_out = vblocks;
     const int rblocks = (int)std::max<long long>(
         1, std::min<long long>(((long long)n + WG * VROWS - 1) / (WG * VROWS), (long long)cus * 4));
-    T.kern(0, k_validate_rows, rblocks, WG, n, J.rowptr, J.colidx, w->ctl, o.twave, o.tsplit, J.expect_nnz);
+    T.kern(0, k_validate_rows, rblocks, WG, n, J.rowptr, J.colidx, w->ctl, o.twave, o.tsplit, J.expect_nnz,
+           o.tiles);
     T.kern(0, k_validate_arcs, cus * 4, WG, n, J.rowptr, J.colidx, w->ctl);
     if (voff) k_validate_batch<<<std::min(G, cus * 16), WG, 0, st>>>(G, n, voff, J.rowptr, J.colidx, w->ctl);
     if (o.validate >= 1) k_check_symmetric<<<std::max(vblocks, 1), WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl);
@@ -1174,7 +1184,8 @@ int run_job(Workspace* w, Job& J, const long long* voff, int G) {
     const int vblocks = (int)std::min<long long>(((long long)n + WG - 1) / WG, (long long)cus * 4);
     const int rblocks = (int)std::max<long long>(
         1, std::min<long long>(((long long)n + WG * VROWS - 1) / (WG * VROWS), (long long)cus * 4));
-    T.kern(0, k_validate_rows, rblocks, WG, n, J.rowptr, J.colidx, w->ctl, twave, J.opt.tsplit, -1LL);
+    T.kern(0, k_validate_rows, rblocks, WG, n, J.rowptr, J.colidx, w->ctl, twave, J.opt.tsplit, -1LL,
+           J.opt.tiles);
     // the arc pass skips itself when the vertex pass found an error, so one read-back
     // covers both
     T.kern(0, k_validate_arcs, cus * 4, WG, n, J.rowptr, J.colidx, w->ctl);

@@ -44,8 +44,13 @@ constexpr int NTILE = 4;
 constexpr int BSPLIT = 6;
 constexpr int SPLIT_CH = 2048;        // arcs per chunk of a split row
 constexpr int HW = 32;                // words of a split row's colour bitmap (colours 1..1024)
-__host__ __device__ inline int bucket_of(int deg, int twave, int tsplit) {
-    return deg <= 5 ? 0 : deg <= 13 ? 1 : deg <= 29 ? 2 : deg <= 61 ? 3 : deg <= twave ? 4 : deg <= tsplit ? 5 : 6;
+// Largest degrees of the tile buckets 0..2 packed one per byte (bucket 3 ends at 61):
+// the defaults are the most each tile width can hold (4L-3 for L = 2, 4, 8 lanes); any
+// smaller non-decreasing values are valid and only move vertices to wider tiles.
+constexpr int TILES_DEFAULT = 5 | (13 << 8) | (29 << 16);
+__host__ __device__ inline int bucket_of(int deg, int tiles, int twave, int tsplit) {
+    return deg <= (tiles & 0xff) ? 0 : deg <= ((tiles >> 8) & 0xff) ? 1 : deg <= ((tiles >> 16) & 0xff) ? 2
+         : deg <= 61 ? 3 : deg <= twave ? 4 : deg <= tsplit ? 5 : 6;
 }
 __host__ __device__ inline int split_chunks(int deg) { return (deg + SPLIT_CH - 1) / SPLIT_CH; }
 
@@ -307,6 +312,7 @@ struct RoundArgs {
     int par_in;         // worklist parity read this round
     int par_out;
     int twave;
+    int tiles;          // tile-bucket degree limits (bucket_of)
     int sorted;         // 1: every row ascending -> conflict scans stop at the first w >= v
     int round;          // persistent mode: 0-based index of the first round it runs
     int nnz;            // rowptr[n], bounds the 16-byte row reads

@@ -32,7 +32,7 @@ constexpr int VQUADS = 4;  // 16-byte quads of colidx per lane and loop pass of 
 
 __global__ __launch_bounds__(WG) void k_validate_rows(int n, const int* __restrict__ rowptr,
                                                       const int* __restrict__ colidx, Ctl* ctl, int twave,
-                                                      int tsplit, long long expect_nnz) {
+                                                      int tsplit, long long expect_nnz, int tiles) {
     const int nnz = rowptr[n];
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->nnz = nnz;
     const bool stated = expect_nnz < 0 || (long long)nnz == expect_nnz;
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(WG) void k_validate_rows(int n, const int* __restri
             mydeg = max(mydeg, deg);
             if (deg > WAKE_DEG) big += deg;
             if (deg > 0) {
-                const int bk = bucket_of(deg, twave, tsplit);
+                const int bk = bucket_of(deg, tiles, twave, tsplit);
                 if (bk == BSPLIT) chunks += split_chunks(deg);
 #pragma unroll
                 for (int b = 0; b < NB; ++b) hist[b] += (bk == b);
@@ -199,7 +199,7 @@ __device__ __forceinline__ void round1_body(int n, const int* __restrict__ rowpt
                                             int rule, int jp, int* hint, int* llen, int* clen,
                                             unsigned long long* lb1, int fbytes, unsigned char* dirty,
                                             unsigned char* rflag, unsigned char* aflag, int* srnd,
-                                            unsigned long long* Fs, unsigned char* Fq, int4* crec1) {
+                                            unsigned long long* Fs, unsigned char* Fq, int4* crec1, int tiles) {
     constexpr int ITER = 4;
     __shared__ int buf[WAVES][NB][ITER * 64];
     __shared__ int wcnt[WAVES][NB];
@@ -283,7 +283,7 @@ __device__ __forceinline__ void round1_body(int n, const int* __restrict__ rowpt
             }
             if (lose) {
                 X[v] = jp ? 0 : (FLAG | 1 | (rflag && end - beg > WAKE_DEG ? BIG : 0));
-                bkt = bucket_of(end - beg, twave, tsplit);
+                bkt = bucket_of(end - beg, tiles, twave, tsplit);
                 if (rflag && bkt < NTILE) bkt = -1;      // wake flags: not listed
                 if (llen && bkt >= NTILE && bkt < BSPLIT) llen[v] = -1;   // live list not built yet
                 if (bkt == BSPLIT) {
@@ -368,9 +368,9 @@ __global__ __launch_bounds__(WG) void k_round1(int n, const int* __restrict__ ro
                                                int rule, int jp, int* hint, int* llen, int* clen,
                                                unsigned long long* lb1, int fbytes, unsigned char* dirty,
                                                unsigned char* rflag, unsigned char* aflag, int* srnd,
-                                               unsigned long long* Fs, unsigned char* Fq, int4* crec1) {
+                                               unsigned long long* Fs, unsigned char* Fq, int4* crec1, int tiles) {
     round1_body(n, rowptr, colidx, X, out, wl1, ctl, sorted, twave, tsplit, seg.s, cstart1, owner1, F, nnz,
-                rule, jp, hint, llen, clen, lb1, fbytes, dirty, rflag, aflag, srnd, Fs, Fq, crec1);
+                rule, jp, hint, llen, clen, lb1, fbytes, dirty, rflag, aflag, srnd, Fs, Fq, crec1, tiles);
 }
 
 // Flag-scanning conflict test of the vertices of at most WAKE_DEG arcs, run by block

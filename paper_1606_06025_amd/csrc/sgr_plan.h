@@ -163,7 +163,7 @@ __global__ __launch_bounds__(WG) void k_round1_dev(const DevPlan* __restrict__ p
     if (a.ctl->err) return;
     round1_body(a.n, a.rowptr, a.colidx, a.X, a.out, const_cast<int*>(a.wl_in), a.ctl, a.sorted, a.twave,
                 a.tsplit, a.seg, a.cstart[1], a.owner[1], a.F, a.nnz, a.rule, 0, a.hint, a.llen, a.clen, p->lb1,
-                a.pushff == 2, a.dirty, nullptr, nullptr, nullptr, nullptr, a.Fq, a.crec[1]);
+                a.pushff == 2, a.dirty, nullptr, nullptr, nullptr, nullptr, a.Fq, a.crec[1], a.tiles);
 }
 
 // Every round after the first in one launch (persistent_rounds), arguments from the plan.

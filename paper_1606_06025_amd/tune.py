@@ -1,8 +1,8 @@
 """Autotuner for the colouring launch options.
 
 None of the options changes the colouring; they only move work between kernels and
-launch shapes: drive mode (host loop / replayed hipGraph), FirstFit variant (rescan /
-push bitmaps), the degree thresholds of the wavefront and split-row buckets, the
+launch shapes: drive mode (host loop / replayed hipGraph / persistent), FirstFit variant
+(rescan / push bitmaps), the degree thresholds of the tile, wavefront and split-row buckets, the
 workgroups per CU, how the low-degree conflict test maps lanes, and how often the
 host reads the queue sizes back.  The tuner times candidates on the actual graph by
 coordinate descent from the library defaults (each knob in turn, keeping the best
@@ -29,6 +29,8 @@ KNOBS: List[Tuple[str, Sequence[int]]] = [
     ("mode", (1, 3, 2)),
     ("t_wave", (1024, 256, 128)),
     ("t_split", (2048, 8192, 1024)),
+    # tile-bucket degree limits t0 | t1 << 8 | t2 << 16 (0 = 5, 13, 29)
+    ("tile_limits", (0, 3 | (9 << 8) | (21 << 16), 2 | (5 << 8) | (13 << 16))),
     ("blocks_per_cu", (6, 4, 8)),
     ("lane_detect", (-1, 15)),
     ("sync_every", (8, 16, 32)),

@@ -87,6 +87,10 @@ def test_algorithm_option_errors_without_device_work(lib):
     assert ex(opts(ordered=-3)) == L.EINVAL
     assert ex(opts(wake=2)) == L.EINVAL
     assert ex(opts(wake=-2)) == L.EINVAL
+    assert ex(opts(tile_limits=6 | (13 << 8) | (29 << 16))) == L.EINVAL    # t0 above 5
+    assert ex(opts(tile_limits=5 | (4 << 8) | (29 << 16))) == L.EINVAL     # not non-decreasing
+    assert ex(opts(tile_limits=5 | (13 << 8) | (30 << 16))) == L.EINVAL    # t2 above 29
+    assert ex(opts(tile_limits=1 << 24)) == L.EINVAL
     for algo in (L.ALGO_SGR_TOPO, L.ALGO_JP):
         for mode in (L.MODE_PERSISTENT, L.MODE_GRAPH):
             assert ex(opts(algorithm=algo, mode=mode)) == L.EINVAL
@@ -106,10 +110,10 @@ def _header_struct_fields(name):
 
 
 def test_struct_layouts_match_header():
-    # csrcolor_opts: 17 x 32-bit fields (10 options, algorithm, two seed halves, hints, live lists, ordered,
-    # wake lists)
+    # csrcolor_opts: 18 x 32-bit fields (10 options, algorithm, two seed halves, hints, live lists, ordered,
+    # wake lists, tile limits)
     # csrcolor_stats: 4 int32, int64, 2 int32, 2 pointers, 3 double, 2 int32, a pointer
-    assert ctypes.sizeof(L.Opts) == 17 * 4
+    assert ctypes.sizeof(L.Opts) == 18 * 4
     assert ctypes.sizeof(L.Stats) == 4 * 4 + 8 + 2 * 4 + 2 * 8 + 3 * 8 + 2 * 4 + 8
     assert _header_struct_fields("csrcolor_opts") == [f[0] for f in L.Opts._fields_]
     assert _header_struct_fields("csrcolor_stats") == [f[0] for f in L.Stats._fields_]

@@ -124,7 +124,11 @@ def test_mixed_stencils(dev):
                                 dict(blocks_per_cu=1), dict(blocks_per_cu=3), dict(sync_every=1),
                                 dict(sync_every=5), dict(t_wave=70, blocks_per_cu=2, sync_every=3),
                                 dict(hints=-1), dict(hints=1, lane_detect=-1), dict(hints=-1, lane_detect=-1),
-                                dict(wake=-1), dict(wake=1, lane_detect=-1), dict(wake=1, firstfit=2)])
+                                dict(wake=-1), dict(wake=1, lane_detect=-1), dict(wake=1, firstfit=2),
+                                dict(tile_limits=3 | (9 << 8) | (21 << 16)),
+                                dict(tile_limits=1 | (1 << 8) | (1 << 16), wake=-1),
+                                dict(tile_limits=2 | (5 << 8) | (13 << 16), firstfit=1, lane_detect=-1),
+                                dict(tile_limits=2 | (5 << 8) | (13 << 16), mode=2)])
 def test_launch_options_do_not_change_result(dev, kw):
     import oracle
     g = gg.rmat(13, 16, 9)
