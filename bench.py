@@ -511,11 +511,21 @@ def bench_serve(args, dev) -> int:
     pairs = [(g.rowptr, g.colidx) for g in graphs]
     budget = int(args.hbm_budget_gb * (1 << 30))
 
+    # batch limits (they size every slot's reserved workspace): twice the largest request
+    limits = dict(max_batch=args.max_batch, max_batch_vertices=2 * max(g.n for g in graphs),
+                  max_batch_arcs=2 * max(g.nnz for g in graphs))
+    ledger = {}
+
     def run(arrivals):
         be = serve.HipBackend(nslots=args.slots)
-        with serve.ColoringServer(be, budget, max_batch=args.max_batch) as srv:
+        with serve.ColoringServer(be, budget, **limits) as srv:
             rr, wall = serve.replay(srv, pairs, arrivals)
             peak = srv.peak_bytes
+            ledger.update(reserved_bytes=srv.reserved_bytes, peak_bytes=max(ledger.get("peak_bytes", 0), peak),
+                          library_bytes_in_use=max(ledger.get("library_bytes_in_use", 0),
+                                                   api.device_bytes_in_use()))
+        # the slots' workspaces belong to this server's streams
+        api.release_workspace()
         bad = [r for r in rr if r.error]
         if bad:
             raise RuntimeError(f"{len(bad)} requests failed: {bad[0].error}")
@@ -546,13 +556,23 @@ def bench_serve(args, dev) -> int:
     # (b) graphs already resident, colouring only
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    alone = []
     for rp, ci in pairs:
         drp = torch.from_numpy(rp).to(dev)
         dci = torch.from_numpy(ci).to(dev)
         col, _, _ = api.color(drp, dci)
-        col.cpu()
+        alone.append(col.cpu())
     torch.cuda.synchronize()
     single_path = time.perf_counter() - t0
+    # every served colouring (saturation run) against the same graph coloured alone, and
+    # the smaller requests against the CPU oracle
+    import oracle
+    same_alone = all(np.array_equal(r.colors, a.numpy()) for r, a in zip(rr, alone))
+    small = [i for i, g in enumerate(graphs) if g.nnz <= 1_000_000]
+    same_oracle = all(np.array_equal(rr[i].colors, oracle.sgr(graphs[i].n, graphs[i].rowptr, graphs[i].colidx).colors)
+                      for i in small)
+    log(f"served colourings equal alone: {same_alone}; {len(small)} requests of <= 1M arcs equal the oracle: "
+        f"{same_oracle}")
     dpairs = [(torch.from_numpy(rp).to(dev), torch.from_numpy(ci).to(dev)) for rp, ci in pairs]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -569,6 +589,9 @@ def bench_serve(args, dev) -> int:
         "dtype": "int32", "data": "synthetic",
         "config": {"workload": f"serve_{len(pairs)}_requests", "requests": len(pairs), "total_arcs": total_arcs,
                    "slots": args.slots, "hbm_budget_gb": args.hbm_budget_gb, "peak_admitted_bytes": peak,
+                   "ledger": ledger, "batch_limits": limits,
+                   "served_equal_alone": same_alone, "oracle_checked_requests": len(small),
+                   "oracle_equal": same_oracle,
                    "saturation_qps": sat_qps, "saturation_phases": phases, "loads": loads,
                    "one_graph_per_launch_with_transfers_arcs_per_s": total_arcs / single_path,
                    "one_graph_per_launch_resident_arcs_per_s": total_arcs / single,
@@ -576,7 +599,7 @@ def bench_serve(args, dev) -> int:
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(rec), flush=True)
-    return 0
+    return 0 if same_alone and same_oracle else 1
 
 
 def main() -> int:
@@ -587,7 +610,7 @@ def main() -> int:
     ap.add_argument("--workload", default="rmat23")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--graphs", type=int, default=2048, help="batched workload: number of graphs")
-    ap.add_argument("--requests", type=int, default=96, help="serve workload: number of requests")
+    ap.add_argument("--requests", type=int, default=512, help="serve workload: number of requests")
     ap.add_argument("--slots", type=int, default=3, help="serve workload: concurrent stream slots")
     ap.add_argument("--max-batch", type=int, default=16, help="serve workload: requests per batch")
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="serve workload: admission budget")

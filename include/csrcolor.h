@@ -285,6 +285,20 @@ int csrcolor_color_multi(int32_t G, const int32_t *n_host, const int64_t *nnz_ho
                          int32_t *const *colors_host, int32_t *ncolors_out,
                          const csrcolor_opts *opts, hipStream_t stream);
 
+/* Upper bound, in bytes, of the device memory one workspace needs to colour a graph of
+ * n vertices and nnz arcs with any options except statistics and ordered compaction
+ * (csrcolor_color, _ex, _batched; for csrcolor_color_multi give G >= 1 and the union's
+ * totals: it adds the library's copy of the union).  A workspace is kept per (device,
+ * stream) at the largest size it has needed, so a caller that bounds the graphs it
+ * gives one stream bounds that stream's workspace.  Pinned host staging (a few bytes
+ * per graph) is not included.  Returns CSRCOLOR_EINVAL for negative arguments. */
+int64_t csrcolor_workspace_bytes(int32_t G, int64_t n, int64_t nnz);
+
+/* Device bytes the library's workspaces hold now, over every device and stream (the
+ * fixed array of csrcolor_color_noalloc excluded).  Must not overlap a call that grows
+ * or releases a workspace. */
+int64_t csrcolor_device_bytes_in_use(void);
+
 /* Static description of a status code. */
 const char *csrcolor_strerror(int status);
 

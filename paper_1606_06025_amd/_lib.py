@@ -40,7 +40,8 @@ MODE_PERSISTENT = 2
 MODE_GRAPH = 3
 
 EXPORTS = ["csrcolor_color", "csrcolor_color_ex", "csrcolor_color_batched", "csrcolor_color_multi",
-           "csrcolor_color_noalloc", "csrcolor_strerror", "csrcolor_release_workspace", "csrcolor_version"]
+           "csrcolor_color_noalloc", "csrcolor_strerror", "csrcolor_release_workspace", "csrcolor_version",
+           "csrcolor_workspace_bytes", "csrcolor_device_bytes_in_use"]
 
 
 class Opts(ctypes.Structure):
@@ -99,6 +100,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.csrcolor_strerror.restype = ctypes.c_char_p
     lib.csrcolor_release_workspace.argtypes = []
     lib.csrcolor_release_workspace.restype = None
+    lib.csrcolor_workspace_bytes.argtypes = [I32, ctypes.c_int64, ctypes.c_int64]
+    lib.csrcolor_workspace_bytes.restype = ctypes.c_int64
+    lib.csrcolor_device_bytes_in_use.argtypes = []
+    lib.csrcolor_device_bytes_in_use.restype = ctypes.c_int64
     lib.csrcolor_version.argtypes = []
     lib.csrcolor_version.restype = ctypes.c_int
     _lib = lib

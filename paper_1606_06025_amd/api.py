@@ -209,3 +209,14 @@ def color_multi(graphs: Sequence[Tuple[torch.Tensor, torch.Tensor]], outs: Optio
 
 def release_workspace() -> None:
     L.load().csrcolor_release_workspace()
+
+
+def workspace_bytes(n: int, nnz: int, graphs: int = 0) -> int:
+    """Upper bound of the device bytes one stream's workspace needs for a graph (or, with
+    graphs >= 1, a union given to color_multi) of n vertices and nnz arcs."""
+    return int(L.load().csrcolor_workspace_bytes(graphs, n, nnz))
+
+
+def device_bytes_in_use() -> int:
+    """Device bytes the library's workspaces hold now."""
+    return int(L.load().csrcolor_device_bytes_in_use())

@@ -258,6 +258,45 @@ void free_ws_arrays(Workspace* w) {
 // Bytes of a wake-flag array for n vertices: whole scans of VPW vertices, zero padded.
 size_t flag_bytes(size_t n) { return (n + VPW - 1) / VPW * VPW + VPW; }
 
+// Device bytes of the per-vertex arrays for `cap` vertices (ensure_capacity).
+size_t vertex_bytes(size_t cap) {
+    return cap * (7 * sizeof(int) + sizeof(unsigned long long) + KQ + 1) + 16 + 2 * flag_bytes(cap);
+}
+
+// Device bytes a workspace holds now, from the capacities it was allocated with.
+size_t ws_bytes_now(const Workspace* w) {
+    size_t b = 0;
+    if (w->ctl) b += sizeof(Ctl) + 2 * sizeof(unsigned long long);
+    if (w->cap_n) b += vertex_bytes(w->cap_n);
+    b += w->F_cap * sizeof(unsigned) + w->split_cap * sizeof(int) + w->live_cap * sizeof(int) +
+         w->lb_cap * sizeof(unsigned long long) + (size_t)w->st_cap * 2 * sizeof(long long);
+    if (w->plan) b += sizeof(DevPlan);
+    if (w->u_rowptr)
+        b += (w->u_n_cap + 1) * sizeof(int) + std::max(w->u_e_cap, (size_t)1) * sizeof(int) +
+             std::max(w->u_n_cap, (size_t)1) * sizeof(int) + (w->u_g_cap + 1) * sizeof(long long) +
+             w->u_g_cap * sizeof(MultiDesc);
+    return b;
+}
+
+// Upper bound of the device bytes one workspace needs to colour a graph of n vertices
+// and nnz arcs (G > 0: a union of G graphs given to csrcolor_color_multi, whose copy
+// the workspace also holds), for every option except statistics and ordered
+// compaction: the allocations of ensure_capacity, ensure_F, ensure_split, ensure_live
+// and ensure_union at the sizes either drive path asks for.
+size_t ws_bound(long long G, long long n, long long nnz) {
+    const size_t cap = std::max<size_t>((size_t)n, 1024);
+    const size_t e = (size_t)std::max<long long>(nnz, 0);
+    size_t b = sizeof(Ctl) + 2 * sizeof(unsigned long long) + sizeof(DevPlan) + vertex_bytes(cap);
+    b += std::max<size_t>((cap + e) / 4 + 4, 4096) * sizeof(unsigned);      // push flags
+    b += std::max<size_t>(e / 16 + 64, 4096) * sizeof(int);                 // split-row scratch
+    b += std::max<size_t>(e, 4096) * sizeof(int);                           // live lists
+    if (G > 0)
+        b += ((size_t)n + 1) * sizeof(int) + std::max<size_t>(e, 1) * sizeof(int) +
+             std::max<size_t>((size_t)n, 1) * sizeof(int) + ((size_t)G + 1) * sizeof(long long) +
+             (size_t)G * sizeof(MultiDesc);
+    return b;
+}
+
 int ensure_capacity(Workspace* w, size_t n, int st_cap) {
     if (!w->ctl) {
         HIP_TRY(hipMalloc(&w->ctl, sizeof(Ctl)));
@@ -1611,6 +1650,18 @@ void csrcolor_release_workspace(void) {
         w->sz_h = nullptr;
     }
     (void)hipSetDevice(cur);
+}
+
+int64_t csrcolor_workspace_bytes(int32_t G, int64_t n, int64_t nnz) {
+    if (G < 0 || n < 0 || nnz < 0) return CSRCOLOR_EINVAL;
+    return (int64_t)ws_bound(G, n, nnz);
+}
+
+int64_t csrcolor_device_bytes_in_use(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    size_t b = 0;
+    for (auto& kv : g_ws) b += ws_bytes_now(kv.second);
+    return (int64_t)b;
 }
 
 int csrcolor_version(void) { return 100; }

@@ -137,3 +137,16 @@ def test_noalloc_limits_match_header():
     txt = open(HEADER).read()
     assert re.search(r"#define CSRCOLOR_NOALLOC_MAX_N\s+%d\b" % L.NOALLOC_MAX_N, txt)
     assert re.search(r"#define CSRCOLOR_NOALLOC_MAX_NNZ\s+%d\b" % L.NOALLOC_MAX_NNZ, txt)
+
+
+def test_workspace_bytes_query(lib):
+    """The workspace bound grows with the vertices, the arcs and the union copy, and is
+    at least the per-vertex and per-arc arrays the library allocates."""
+    wb = lib.csrcolor_workspace_bytes
+    assert wb(0, -1, 0) == L.EINVAL and wb(-1, 10, 10) == L.EINVAL and wb(0, 10, -5) == L.EINVAL
+    n, m = 1 << 20, 1 << 24
+    base = wb(0, n, m)
+    assert base > 0 and wb(0, n + 4096, m) > base and wb(0, n, m + 4096) > base
+    assert wb(3, n, m) >= base + 4 * (2 * n + m)          # the union's CSR copy and colours
+    assert base >= 55 * n + 5 * m                          # colour state, lists, flags, live lists
+    assert lib.csrcolor_device_bytes_in_use() >= 0

@@ -25,7 +25,7 @@ class OracleBackend(serve.Backend):
         self.lock = threading.Lock()
         self.batches = []
 
-    def upload(self, rowptr, colidx):
+    def upload(self, rowptr, colidx, uploader=0):
         if len(rowptr) - 1 in self.fail_on:
             raise ValueError("bad graph")
         with self.lock:
@@ -137,3 +137,82 @@ def test_failing_request_fails_alone():
 
 def test_footprint_model_monotone():
     assert serve.footprint_bytes(10, 20) < serve.footprint_bytes(11, 20) < serve.footprint_bytes(11, 21)
+
+
+class BatchFailBackend(OracleBackend):
+    """The device rejects any batch holding the graph of `bad_n` vertices (as the library
+    rejects a union with one malformed graph)."""
+
+    def __init__(self, bad_n, **kw):
+        super().__init__(**kw)
+        self.bad_n = bad_n
+
+    def run_batch(self, slot, handles):
+        if any(len(rp) - 1 == self.bad_n for rp, _ in handles):
+            raise RuntimeError("csrcolor status -2: malformed CSR")
+        return super().run_batch(slot, handles)
+
+
+def test_failed_batch_reruns_each_request_alone(oracle_mod):
+    gs = [gg.cycle(20 + i) for i in range(8)]
+    bad = gg.cycle(17)
+    be = BatchFailBackend(17, nslots=1, delay=0.01)
+    with serve.ColoringServer(be, 1 << 40, max_batch=16) as srv:
+        # queued before the scheduler starts: the first batch holds the bad graph too
+        rs = [srv.submit(g.rowptr, g.colidx) for g in gs[:4]]
+        rb = srv.submit(bad.rowptr, bad.colidx)
+        rs += [srv.submit(g.rowptr, g.colidx) for g in gs[4:]]
+        for r in rs + [rb]:
+            assert r.wait(30)
+    assert rb.error and "malformed" in rb.error
+    for g, r in zip(gs, rs):
+        ref = oracle_mod.sgr(g.n, g.rowptr, g.colidx)
+        assert r.error is None and (r.colors == ref.colors).all()
+    assert be.live == 0
+
+
+class SizedBackend(OracleBackend):
+    def workspace_bytes(self, graphs, n, nnz):
+        return 1000 + 7 * n + 3 * nnz + 11 * graphs
+
+
+def test_ledger_reserves_slots_and_charges_requests(oracle_mod):
+    """The slots' workspaces are reserved up front at the size for the batch limits;
+    requests are charged their CSR and output; the total never exceeds the budget and
+    a request above the batch limits is rejected."""
+    gs = _graphs(20, seed=11)
+    be = SizedBackend(nslots=2, delay=0.002)
+    limits = dict(max_batch=4, max_batch_vertices=4000, max_batch_arcs=40000)
+    reserved = 2 * be.workspace_bytes(4, 4000, 40000)
+    budget = reserved + 3 * max(serve.footprint_bytes(g.n, g.nnz) for g in gs)
+    big = gg.erdos_renyi(5000, 10000, 1)        # more vertices than a batch may hold
+    with serve.ColoringServer(be, budget, **limits) as srv:
+        assert srv.reserved_bytes == reserved
+        rb = srv.submit(big.rowptr, big.colidx)
+        reqs, _ = serve.replay(srv, [(g.rowptr, g.colidx) for g in gs], [0.0003 * i for i in range(len(gs))])
+        assert reserved < srv.peak_bytes <= budget
+    assert rb.error and "workspace" in rb.error
+    for g, r in zip(gs, reqs):
+        assert r.error is None
+        assert r.batch_size <= 4
+    with pytest.raises(ValueError):
+        serve.ColoringServer(be, reserved - 1, **limits)
+
+
+def test_small_request_slot(oracle_mod):
+    """With small_arcs set, slot 0 only runs batches led by small requests; every result
+    is still the stand-alone colouring."""
+    class SlotBackend(OracleBackend):
+        def run_batch(self, slot, handles):
+            self.seen = getattr(self, "seen", [])
+            self.seen.append((slot, int(handles[0][1].size)))       # the batch's lead request
+            return super().run_batch(slot, handles)
+    gs = [gg.erdos_renyi(3000, 30000, 1, i) if i % 3 == 0 else gg.cycle(30 + i) for i in range(18)]
+    be = SlotBackend(nslots=2, delay=0.005)
+    with serve.ColoringServer(be, 1 << 40, max_batch=2, small_arcs=1000) as srv:
+        reqs, _ = serve.replay(srv, [(g.rowptr, g.colidx) for g in gs], [0.001 * i for i in range(len(gs))])
+    assert all(lead <= 1000 for slot, lead in be.seen if slot == 0)
+    assert any(slot == 0 for slot, _ in be.seen) and any(lead > 1000 for _, lead in be.seen)
+    for g, r in zip(gs, reqs):
+        ref = oracle_mod.sgr(g.n, g.rowptr, g.colidx)
+        assert r.error is None and (r.colors == ref.colors).all()
