@@ -741,7 +741,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     const int nchunk = w->ctl_h->hchunks;
     // live lists: the vertices of degree > 61 scan lists of their uncoloured lower
     // neighbours (id rule, worklist SGR only)
-    const bool use_live = J.opt.live && J.opt.rule == 0 && J.opt.algo == CSRCOLOR_ALGO_SGR &&
+    const bool use_live = J.opt.live && J.opt.rule <= 1 && J.opt.algo == CSRCOLOR_ALGO_SGR &&
                           hist[NTILE] + hist[NTILE + 1] + hist[BSPLIT] > 0;
     // with live lists the chunk records come first (16-byte aligned)
     const size_t recs = use_live ? 8 * (size_t)nchunk : 0;
@@ -764,15 +764,16 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     int* settled = hubflags + (size_t)nhub * (HW + 4) + (use_live ? 2 * (size_t)nchunk : 0);
     if (use_live && (rc = ensure_live(w, std::max<size_t>((size_t)w->ctl_h->nnz, 1)))) return rc;
 
-    // conflict hints serve the id rule (the degree rule would need the neighbour's degree too)
-    int* hint = (J.opt.hints && J.opt.rule == 0) ? w->hint : nullptr;
+    // conflict hints and live lists serve both rules (a hint or list entry beat the vertex
+    // when it was recorded, and ids and degrees never change); wake flags the id rule only
+    int* hint = (J.opt.hints && J.opt.rule <= 1) ? w->hint : nullptr;
     // wake flags need the id rule's hints, push FirstFit and the host loop; ordered
     // compaction is a property of the full worklists they replace
     // auto: the sleeping vertices are the short ones; where long rows hold most arcs the
     // full worklist rounds measured faster (R-MAT: 66 vs 78 ms at scale 23)
     const bool wake_wanted = J.opt.wake > 0 || (J.opt.wake == 0 && w->ctl_h->bigarcs * 10 < w->ctl_h->nnz);
     // (colour words keep BIG at bit 30, so colours must stay below 2^30)
-    const bool use_wake = wake_wanted && hint && J.opt.pushff && J.opt.algo == CSRCOLOR_ALGO_SGR &&
+    const bool use_wake = wake_wanted && hint && J.opt.rule == 0 && J.opt.pushff && J.opt.algo == CSRCOLOR_ALGO_SGR &&
                           J.opt.mode == CSRCOLOR_MODE_LOOP && !J.opt.ordered && J.maxdeg < CMASK - 1;
     const bool longrows = hist[NTILE] + hist[NTILE + 1] + hist[BSPLIT] > 0;
     J.wake = use_wake;
@@ -1088,7 +1089,7 @@ int enqueue_device(Workspace* w, Job& J, const long long* voff, int G, int* ncol
     t.F = w->F;
     t.dirty = w->dirty;
     t.rule = o.rule;
-    t.hint = (o.hints && o.rule == 0) ? w->hint : nullptr;
+    t.hint = (o.hints && o.rule <= 1) ? w->hint : nullptr;
     t.live = w->live;
     t.llen = w->llen;
     t.lpos = w->lpos;
@@ -1105,7 +1106,7 @@ int enqueue_device(Workspace* w, Job& J, const long long* voff, int G, int* ncol
     c.split = w->split;
     c.lb1 = lb;
     c.lb1_ints = lb ? 2 * NB * r1blocks : 0;
-    c.want_live = o.live && o.rule == 0 && w->live != nullptr;
+    c.want_live = o.live && o.rule <= 1 && w->live != nullptr;
 
     T.run(0, [&] { k_init<<<1, WG, 0, st>>>(w->ctl); });
     const int vblocks = (int)std::min<long long>(((long long)n + WG - 1) / WG, (long long)cus * 4);

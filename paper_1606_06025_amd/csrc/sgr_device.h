@@ -401,13 +401,14 @@ __device__ __forceinline__ int tentative(const RoundArgs& a, int v) {
 // Does the remembered neighbour of worklist vertex v still requeue it?  A neighbour
 // that settled in an earlier round cannot hold v's tentative colour (FirstFit excluded
 // it), so an equal colour part means a worklist neighbour of this round that beats v:
-// the same verdict the full scan would reach.
+// the same verdict the full scan would reach.  (The hint was recorded because it beat
+// v, and neither ids nor degrees change, so under either rule it still beats v.)
 // With wake flags the hint of a vertex of at most WAKE_DEG arcs carries FLAG when the
 // neighbour has more arcs (no hint is -1).
 __device__ __forceinline__ bool hint_hit(const RoundArgs& a, int v, int cv) {
     if (!a.hint) return false;
     const int h = a.hint[v];
-    return h != -1 && (h & IDMASK) < v && (a.X[h & IDMASK] & CMASK) == cv;
+    return h != -1 && (a.rule != 0 || (h & IDMASK) < v) && (a.X[h & IDMASK] & CMASK) == cv;
 }
 
 // Is worklist vertex v (tentative colour cv, degree dv) requeued because of row entry

@@ -880,7 +880,7 @@ __device__ __forceinline__ void detect_tiles(const RoundArgs& a, const int* list
             for (int u = 0; u < 2; ++u) {
                 // the remembered neighbour still requeues v (see hint_hit)
                 const int h = h_l[u];
-                hinted_l[u] = h >= 0 && h < v_l[u] && (a.X[h] & CMASK) == cv_l[u];
+                hinted_l[u] = h >= 0 && (a.rule != 0 || h < v_l[u]) && (a.X[h] & CMASK) == cv_l[u];
             }
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
@@ -1019,24 +1019,31 @@ __device__ __forceinline__ void detect_lanes(const RoundArgs& a, const int* list
 // list and a resume position per chunk.
 // ---------------------------------------------------------------------------
 
+// Whether row entry w beats v (degree dv) under the round's rule: a lower id (id rule),
+// or a larger degree, the lower id on equal degree (degree rule).
+__device__ __forceinline__ bool beats_v(const RoundArgs& a, int w, int v, int dv) {
+    return w != v && beats(a.rule, a.rowptr, w, v, dv);
+}
+
 // Scan step: reads the entries of src[beg, end) in quad q of the range, tests them
-// against v and returns the lower neighbours still uncoloured in keep/w.  `row`: the
-// entries come from v's row (for sorted rows an entry >= v ends the lower part).
+// against v (degree dv) and returns the neighbours that beat v and are still
+// uncoloured in keep/w.  `row`: the entries come from v's row (under the id rule, for
+// sorted rows an entry >= v ends the lower part); list entries beat v already.
 __device__ __forceinline__ void live_step(const RoundArgs& a, const int* src, int beg, int end, int q, int v,
-                                          int cv, bool row, int w[4], unsigned& keep, bool& hit, bool& stop,
-                                          int hf) {
+                                          int dv, int cv, bool row, int w[4], unsigned& keep, bool& hit,
+                                          bool& stop, int hf) {
     load_quad(src, a.nnz, beg, end, q, w);
     keep = 0;
     int found = -1;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         if (w[k] < 0) continue;
-        if (w[k] < v) {
+        if (!row || beats_v(a, w[k], v, dv)) {
             const int x = a.X[w[k]];
             if ((x & CMASK) == cv) found = w[k];
             if (x <= 0) keep |= 1u << k;
         } else {
-            stop |= row && a.sorted;       // sorted rows: no lower entries further on
+            stop |= a.rule == 0 && w[k] >= v && a.sorted;   // sorted rows: no lower entries further on
         }
     }
     if (found >= 0) {
@@ -1045,13 +1052,14 @@ __device__ __forceinline__ void live_step(const RoundArgs& a, const int* src, in
     }
 }
 
-// The whole wavefront runs the conflict test of v (tentative colour cv) over the
-// range [rb, re) of its row (the whole row, or a chunk of a split row): its live list
-// live[rb, rb + len), then the unexamined entries colidx[p, re) (len < 0: nothing
-// examined yet, i.e. len = 0 and p = rb).  Stores the new length and resume position
-// at *lenp and *posp; returns whether a conflict was found.  Every lane must call.
-__device__ __forceinline__ bool live_test_wave(const RoundArgs& a, int v, int cv, int rb, int re, int len, int p,
-                                               int* lenp, int* posp, int hf) {
+// The whole wavefront runs the conflict test of v (tentative colour cv, degree dv)
+// over the range [rb, re) of its row (the whole row, or a chunk of a split row): its
+// live list live[rb, rb + len), then the unexamined entries colidx[p, re) (len < 0:
+// nothing examined yet, i.e. len = 0 and p = rb).  Stores the new length and resume
+// position at *lenp and *posp; returns whether a conflict was found.  Every lane must
+// call.
+__device__ __forceinline__ bool live_test_wave(const RoundArgs& a, int v, int dv, int cv, int rb, int re, int len,
+                                               int p, int* lenp, int* posp, int hf) {
     const int lane = __lane_id();
     if (len < 0) {
         len = 0;
@@ -1067,7 +1075,7 @@ __device__ __forceinline__ bool live_test_wave(const RoundArgs& a, int v, int cv
             int w[4];
             unsigned keep;
             bool hit = false, stop = false;
-            live_step(a, a.live, rb, send, q0 + lane, v, cv, false, w, keep, hit, stop, hf);
+            live_step(a, a.live, rb, send, q0 + lane, v, dv, cv, false, w, keep, hit, stop, hf);
             int tot;
             int pos = rb + K + wave_excl(__popc(keep), tot);
             const int qs = rb + quad_end(a.live, rb, q0 + lane);   // position of w[0]
@@ -1097,7 +1105,7 @@ __device__ __forceinline__ bool live_test_wave(const RoundArgs& a, int v, int cv
             int w[4];
             unsigned keep;
             bool hit = false, stop = false;
-            live_step(a, a.colidx, p, re, q0 + lane, v, cv, true, w, keep, hit, stop, hf);
+            live_step(a, a.colidx, p, re, q0 + lane, v, dv, cv, true, w, keep, hit, stop, hf);
             int tot;
             int pos = rb + K + wave_excl(__popc(keep), tot);
 #pragma unroll
@@ -1127,8 +1135,8 @@ __device__ __forceinline__ bool live_test_wave(const RoundArgs& a, int v, int cv
 // empty.  Reads only.  Returns 1 if that quad holds a conflicting neighbour, -1 if
 // nothing is left to examine (no lower uncoloured neighbour remains: no conflict), 0
 // otherwise (the full test decides).
-__device__ __forceinline__ int live_probe(const RoundArgs& a, int v, int cv, int rb, int re, int len, int p,
-                                          int hf) {
+__device__ __forceinline__ int live_probe(const RoundArgs& a, int v, int dv, int cv, int rb, int re, int len,
+                                          int p, int hf) {
     if (len < 0) {
         len = 0;
         p = rb;
@@ -1140,7 +1148,7 @@ __device__ __forceinline__ int live_probe(const RoundArgs& a, int v, int cv, int
     int found = -1;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        if (w[k] >= 0 && w[k] < v && (a.X[w[k]] & CMASK) == cv) found = w[k];
+        if (w[k] >= 0 && (len > 0 || beats_v(a, w[k], v, dv)) && (a.X[w[k]] & CMASK) == cv) found = w[k];
     if (found < 0) return 0;
     if (a.hint) a.hint[v] = found | hf;
     return 1;
@@ -1391,7 +1399,8 @@ __device__ __forceinline__ void detect_stream(const RoundArgs& a, const int* lis
                     const int j = __ffsll((long long)todo) - 1;
                     todo &= todo - 1;
                     const int vj = __builtin_amdgcn_readlane(vd, j);
-                    const bool l = live_test_wave(a, vj, __builtin_amdgcn_readlane(cd, j), __builtin_amdgcn_readlane(bd, j),
+                    const bool l = live_test_wave(a, vj, __builtin_amdgcn_readlane(ed, j) - __builtin_amdgcn_readlane(bd, j),
+                                                  __builtin_amdgcn_readlane(cd, j), __builtin_amdgcn_readlane(bd, j),
                                                   __builtin_amdgcn_readlane(ed, j), __builtin_amdgcn_readlane(ld, j),
                                                   __builtin_amdgcn_readlane(pd, j), &a.llen[vj], &a.lpos[vj], hf);
                     if (lane == j) lost_l = l;
@@ -1437,7 +1446,7 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
             if (a.live && v_l >= 0 && !lost_l) {
                 // every lane looks at the first quad of its own vertex's list (or unexamined
                 // row): most tests end there, the rest get the whole wavefront below
-                const int pr = live_probe(a, v_l, cv_l, beg_l, end_l, len_l, pos_l, W ? a.hflag : 0);
+                const int pr = live_probe(a, v_l, end_l - beg_l, cv_l, beg_l, end_l, len_l, pos_l, W ? a.hflag : 0);
                 lost_l = pr > 0;
                 done_l = pr != 0;
             }
@@ -1451,7 +1460,7 @@ __device__ __forceinline__ void detect_wave(const RoundArgs& a, const int* list,
                 const int end = __builtin_amdgcn_readlane(end_l, j);
                 const int cv = __builtin_amdgcn_readlane(cv_l, j);
                 if (a.live) {
-                    const bool lost = live_test_wave(a, v, cv, beg, end, __builtin_amdgcn_readlane(len_l, j),
+                    const bool lost = live_test_wave(a, v, end - beg, cv, beg, end, __builtin_amdgcn_readlane(len_l, j),
                                                      __builtin_amdgcn_readlane(pos_l, j), &a.llen[v], &a.lpos[v],
                                                      W ? a.hflag : 0);
                     if (lane == j) lost_l = lost;
@@ -1667,7 +1676,7 @@ __device__ __forceinline__ void detect_split_wave(const RoundArgs& a, const int*
         const int nch = split_chunks(re - rb);
         const int beg = rb + k * SPLIT_CH;
         const int end = min(beg + SPLIT_CH, re);
-        const int h = (hh != -1 && (hh & IDMASK) < v) ? (hh & IDMASK) : -1;
+        const int h = (hh != -1 && (a.rule != 0 || (hh & IDMASK) < v)) ? (hh & IDMASK) : -1;
         const bool fresh = cl < 0;                       // nothing examined yet
         const int len = fresh ? 0 : cl;
         const int pos = fresh ? beg : cp;
@@ -1682,15 +1691,21 @@ __device__ __forceinline__ void detect_split_wave(const RoundArgs& a, const int*
         }
         bool hit = !done && h >= 0 && (hx & CMASK) == cv;
         int g[4] = {0, 0, 0, 0};
+        // entries that beat v: every list entry; of the row, by the rule (degree rule:
+        // the neighbours' row bounds are read with their colours)
+        bool bt[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bt[q] = w[q] >= 0 && (len > 0 || (a.rule == 0 ? w[q] < v : w[q] != v));
         if (!done && !hit) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) g[q] = (w[q] >= 0 && w[q] < v) ? a.X[w[q]] : 0;
+            for (int q = 0; q < 4; ++q) g[q] = bt[q] ? a.X[w[q]] : 0;
         }
         if (!done && !hit) {
             int found = -1;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                if (w[q] >= 0 && w[q] < v && (g[q] & CMASK) == cv) found = w[q];
+                if (bt[q] && (g[q] & CMASK) == cv && (len > 0 || a.rule == 0 || beats_v(a, w[q], v, re - rb)))
+                    found = w[q];
             if (found >= 0) {
                 hit = true;
                 if (a.hint) a.hint[v] = found | hf;
@@ -1708,7 +1723,8 @@ __device__ __forceinline__ void detect_split_wave(const RoundArgs& a, const int*
             if (__builtin_amdgcn_readfirstlane(sk)) continue;
             const int vj = __builtin_amdgcn_readlane(v, jj);
             const int cij = __builtin_amdgcn_readlane(ci, jj);
-            const bool hj = live_test_wave(a, vj, __builtin_amdgcn_readlane(cv, jj), __builtin_amdgcn_readlane(beg, jj),
+            const bool hj = live_test_wave(a, vj, __builtin_amdgcn_readlane(re, jj) - __builtin_amdgcn_readlane(rb, jj),
+                                           __builtin_amdgcn_readlane(cv, jj), __builtin_amdgcn_readlane(beg, jj),
                                            __builtin_amdgcn_readlane(end, jj), __builtin_amdgcn_readlane(cl, jj),
                                            __builtin_amdgcn_readlane(cp, jj), &a.clen[cij], &a.cpos[cij], hf);
             if (lane == jj) hit = hj;
@@ -1791,7 +1807,7 @@ __device__ __forceinline__ void detect_phase(const RoundArgs& a, RoundLds& s, in
     }
     if (b < NTILE && a.rule == 0 && !ust && !(a.lane_mode_detect >> 4 & 1)) {
         detect_stream<W, false>(a, list, lo, hi, s, outl, cnt_out, cmax, ust, j);
-    } else if ((b == NTILE || b == NTILE + 1) && a.live && !ust && !(a.lane_mode_detect >> 5 & 1) &&
+    } else if ((b == NTILE || b == NTILE + 1) && a.live && a.rule == 0 && !ust && !(a.lane_mode_detect >> 5 & 1) &&
                hi - lo >= 64 * WAVES) {
         // long rows, at least 64 per wavefront (the early rounds, whose lists are new and
         // whose conflicts come early): lane-streamed; fewer, with longer lists that the
