@@ -186,12 +186,59 @@ __global__ __launch_bounds__(WG) void k_check_symmetric(int n, const int* __rest
 
 // ---------------------------------------------------------------------------
 // Round 1 shortcut.  With an all-zero snapshot FirstFit gives colour 1 to every
-// vertex, so v is requeued iff it has a neighbour w < v.  For sorted rows that is
-// one test of the row's first entry.  Winners are final with colour 1; losers are
-// pushed to the worklist of their degree bucket.
+// vertex, so v is requeued iff it has a neighbour that beats it: under the id rule
+// a neighbour w < v, which for sorted rows is one test of the row's first entry.
+// Otherwise the row is scanned up to its first beater: by one lane for rows of at
+// most R1_LANE arcs, by the wavefront for rows of at most R1_WAVE arcs and by the
+// whole workgroup beyond (a winning hub reads its whole row).  Winners are final
+// with colour 1; losers are pushed to the worklist of their degree bucket.
 // One workgroup handles 4*WG consecutive vertices and compacts them per bucket in
 // LDS, so there are at most NB global atomics per workgroup.
 // ---------------------------------------------------------------------------
+constexpr int R1_LANE = 64;
+constexpr int R1_WAVE = 4096;
+constexpr int R1_NONE = 0x7fffffff;
+
+// First entry of row [beg, end) of v that beats v, scanned by one lane, four entries
+// in flight; -1 if none.
+__device__ __forceinline__ int first_beater_lane(int rule, const int* __restrict__ rowptr,
+                                                 const int* __restrict__ colidx, int v, int beg, int end) {
+    const int dv = end - beg;
+    for (int e = beg; e < end; e += 4) {
+        int w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k] = e + k < end ? colidx[e + k] : -1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (w[k] >= 0 && w[k] != v && beats(rule, rowptr, w[k], v, dv)) return w[k];
+    }
+    return -1;
+}
+
+// The same scanned by the wavefront, 256 entries a step (entry beg + 64k + lane in
+// step slot k); every lane returns the first beater in row order, or -1.
+__device__ __forceinline__ int first_beater_wave(int rule, const int* __restrict__ rowptr,
+                                                 const int* __restrict__ colidx, int v, int beg, int end) {
+    const int lane = __lane_id();
+    const int dv = end - beg;
+    for (int base = beg; base < end; base += 4 * 64) {
+        int w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int e = base + k * 64 + lane;
+            w[k] = e < end ? colidx[e] : -1;
+        }
+        bool b[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b[k] = w[k] >= 0 && w[k] != v && beats(rule, rowptr, w[k], v, dv);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const unsigned long long m = __ballot(b[k]);
+            if (m) return __shfl(w[k], __ffsll((long long)m) - 1);
+        }
+    }
+    return -1;
+}
 __device__ __forceinline__ void round1_body(int n, const int* __restrict__ rowptr,
                                             const int* __restrict__ colidx, int* X, int* out,
                                             int* wl1, Ctl* ctl, int sorted, int twave, int tsplit,
@@ -232,8 +279,19 @@ __device__ __forceinline__ void round1_body(int n, const int* __restrict__ rowpt
     // bucket's run is placed after the runs of the lower tickets (look-back), so every
     // worklist segment starts in ascending id order
     __shared__ int ticket;
-    if (threadIdx.x == 0) ticket = lb1 ? atomicAdd(&ctl->tk1, 1) : (int)blockIdx.x;
+    // rows scanned by the whole workgroup: owners (thread, vertex, row bounds) per pass,
+    // and three rotating slots for the first beater's row position of each step
+    __shared__ int r1cnt[ITER];
+    __shared__ int r1own[WG][4];
+    __shared__ int r1pos[3];
+    if (threadIdx.x == 0) {
+        ticket = lb1 ? atomicAdd(&ctl->tk1, 1) : (int)blockIdx.x;
+        for (int i = 0; i < ITER; ++i) r1cnt[i] = 0;
+        for (int i = 0; i < 3; ++i) r1pos[i] = R1_NONE;
+    }
     __syncthreads();
+    const bool scan_rows = !jp && !(rule == 0 && sorted);
+    int slot = 0;
     const int unit = ticket;
     const long long chunk0 = (long long)unit * (ITER * WG);
     for (int it = 0; it < ITER; ++it) {
@@ -244,28 +302,84 @@ __device__ __forceinline__ void round1_body(int n, const int* __restrict__ rowpt
         bool winpush = false;   // push mode: a round-1 winner with neighbours
         int bkt = -1;
         int wbeg = 0, wend = 0;
+        int beg = 0, end = 0;
+        int by = -1;   // the neighbour that beat v (conflict hint for the next rounds)
+        bool pend = false;
         if (vv < n) {
             const int v = (int)vv;
-            const int beg = rowptr[v], end = rowptr[v + 1];
-            int by = -1;   // the neighbour that beat v (conflict hint for the next rounds)
+            beg = rowptr[v];
+            end = rowptr[v + 1];
             if (jp) {
                 lose = end > beg;
             } else if (end > beg) {
-                if (rule == 0 && sorted) {
+                if (!scan_rows) {
                     by = colidx[beg];
                     lose = by < v;
-                } else {
+                } else if (end - beg <= R1_LANE) {
                     // all tentative colours are 1: requeued iff some neighbour beats v
-                    for (int e = beg; e < end; ++e) {
-                        const int w = colidx[e];
-                        if (w != v && beats(rule, rowptr, w, v, end - beg)) {
-                            lose = true;
-                            by = w;
-                            break;
-                        }
-                    }
+                    by = first_beater_lane(rule, rowptr, colidx, v, beg, end);
+                    lose = by >= 0;
+                } else {
+                    pend = true;
                 }
             }
+        }
+        if (scan_rows) {
+            // longer rows: the wavefront scans each in turn, the longest the workgroup
+            unsigned long long pm = __ballot(pend && end - beg <= R1_WAVE);
+            while (pm) {
+                const int L = __ffsll((long long)pm) - 1;
+                pm &= pm - 1;
+                const int w = first_beater_wave(rule, rowptr, colidx, __shfl((int)vv, L), __shfl(beg, L),
+                                                __shfl(end, L));
+                if (lane == L) {
+                    by = w;
+                    lose = w >= 0;
+                    pend = false;
+                }
+            }
+            if (pend) {
+                const int s = atomicAdd(&r1cnt[it], 1);
+                r1own[s][0] = threadIdx.x;
+                r1own[s][1] = (int)vv;
+                r1own[s][2] = beg;
+                r1own[s][3] = end;
+            }
+            __syncthreads();
+            const int nbig = r1cnt[it];
+            for (int j = 0; j < nbig; ++j) {
+                const int own = r1own[j][0], rv = r1own[j][1], rb = r1own[j][2], re = r1own[j][3];
+                int fp = R1_NONE;
+                for (int base = rb; base < re; base += 4 * WG) {
+                    int w[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int e = base + k * WG + threadIdx.x;
+                        w[k] = e < re ? colidx[e] : -1;
+                    }
+                    int mine = R1_NONE;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (mine == R1_NONE && w[k] >= 0 && w[k] != rv && beats(rule, rowptr, w[k], rv, re - rb))
+                            mine = base + k * WG + threadIdx.x - rb;
+                    if (mine != R1_NONE) atomicMin(&r1pos[slot], mine);
+                    // the next step's slot was last read before the previous barrier
+                    const int nxt = slot == 2 ? 0 : slot + 1;
+                    if (threadIdx.x == 0) r1pos[nxt] = R1_NONE;
+                    __syncthreads();
+                    fp = r1pos[slot];
+                    slot = nxt;
+                    if (fp != R1_NONE) break;
+                }
+                if ((int)threadIdx.x == own) {
+                    by = fp != R1_NONE ? colidx[rb + fp] : -1;
+                    lose = by >= 0;
+                    pend = false;
+                }
+            }
+        }
+        if (vv < n) {
+            const int v = (int)vv;
             if (hint && rflag) {
                 // wake flags: the hint of a short loser names its class, a long loser's hint
                 // carries FLAG, a winner's is cleared: a hint without FLAG names a sleeper

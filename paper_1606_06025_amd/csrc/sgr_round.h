@@ -1646,13 +1646,15 @@ __device__ __forceinline__ void detect_split_wave(const RoundArgs& a, const int*
     const int lane = __lane_id();
     const int nw = nbk * WAVES;                      // wavefronts of the bucket
     const int gw = j * WAVES + (threadIdx.x >> 6);   // this one's index among them
-    // chunks per batch: spread over every wavefront of the bucket, at most 64 (most
-    // chunks need no scan, but the ones that do are scanned one after another)
-    const int B = min(64, max(1, (nchunks + nw - 1) / nw));
+    // chunks per wavefront: an even share, at most 64 per batch (most chunks need no
+    // scan, but the ones that do are scanned one after another).  Wavefront gw takes
+    // the chunks s * nw + gw, which spreads the chunks of each hub over the wavefronts
+    // (a hub that nothing beats scans every chunk whole)
+    const int per = (nchunks + nw - 1) / nw;
     const int hf = W ? a.hflag : 0;
-    for (int t0 = gw * B; t0 < nchunks; t0 += nw * B) {
-        const int t = t0 + lane;
-        const bool on = lane < B && t < nchunks;
+    for (int s0 = 0; s0 < per; s0 += 64) {
+        const int t = (s0 + lane) * nw + gw;
+        const bool on = s0 + lane < per && t < nchunks;
         int p = 0, v = 0, k = 0, ci = 0;
         if (on) {
             const int4 r = crec[t];
