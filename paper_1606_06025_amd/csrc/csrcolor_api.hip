@@ -470,12 +470,12 @@ Options parse_opts(const csrcolor_opts* o) {
 // work (plan_cost), never more workgroups than it has units for.
 void make_plan(const int ub[NB], int budget, int boff[NB + 1]) {
     double tot = 0;
-    for (int b = 0; b < NB; ++b) tot += (double)ub[b] * plan_cost(b);
+    for (int b = 0; b < NB; ++b) tot += (double)ub[b] * plan_cost(b, 1);
     boff[0] = 0;
     for (int b = 0; b < NB; ++b) {
         int nb = 0;
         if (ub[b] > 0) {
-            const double share = tot > 0 ? ub[b] * plan_cost(b) / tot : 1.0;
+            const double share = tot > 0 ? ub[b] * plan_cost(b, 1) / tot : 1.0;
             nb = std::max(1, (int)(share * budget + 0.5));
             const int useful = (ub[b] + plan_units_per_block(b) - 1) / plan_units_per_block(b);
             nb = std::min(nb, std::max(useful, 1));

@@ -288,7 +288,8 @@ struct Ctl {
     int tk[8];          // ordered compaction: conflict-test tickets per bucket (reset by FirstFit)
     int tk1;            // ordered compaction: round-1 tickets
     int nsettled;       // push tasks (split row, chunk) of the rows that settled this round
-    int pad[2];
+    int pround;         // FirstFit phases run so far (the 0-based index of the current round)
+    int pad[1];
     long long bigarcs;  // arcs of the rows longer than WAKE_DEG
     // device-wide barrier of the persistent mode, each counter on its own 128-byte line
     int bar[8][32];

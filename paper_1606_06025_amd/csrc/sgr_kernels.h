@@ -525,7 +525,8 @@ __global__ __launch_bounds__(WG, 6) void k_detect(RoundArgs a) {
         if (a.dev_plan) {
             int cnt[NB];
             queue_sizes(a.ctl, a.par_in, cnt);
-            device_plan(cnt, gridDim.x, boff);
+            // the round index: counted by the FirstFit phase, so it is fixed here
+            device_plan(cnt, gridDim.x, boff, a.ctl->pround);
         } else {
             for (int k = 0; k <= NB; ++k) boff[k] = a.boff[k];
         }

@@ -63,13 +63,17 @@ __device__ __forceinline__ void block_bucket(const int* boff, int bid, int& b, i
 // Per-bucket cost weights (time per queued unit: a worklist vertex, or a chunk of a
 // split row) and the most blocks a bucket can use per unit, shared by the host plan
 // and the device plan.  The weights follow the block time per unit measured on MI355X
-// for the default tests (R-MAT scale 23, rounds 2 to 300: about 0.25 block-us per
-// vertex of at most 61 arcs, 0.5-1 per vertex of 62-1024 arcs, 2-3 per vertex of
-// 1025-2048 arcs, 1.6-4 per 2048-arc chunk): live lists and hints make the tests cost
-// per vertex rather than per arc.
-__host__ __device__ inline int plan_cost(int b) {
-    constexpr int c[NB] = {50, 60, 60, 60, 200, 600, 450};
-    return c[b];
+// on R-MAT scale 23: live lists and hints make the tests cost per vertex rather than
+// per arc.  In the first rounds (0-based round index r <= 2) every long row and chunk
+// is read for the first time (vertex of at most 61 arcs : 62-1024 arcs : 1025-2048
+// arcs : 2048-arc chunk about 0.16 : 0.6 : 1.3-2.3 : 1.5 block-us); from r = 10 on
+// the lists are built and a chunk costs about what a wavefront-bucket vertex does
+// (1 : 1.8 : 1); in between the weights move linearly.
+__host__ __device__ inline int plan_cost(int b, int r) {
+    constexpr int fresh[NB] = {50, 60, 60, 60, 200, 600, 450};
+    constexpr int steady[NB] = {50, 60, 60, 60, 200, 380, 210};
+    const int f = r <= 2 ? 8 : r >= 10 ? 0 : 10 - r;     // eighths of the way back to fresh
+    return steady[b] + (fresh[b] - steady[b]) * f / 8;
 }
 __host__ __device__ inline int plan_units_per_block(int b) {
     constexpr int u[NB] = {WG, WG, WG, WG, WAVES, WAVES, WAVES};
@@ -77,14 +81,14 @@ __host__ __device__ inline int plan_units_per_block(int b) {
 }
 
 // Partition of nblk blocks over the buckets for queue sizes cnt[] (chunks for the
-// split bucket): one block per non-empty bucket, the rest in proportion to the
-// estimated arc work, capped by what a bucket can use.  Integer arithmetic only,
+// split bucket) in 0-based round r: one block per non-empty bucket, the rest in
+// proportion to the estimated work, capped by what a bucket can use.  Integer arithmetic only,
 // so every block that evaluates it gets the same answer.
-__device__ __forceinline__ void device_plan(const int* cnt, int nblk, int* boff) {
+__device__ __forceinline__ void device_plan(const int* cnt, int nblk, int* boff, int r) {
     long long tot = 0;
     int nz = 0;
     for (int b = 0; b < NB; ++b) {
-        tot += (long long)cnt[b] * plan_cost(b);
+        tot += (long long)cnt[b] * plan_cost(b, r);
         nz += cnt[b] > 0;
     }
     const long long rem = nblk > nz ? nblk - nz : 0;
@@ -92,7 +96,7 @@ __device__ __forceinline__ void device_plan(const int* cnt, int nblk, int* boff)
     for (int b = 0; b < NB; ++b) {
         int nb = 0;
         if (cnt[b] > 0) {
-            const long long extra = tot > 0 ? rem * cnt[b] * plan_cost(b) / tot : 0;
+            const long long extra = tot > 0 ? rem * cnt[b] * plan_cost(b, r) / tot : 0;
             const int useful = (cnt[b] + plan_units_per_block(b) - 1) / plan_units_per_block(b);
             nb = (int)min((long long)useful, 1 + extra);
         }
@@ -718,6 +722,7 @@ __device__ __forceinline__ void assign_phase(const RoundArgs& a, RoundLds& s, in
         }
         a.ctl->ccnt[a.par_out] = 0;
         a.ctl->nsettled = 0;
+        a.ctl->pround += 1;
     }
     // the conflict test of this round uses one look-back status word per block of its
     // grid (the FirstFit grid may be smaller)
@@ -768,7 +773,7 @@ __global__ __launch_bounds__(WG) void k_assign(RoundArgs a) {
         if (a.dev_plan) {
             int cnt[NB];
             queue_sizes(a.ctl, a.par_in, cnt);
-            device_plan(cnt, gridDim.x, boff);
+            device_plan(cnt, gridDim.x, boff, 1);
         } else {
             for (int k = 0; k <= NB; ++k) boff[k] = a.boff[k];
         }
@@ -1936,7 +1941,7 @@ __device__ __forceinline__ void grid_sync(Ctl* ctl, int& gen, long long limit) {
 // in push mode the split-hub push phase with its barrier.  Returns false when every
 // queue was empty (the colouring is complete) or a barrier timed out.
 __device__ __forceinline__ bool persistent_round(const RoundArgs& a, RoundLds& s, int* boff, int& total,
-                                                 int& gen, int& cmax, long long limit) {
+                                                 int& gen, int& cmax, long long limit, int r) {
     if (threadIdx.x == 0) {
         int cnt[NB];
         for (int b = 0; b < NB; ++b) cnt[b] = ld_agent(&a.ctl->cnt[a.par_in][b]);
@@ -1944,7 +1949,7 @@ __device__ __forceinline__ bool persistent_round(const RoundArgs& a, RoundLds& s
         int t = 0;
         for (int b = 0; b < NB; ++b) t += cnt[b];
         total = (ld_agent(&a.ctl->err) & ERR_BARRIER) ? -1 : t;
-        device_plan(cnt, gridDim.x, boff);
+        device_plan(cnt, gridDim.x, boff, r);
     }
     __syncthreads();
     if (total <= 0) {
@@ -1975,8 +1980,8 @@ __device__ __forceinline__ void persistent_rounds(const RoundArgs& a_odd, const 
     int gen = 0;
     int cmax = 0;
     for (int r = first_round; r < max_rounds; ++r) {
-        const bool more = (r & 1) ? persistent_round(a_odd, s, boff, total, gen, cmax, limit)
-                                  : persistent_round(a_even, s, boff, total, gen, cmax, limit);
+        const bool more = (r & 1) ? persistent_round(a_odd, s, boff, total, gen, cmax, limit, r)
+                                  : persistent_round(a_even, s, boff, total, gen, cmax, limit, r);
         if (!more) break;
     }
     cmax = block_max(cmax, s.red);

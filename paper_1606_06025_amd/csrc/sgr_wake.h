@@ -178,6 +178,7 @@ __global__ __launch_bounds__(WG) void k_wassign(RoundArgs a) {
         }
         a.ctl->ccnt[a.par_out] = 0;
         a.ctl->nsettled = 0;
+        a.ctl->pround += 1;
     }
     const long long nwv = (long long)gridDim.x * WAVES;
     const int k = a.vpw / 64;
