@@ -515,9 +515,11 @@ def bench_serve(args, dev) -> int:
     limits = dict(max_batch=args.max_batch, max_batch_vertices=2 * max(g.n for g in graphs),
                   max_batch_arcs=2 * max(g.nnz for g in graphs))
     ledger = {}
+    sopts = dict(mode=args.mode, blocks_per_cu=args.blocks_per_cu, sync_every=args.sync_every)
+    opts = api.make_opts(**sopts) if any(sopts.values()) else None
 
     def run(arrivals):
-        be = serve.HipBackend(nslots=args.slots)
+        be = serve.HipBackend(nslots=args.slots, opts=opts)
         with serve.ColoringServer(be, budget, **limits) as srv:
             rr, wall = serve.replay(srv, pairs, arrivals)
             peak = srv.peak_bytes
@@ -551,6 +553,17 @@ def bench_serve(args, dev) -> int:
         loads[f"{int(frac * 100)}pct"] = {"qps": q, "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"],
                                           "arcs_per_s": total_arcs / wall_q}
         log(f"load {frac:.0%} ({q:.1f} req/s): p50 {s['p50_ms']:.2f} ms, p99 {s['p99_ms']:.2f} ms")
+        # the slowest requests and where their time went
+        for r in sorted(rr_q, key=lambda r: -r.latency)[:6]:
+            log(f"  slow: {r.nnz} arcs, latency {r.latency * 1e3:.1f} ms = admit {(r.admitted - r.arrival) * 1e3:.1f}"
+                f" + upload {(r.uploaded - r.admitted) * 1e3:.1f} + wait {(r.started - r.uploaded) * 1e3:.1f}"
+                f" + batch {(r.done_time - r.started) * 1e3:.1f} (batch of {r.batch_size})")
+        for lo, hi in ((0, 1e6), (1e6, 1e7), (1e7, 1e12)):
+            sub = [r for r in rr_q if lo <= r.nnz < hi]
+            if sub:
+                ss = serve.latency_summary(sub)
+                log(f"  {int(lo)}..{int(hi)} arcs: {len(sub)} requests, p50 {ss['p50_ms']:.2f} ms, "
+                    f"p99 {ss['p99_ms']:.2f} ms")
     # one graph per launch on one stream: (a) the whole request path of each graph in
     # turn (upload, colour, download), which is what the server does for every request;
     # (b) graphs already resident, colouring only

@@ -1116,7 +1116,7 @@ int enqueue_device(Workspace* w, Job& J, const long long* voff, int G, int* ncol
     T.kern(0, k_validate_rows, rblocks, WG, n, J.rowptr, J.colidx, w->ctl, o.twave, o.tsplit, J.expect_nnz,
            o.tiles);
     T.kern(0, k_validate_arcs, cus * 4, WG, n, J.rowptr, J.colidx, w->ctl);
-    if (voff) k_validate_batch<<<std::min(G, cus * 16), WG, 0, st>>>(G, n, voff, J.rowptr, J.colidx, w->ctl);
+    if (voff) k_validate_batch<<<cus * 4, WG, 0, st>>>(G, n, voff, J.rowptr, J.colidx, w->ctl);
     if (o.validate >= 1) k_check_symmetric<<<std::max(vblocks, 1), WG, 0, st>>>(n, J.rowptr, J.colidx, w->ctl);
     if (st_cap) {
         k_fill<<<std::max(1, std::min((2 * st_cap + WG - 1) / WG, cus)), WG, 0, st>>>(
@@ -1229,7 +1229,7 @@ int run_job(Workspace* w, Job& J, const long long* voff, int G) {
     // the arc pass skips itself when the vertex pass found an error, so one read-back
     // covers both
     T.kern(0, k_validate_arcs, cus * 4, WG, n, J.rowptr, J.colidx, w->ctl);
-    if (voff) k_validate_batch<<<std::min(G, cus * 16), WG, 0, st>>>(G, n, voff, J.rowptr, J.colidx, w->ctl);
+    if (voff) k_validate_batch<<<cus * 4, WG, 0, st>>>(G, n, voff, J.rowptr, J.colidx, w->ctl);
     HIP_TRY(hipGetLastError());
     if ((rc = read_ctl(w))) return rc;
     if (w->ctl_h->err) return CSRCOLOR_EBADCSR;

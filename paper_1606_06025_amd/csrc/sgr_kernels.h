@@ -608,7 +608,16 @@ __global__ __launch_bounds__(WG) void k_scatter(const MultiDesc* __restrict__ d,
 }
 
 // Batched validation: voff[0] == 0, non-decreasing, voff[G] == n_total, and every
-// arc of graph g stays inside graph g.
+// arc of graph g stays inside graph g.  The graph checks are a grid-stride loop over
+// g.  The arc checks are spread over the whole grid whatever the graph sizes: every
+// wavefront takes chunks of VB_CHUNK consecutive arc positions, finds the graph that
+// owns the chunk's first position (the last g whose first arc rowptr[voff[g]] is at or
+// before it) by binary search, and steps to the next graph wherever a position passes
+// the current graph's last arc.  Runs after the row pass accepted rowptr; the voff
+// entries it follows are clamped to [0, n_total], so a malformed voff (which fails the
+// graph checks) still keeps every read in bounds.
+constexpr int VB_CHUNK = 4096;
+
 __global__ __launch_bounds__(WG) void k_validate_batch(int G, int n_total, const long long* __restrict__ voff,
                                                        const int* __restrict__ rowptr,
                                                        const int* __restrict__ colidx, Ctl* ctl) {
@@ -616,23 +625,39 @@ __global__ __launch_bounds__(WG) void k_validate_batch(int G, int n_total, const
     if (ctl->err) return;
     int bad = 0;
     const long long nnz = rowptr[n_total];
-    for (int g = blockIdx.x; g < G; g += gridDim.x) {
+    const long long nthr = (long long)gridDim.x * WG;
+    for (long long g = (long long)blockIdx.x * WG + threadIdx.x; g < G; g += nthr) {
         const long long v0 = voff[g], v1 = voff[g + 1];
-        if ((g == 0 && v0 != 0) || v0 < 0 || v0 > n_total || v1 < v0 || v1 > n_total ||
-            (g == G - 1 && v1 != n_total)) {
+        if ((g == 0 && v0 != 0) || v0 < 0 || v0 > n_total || v1 < v0 || v1 > n_total || (g == G - 1 && v1 != n_total))
             bad = 1;
-            continue;
+    }
+    const int lane = __lane_id();
+    const long long nw = (long long)gridDim.x * WAVES;
+    for (long long c = (long long)blockIdx.x * WAVES + (threadIdx.x >> 6); c * VB_CHUNK < nnz; c += nw) {
+        const long long e0 = c * VB_CHUNK, e1 = min(e0 + VB_CHUNK, nnz);
+        int lo = 0, hi = G - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            const long long vm = min(max(voff[mid], 0ll), (long long)n_total);
+            if (rowptr[vm] <= e0) lo = mid;
+            else hi = mid - 1;
         }
-        // the row pass checked 0 <= rowptr[v] <= rowptr[v+1] <= rowptr[n_total]; the
-        // clamp keeps the reads inside colidx even if it is ever skipped
-        const long long e0 = min(max((long long)rowptr[v0], 0ll), nnz);
-        const long long e1 = min(max((long long)rowptr[v1], e0), nnz);
-        for (long long e = e0 + threadIdx.x; e < e1; e += WG) {
+        int g = lo;
+        long long v0 = min(max(voff[g], 0ll), (long long)n_total);
+        long long v1 = min(max(voff[g + 1], 0ll), (long long)n_total);
+        long long gend = rowptr[v1];
+        for (long long e = e0 + lane; e < e1; e += 64) {
+            while (e >= gend && g < G - 1) {
+                ++g;
+                v0 = v1;
+                v1 = min(max(voff[g + 1], 0ll), (long long)n_total);
+                gend = rowptr[v1];
+            }
             const int w = colidx[e];
             if (w < v0 || w >= v1) bad = 1;
         }
     }
-    if (__ballot(bad) && __lane_id() == 0) atomicOr(&ctl->err, ERR_BATCH);
+    if (__ballot(bad) && lane == 0) atomicOr(&ctl->err, ERR_BATCH);
 }
 
 }  // namespace csrcolor

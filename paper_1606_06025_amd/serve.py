@@ -52,6 +52,7 @@ class Request:
     ncolors: int = -1
     error: Optional[str] = None
     admitted: float = -1.0
+    uploaded: float = -1.0
     started: float = -1.0
     done_time: float = -1.0
     batch_size: int = 0
@@ -291,6 +292,7 @@ class ColoringServer:
         except Exception as e:  # a bad request fails alone
             req.error = f"upload failed: {e}"
         with self._cv:
+            req.uploaded = self.clock()
             if req.error:
                 self._finish(req)
             else:

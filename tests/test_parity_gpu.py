@@ -226,6 +226,41 @@ def test_batched_rejects_cross_graph_arcs(dev):
     assert e.value.status == L.EBADCSR
 
 
+def test_batched_validation_finds_every_cross_arc(dev):
+    """The batch check spreads the arcs over the grid in fixed chunks and finds each
+    chunk's graph by binary search: a union with empty graphs at the start, middle and
+    end and a graph spanning many chunks passes (and colours as its parts do), and one
+    arc moved into another graph is rejected wherever it sits (chunk edges, graph
+    edges, first and last arc)."""
+    import oracle
+    from paper_1606_06025_amd import _lib as L, api
+    parts = [gg.edgeless(3), gg.erdos_renyi(900, 5000, 7, 1), gg.edgeless(0), gg.rmat(12, 8, 3),
+             gg.edgeless(5), gg.cycle(9), gg.edgeless(2)]
+    b = gg.concat_graphs(parts)
+    voff = torch.from_numpy(b.voff).to(dev)
+    rp = torch.from_numpy(b.rowptr).to(dev)
+    colors, ncol = api.color_batched(voff, rp, torch.from_numpy(b.colidx).to(dev))
+    colors = colors.cpu().numpy()
+    for i, p in enumerate(parts):
+        if p.n:
+            ref = oracle.sgr(p.n, p.rowptr, p.colidx)
+            assert (colors[b.voff[i]:b.voff[i + 1]] == ref.colors).all(), i
+    first = [int(b.rowptr[b.voff[i]]) for i in range(len(parts) + 1)]
+    owner = np.searchsorted(np.array(first), np.arange(b.nnz), side="right") - 1
+    spots = {0, 4095, 4096, 4097, 8191, 8192, b.nnz - 1}
+    for i in range(len(parts)):
+        if first[i + 1] > first[i]:
+            spots |= {first[i], first[i + 1] - 1}
+    for e in sorted(x for x in spots if 0 <= x < b.nnz):
+        g = owner[e]
+        ci = b.colidx.copy()
+        # a vertex just outside graph g (below its range, or above it for the first graph)
+        ci[e] = b.voff[g] - 1 if b.voff[g] > 0 else b.voff[g + 1]
+        with pytest.raises(L.CsrColorError) as err:
+            api.color_batched(voff, rp, torch.from_numpy(ci).to(dev))
+        assert err.value.status == L.EBADCSR, e
+
+
 @pytest.mark.parametrize("shift", [0, 1, 2, 3])
 def test_validation_at_every_alignment(dev, shift):
     """The arc check streams colidx as aligned 16-byte quads: at every offset of the
