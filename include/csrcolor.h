@@ -30,12 +30,14 @@
  *   - Output colours are 0-based: colors_out[v] in [0, ncolors).
  *   - Work is enqueued on `stream`.  The library keeps a per-(device, stream)
  *     workspace that is grown on demand and freed by csrcolor_release_workspace():
- *     with the default options about 35 bytes per vertex plus 5 bytes per arc (colour
- *     state, two worklists, conflict hints, live-list lengths and lists, byte flags of
- *     the forbidden colours, wake flags and masks) plus the split-row scratch and a
- *     small control block; the multi-graph call adds a copy of the union CSR and its
- *     colours.  Calls on the same stream are serialised by a lock, calls on different
- *     streams do not share scratch.
+ *     with the default options at most about 56 bytes per vertex plus 5.3 bytes
+ *     per arc (colour state, two worklists, conflict hints, live-list lengths,
+ *     resume positions and lists, small-colour flag slots, byte flags of the
+ *     forbidden colours, wake flags and masks) plus the split-row scratch and a
+ *     small control block; the multi-graph call adds a copy of the union CSR and
+ *     its colours (csrcolor_workspace_bytes gives the exact bound).  Calls on the
+ *     same stream are serialised by a lock, calls on different streams do not
+ *     share scratch.
  *   - Errors are negative csrcolor_status values; outputs are then unspecified.
  *     Structural validation (rowptr monotone and in range, colidx in range) is
  *     always done on the device before any colouring kernel runs, so a
