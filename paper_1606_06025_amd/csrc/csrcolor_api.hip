@@ -163,6 +163,9 @@ int num_cus(int dev) {
     return g_num_cus[dev];
 }
 
+// Workgroups of a conflict-test launch: the budget, at most DETECT_PER_CU per CU.
+int detect_grid(int dev, int budget) { return std::max(1, std::min(budget, num_cus(dev) * DETECT_PER_CU)); }
+
 Workspace* get_ws(int dev, hipStream_t stream) {
     std::lock_guard<std::mutex> lk(g_mu);
     auto key = std::make_pair(dev, stream);
@@ -545,7 +548,7 @@ int drive_loop(Workspace* w, Job& J, RoundArgs& a, int ub[NB], int budget, KTime
                 RoundArgs ad = a;
                 ad.dev_plan = 1;
                 ad.lbs_n = budget;
-                T.kern(2, k_detect<false>, budget, WG, ad);
+                T.kern(2, k_detect<false>, detect_grid(w->device, budget), WG, ad);
             }
             if (a.pushff && ub[BSPLIT] > 0) {
                 const int pg = std::min(ub[BSPLIT], budget);
@@ -608,7 +611,7 @@ int drive_wake(Workspace* w, Job& J, RoundArgs& a, int budget, bool big, int nhu
             if (a.ubytes) T.kern(2, k_detect_flags<true>, a.gdense, WG, a);
             else T.kern(2, k_detect_flags<false>, a.gdense, WG, a);
             // the worklists of the long rows, if any, in a launch of their own
-            if (big) T.kern(2, k_detect<true>, budget, WG, a);
+            if (big) T.kern(2, k_detect<true>, detect_grid(w->device, budget), WG, a);
             if (nhub > 0) T.kern(2, k_push<true>, pgrid, WG, a);
             par ^= 1;
             ++r;
@@ -659,7 +662,7 @@ int drive_graph(Workspace* w, Job& J, RoundArgs& a, int budget) {
             r.wl_in = w->wl[par];
             r.wl_out = w->wl[par ^ 1];
             k_assign<<<budget, WG, 0, w->gstream>>>(r);
-            k_detect<false><<<budget, WG, 0, w->gstream>>>(r);
+            k_detect<false><<<detect_grid(w->device, budget), WG, 0, w->gstream>>>(r);
             if (r.pushff && r.cstart[1] != r.cstart[0]) k_push<false><<<budget, WG, 0, w->gstream>>>(r);  // split hubs exist
         }
         hipError_t ce = hipStreamEndCapture(w->gstream, &g);

@@ -517,8 +517,14 @@ __device__ __forceinline__ void detect_flags_phase(const RoundArgs& a, int* ids,
 // Conflict test of a round (Sec. 3, ConflictResolve; see detect_phase), one launch for
 // every degree bucket (with wake flags only the rows longer than WAKE_DEG are on the
 // worklists).
+// Four workgroups per CU: the conflict test needs about 104 VGPRs, and with six per CU
+// the compiler kept 80 and spilled 108 bytes per lane to scratch (R-MAT scale 23:
+// 40.3 -> 39.7 ms with four).  Its grid is at most this many blocks per CU, so that every
+// block is resident at once.
+constexpr int DETECT_PER_CU = 4;
+
 template <bool W>
-__global__ __launch_bounds__(WG, 6) void k_detect(RoundArgs a) {
+__global__ __launch_bounds__(WG, DETECT_PER_CU) void k_detect(RoundArgs a) {
     __shared__ RoundLds s;
     __shared__ int boff[NB + 1];
     if (threadIdx.x == 0) {
