@@ -476,6 +476,45 @@ def test_degree_rule_matches_oracle(dev, mode):
             _assert_parity(g, dev, rule=1, mode=mode, firstfit=ff)
 
 
+def _one_beater_graph(D, p, rule):
+    """Hub H of degree D whose only beater sits at position p of H's row; the other
+    neighbours are leaves.  Degree rule: sorted rows, the beater B has degree D + 1
+    (ids: leaves 0..p-1, B = p, leaves p+1..D-1, H = D, B's own leaves after H).  Id
+    rule: H = 1, the beater is vertex 0, every other neighbour has a higher id, and H's
+    row lists them in descending order with 0 at position p (unsorted rows)."""
+    if rule == 1:
+        H, B = D, p
+        edges = [(H, x) for x in range(D)] + [(B, D + 1 + k) for k in range(D)]
+        g = gg.from_edges(2 * D + 1, edges, name=f"beater_r1_D{D}_p{p}")
+        row = g.colidx[g.rowptr[H]:g.rowptr[H + 1]]
+        assert row[p] == B and int(np.diff(g.rowptr)[B]) == D + 1
+        return g
+    n = D + 1
+    others = list(range(n - 1, 1, -1))            # D - 1 higher neighbours, descending
+    hub_row = others[:p] + [0] + others[p:]
+    rows = {0: [1], 1: hub_row}
+    for x in others:
+        rows[x] = [1]
+    rowptr = np.zeros(n + 1, np.int32)
+    for v in range(n):
+        rowptr[v + 1] = rowptr[v] + len(rows[v])
+    colidx = np.concatenate([np.asarray(rows[v], np.int32) for v in range(n)])
+    return gg.CSR(n, rowptr, colidx, f"beater_r0_unsorted_D{D}_p{p}")
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_round1_scan_finds_the_only_beater(dev, rule):
+    """Without the id rule's first-arc test (degree rule, unsorted rows) round 1 scans a
+    row up to its first beater: one lane up to 64 arcs, the wavefront up to 4096, the
+    workgroup beyond, 256 or 1024 entries a step.  A hub whose only beater sits at a
+    lane, step or workgroup boundary (or at the row's end) must lose in round 1, as in
+    the oracle; a missed beater makes it a round-1 winner and changes the colouring."""
+    for D in (40, 65, 300, 4096, 4097, 5000):
+        for p in sorted({0, 3, 4, 63, 64, 255, 256, 1023, 1024, 4095, 4096, D - 1}):
+            if p < D:
+                _assert_parity(_one_beater_graph(D, p, rule), dev, rule=rule)
+
+
 def test_degree_rule_split_and_unsorted(dev):
     g = gg.rmat(16, 16, 13)
     _assert_parity(g, dev, rule=1, t_split=1024, t_wave=61)
