@@ -204,7 +204,7 @@ constexpr int R1_NONE = 0x7fffffff;
 __device__ __forceinline__ int first_beater_lane(int rule, const int* __restrict__ rowptr,
                                                  const int* __restrict__ colidx, int v, int beg, int end) {
     const int dv = end - beg;
-    for (int e = beg; e < end; e += 4) {
+    for (long long e = beg; e < end; e += 4) {   // (64-bit: end may lie near the int range's top)
         int w[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) w[k] = e + k < end ? colidx[e + k] : -1;
@@ -221,11 +221,11 @@ __device__ __forceinline__ int first_beater_wave(int rule, const int* __restrict
                                                  const int* __restrict__ colidx, int v, int beg, int end) {
     const int lane = __lane_id();
     const int dv = end - beg;
-    for (int base = beg; base < end; base += 4 * 64) {
+    for (long long base = beg; base < end; base += 4 * 64) {
         int w[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int e = base + k * 64 + lane;
+            const long long e = base + k * 64 + lane;
             w[k] = e < end ? colidx[e] : -1;
         }
         bool b[4];
@@ -350,18 +350,18 @@ __device__ __forceinline__ void round1_body(int n, const int* __restrict__ rowpt
             for (int j = 0; j < nbig; ++j) {
                 const int own = r1own[j][0], rv = r1own[j][1], rb = r1own[j][2], re = r1own[j][3];
                 int fp = R1_NONE;
-                for (int base = rb; base < re; base += 4 * WG) {
+                for (long long base = rb; base < re; base += 4 * WG) {
                     int w[4];
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        const int e = base + k * WG + threadIdx.x;
+                        const long long e = base + k * WG + threadIdx.x;
                         w[k] = e < re ? colidx[e] : -1;
                     }
                     int mine = R1_NONE;
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
                         if (mine == R1_NONE && w[k] >= 0 && w[k] != rv && beats(rule, rowptr, w[k], rv, re - rb))
-                            mine = base + k * WG + threadIdx.x - rb;
+                            mine = (int)(base + k * WG + threadIdx.x - rb);
                     if (mine != R1_NONE) atomicMin(&r1pos[slot], mine);
                     // the next step's slot was last read before the previous barrier
                     const int nxt = slot == 2 ? 0 : slot + 1;
