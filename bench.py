@@ -519,7 +519,7 @@ def bench_serve(args, dev) -> int:
     opts = api.make_opts(**sopts) if any(sopts.values()) else None
 
     def run(arrivals):
-        be = serve.HipBackend(nslots=args.slots, opts=opts)
+        be = serve.HipBackend(nslots=args.slots, opts=opts, small_grid_arcs=args.serve_small_grid)
         with serve.ColoringServer(be, budget, **limits) as srv:
             rr, wall = serve.replay(srv, pairs, arrivals)
             peak = srv.peak_bytes
@@ -626,6 +626,8 @@ def main() -> int:
     ap.add_argument("--requests", type=int, default=512, help="serve workload: number of requests")
     ap.add_argument("--slots", type=int, default=3, help="serve workload: concurrent stream slots")
     ap.add_argument("--max-batch", type=int, default=16, help="serve workload: requests per batch")
+    ap.add_argument("--serve-small-grid", type=int, default=0,
+                    help="serve workload: batches of at most this many arcs run on one workgroup per CU")
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="serve workload: admission budget")
     ap.add_argument("--max-scale", type=int, default=20, help="serve workload: largest R-MAT scale")
     ap.add_argument("--max-er-n", type=float, default=1e6, help="serve workload: largest ER size")

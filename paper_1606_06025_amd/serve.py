@@ -99,9 +99,11 @@ class HipBackend(Backend):
     buffer.  (Pinning every request's arrays first costs more than it saves: the pinned
     allocation and its page locking ran at a fraction of the copy engine's rate.)"""
 
-    def __init__(self, nslots: int = 2, device: str = "cuda:0", opts=None, nuploaders: int = 2):
+    def __init__(self, nslots: int = 2, device: str = "cuda:0", opts=None, nuploaders: int = 2,
+                 small_grid_arcs: int = 0, small_grid_per_cu: int = 1):
+        import ctypes
         import torch
-        from . import _lib
+        from . import _lib, api
         _lib.load()
         self.torch = torch
         self.device = torch.device(device)
@@ -110,6 +112,16 @@ class HipBackend(Backend):
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(nslots)]
         self.up_streams = [torch.cuda.Stream(device=self.device) for _ in range(nuploaders)]
         self.opts = opts
+        # batches of at most small_grid_arcs arcs launch on small_grid_per_cu workgroups
+        # per CU, leaving the rest of the GPU to the batches of other slots
+        self.small_grid_arcs = int(small_grid_arcs)
+        self.small_opts = None
+        if self.small_grid_arcs > 0:
+            so = api.make_opts()
+            if opts is not None:
+                ctypes.memmove(ctypes.addressof(so), ctypes.addressof(opts), ctypes.sizeof(so))
+            so.blocks_per_cu = small_grid_per_cu
+            self.small_opts = so
 
     def workspace_bytes(self, graphs, n, nnz):
         from . import api
@@ -139,8 +151,10 @@ class HipBackend(Backend):
         sizes = [h[2].numel() for h in handles]
         host = torch.empty(sum(sizes), dtype=torch.int32, pin_memory=True)
         with torch.cuda.stream(st):
+            small = self.small_opts is not None and sum(h[3] for h in handles) <= self.small_grid_arcs
             outs, ncol = api.color_multi([(h[0], h[1]) for h in handles], outs=[h[2] for h in handles],
-                                         nnz=[h[3] for h in handles], opts=self.opts, stream=st)
+                                         nnz=[h[3] for h in handles], opts=self.small_opts if small else self.opts,
+                                         stream=st)
             off = 0
             for o, k in zip(outs, sizes):
                 host[off:off + k].copy_(o[:k], non_blocking=True)
