@@ -52,11 +52,12 @@ def test_color_multi_rejects_bad_graph(dev):
     assert e.value.status == L.EBADCSR
 
 
-def test_server_alone_vs_mix(dev):
+@pytest.mark.parametrize("small_grid", [0, 200_000])
+def test_server_alone_vs_mix(dev, small_grid):
     """Every served result is the CPU oracle's colouring, and the one the graph gets
-    alone (tolerance 0).  Also the regression case of the first multi-graph call on
-    fresh streams (each slot's workspace starts empty and grows while the union is
-    being built)."""
+    alone (tolerance 0), also with small batches on one workgroup per CU.  Also the
+    regression case of the first multi-graph call on fresh streams (each slot's
+    workspace starts empty and grows while the union is being built)."""
     import oracle
     from paper_1606_06025_amd import api, serve
     gs = _mix(24, 7)
@@ -67,7 +68,7 @@ def test_server_alone_vs_mix(dev):
         c, nc, _ = api.color(torch.from_numpy(g.rowptr).to(dev), torch.from_numpy(g.colidx).to(dev))
         alone.append((c.cpu().numpy(), nc))
     limits = dict(max_batch=8, max_batch_vertices=8 * max(g.n for g in gs), max_batch_arcs=8 * max(g.nnz for g in gs))
-    be = serve.HipBackend(nslots=3)
+    be = serve.HipBackend(nslots=3, small_grid_arcs=small_grid)
     reserved = 3 * be.workspace_bytes(limits["max_batch"], limits["max_batch_vertices"], limits["max_batch_arcs"])
     budget = reserved + 6 * max(serve.footprint_bytes(g.n, g.nnz) for g in gs)
     # every request is queued before the scheduler starts, so the first dispatch finds
