@@ -193,14 +193,20 @@ def conflicts(n: int, rowptr, colidx, colors) -> int:
     """Number of arcs whose two (distinct) endpoints share a colour."""
     lib = _load()
     rp, ci, co = _as_i32(rowptr), _as_i32(colidx), _as_i32(colors)
-    return int(lib.oracle_count_conflicts(n, _ptr(rp), _ptr(ci), _ptr(co)))
+    k = int(lib.oracle_count_conflicts(n, _ptr(rp), _ptr(ci), _ptr(co)))
+    if k < 0:
+        raise ValueError(f"oracle_count_conflicts failed with status {k}")
+    return k
 
 
 def non_grundy(n: int, rowptr, colidx, colors) -> int:
     """Number of vertices whose 0-based colour differs from the mex of its neighbours."""
     lib = _load()
     rp, ci, co = _as_i32(rowptr), _as_i32(colidx), _as_i32(colors)
-    return int(lib.oracle_count_non_grundy(n, _ptr(rp), _ptr(ci), _ptr(co)))
+    k = int(lib.oracle_count_non_grundy(n, _ptr(rp), _ptr(ci), _ptr(co)))
+    if k < 0:
+        raise ValueError(f"oracle_count_non_grundy failed with status {k}")
+    return k
 
 
 def bytes_model(res: SGRResult, n: int) -> int:

@@ -251,12 +251,15 @@ int oracle_sgr_topo(int32_t n, const int32_t *rowptr, const int32_t *colidx,
 
 /* Sequential greedy colouring in natural vertex order (Sec. 2.1, Algorithm 1):
  * vertex v takes the smallest positive colour not held by an already-coloured
- * neighbour.  Output colours are 0-based. */
+ * neighbour.  Output colours are 0-based.  Returns -2 if a colidx entry is out of
+ * range. */
 int oracle_serial_ff(int32_t n, const int32_t *rowptr, const int32_t *colidx,
                      int32_t *colors_out, int32_t *ncolors_out)
 {
     *ncolors_out = 0;
     if (n <= 0) return 0;
+    for (int64_t e = 0; e < rowptr[n]; ++e)
+        if (colidx[e] < 0 || colidx[e] >= n) return -2;
     int32_t *col = calloc((size_t)n, sizeof(int32_t));
     int64_t *stamp = calloc((size_t)n + 2, sizeof(int64_t));
     if (!col || !stamp) { free(col); free(stamp); return -1; }
@@ -277,10 +280,14 @@ int oracle_serial_ff(int32_t n, const int32_t *rowptr, const int32_t *colidx,
     return 0;
 }
 
-/* Number of arcs (v, w), v != w, whose endpoints share a colour (0 = proper). */
+/* Number of arcs (v, w), v != w, whose endpoints share a colour (0 = proper); -2 if a
+ * colidx entry is out of range. */
 int64_t oracle_count_conflicts(int32_t n, const int32_t *rowptr, const int32_t *colidx,
                                const int32_t *colors)
 {
+    if (n <= 0) return 0;
+    for (int64_t e = 0; e < rowptr[n]; ++e)
+        if (colidx[e] < 0 || colidx[e] >= n) return -2;
     int64_t bad = 0;
     for (int32_t v = 0; v < n; ++v)
         for (int64_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
@@ -291,10 +298,14 @@ int64_t oracle_count_conflicts(int32_t n, const int32_t *rowptr, const int32_t *
 }
 
 /* Number of vertices whose colour is not the smallest colour absent from its
- * neighbourhood (0-based colours; 0 = the colouring is a Grundy colouring). */
+ * neighbourhood (0-based colours; 0 = the colouring is a Grundy colouring); -2 if a
+ * colidx entry is out of range. */
 int64_t oracle_count_non_grundy(int32_t n, const int32_t *rowptr, const int32_t *colidx,
                                 const int32_t *colors)
 {
+    if (n <= 0) return 0;
+    for (int64_t e = 0; e < rowptr[n]; ++e)
+        if (colidx[e] < 0 || colidx[e] >= n) return -2;
     int64_t *stamp = calloc((size_t)n + 2, sizeof(int64_t));
     if (!stamp) return -1;
     int64_t bad = 0;
