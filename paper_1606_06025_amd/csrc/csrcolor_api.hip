@@ -577,16 +577,21 @@ int drive_loop(Workspace* w, Job& J, RoundArgs& a, int ub[NB], int budget, KTime
 // every vertex is settled (the lowest uncoloured vertex is always tested).  That is
 // read back after every batch of rounds, one batch behind; rounds launched past the end
 // do nothing.
+// Launch shape of the flag scans: about 4096 wavefronts per scan (fewer leave the chip
+// idle, more pay their fixed costs (launch, flag load, compaction) on mostly empty
+// ranges; measured on the stencil: 2.1 M vertices best at 512 per wavefront, 0.9 M at
+// 256).
+void wake_shape(RoundArgs& a, int n, int budget) {
+    a.vpw = 64;
+    while (a.vpw < VPW && (long long)a.vpw * 4096 < n) a.vpw *= 2;
+    const long long scans = ((long long)n + (long long)a.vpw * WAVES - 1) / ((long long)a.vpw * WAVES);
+    a.gdense = (int)std::max<long long>(1, std::min<long long>(scans, 4LL * budget));
+}
+
 int drive_wake(Workspace* w, Job& J, RoundArgs& a, int budget, bool big, int nhub, int nchunk, KTimer& T) {
     hipStream_t st = w->stream;
     a.dev_plan = 1;
-    // about 4096 wavefronts per scan: fewer leave the chip idle, more pay their fixed
-    // costs (launch, flag load, compaction) on mostly empty ranges (measured on the
-    // stencil: 2.1 M vertices best at 512 per wavefront, 0.9 M at 256)
-    a.vpw = 64;
-    while (a.vpw < VPW && (long long)a.vpw * 4096 < J.n) a.vpw *= 2;
-    const long long scans = ((long long)J.n + (long long)a.vpw * WAVES - 1) / ((long long)a.vpw * WAVES);
-    a.gdense = (int)std::max<long long>(1, std::min<long long>(scans, 4LL * budget));
+    wake_shape(a, J.n, budget);
     const int pgrid = std::max(std::min(nchunk, budget), 1);
     if (!w->ctl_h2) {
         if (hipHostMalloc(&w->ctl_h2, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return CSRCOLOR_ENOMEM;
@@ -676,24 +681,130 @@ int drive_graph(Workspace* w, Job& J, RoundArgs& a, int budget) {
         w->gargs = a;
         w->gbudget = budget;
     }
+    if (!w->ctl_h2) {
+        if (hipHostMalloc(&w->ctl_h2, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return CSRCOLOR_ENOMEM;
+        for (int i = 0; i < 2; ++i) HIP_TRY(hipEventCreateWithFlags(&w->pev[i], hipEventDisableTiming));
+    }
     // the private stream waits for setup and round 1 on the caller's stream
     HIP_TRY(hipEventRecord(w->gev, w->stream));
     HIP_TRY(hipStreamWaitEvent(w->gstream, w->gev, 0));
+    // batches of k replays, each read back one batch behind (rounds replayed past the end
+    // find empty queues and do nothing), so the GPU never waits for the host
+    Ctl* mir[2] = {w->ctl_h, w->ctl_h2};
+    long long rend[2] = {0, 0};
     long long launched = 1;
     int k = 1;
-    for (;;) {
+    int rc = CSRCOLOR_OK;
+    for (int b = 0;; ++b) {
         for (int i = 0; i < k; ++i) HIP_TRY(hipGraphLaunch(w->gexec, w->gstream));
         launched += 2 * k;
-        HIP_TRY(hipMemcpyAsync(w->ctl_h, w->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, w->gstream));
-        HIP_TRY(hipStreamSynchronize(w->gstream));
-        if (w->ctl_h->err) return CSRCOLOR_EHIP;
-        long long left = 0;
-        for (int b = 0; b < NB; ++b) left += w->ctl_h->cnt[1][b];
-        if (left == 0) break;
-        if (launched > (long long)J.n + 2) return CSRCOLOR_ELIMIT;
+        rend[b & 1] = launched;
+        HIP_TRY(hipMemcpyAsync(mir[b & 1], w->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, w->gstream));
+        HIP_TRY(hipEventRecord(w->pev[b & 1], w->gstream));
+        if (b > 0) {
+            const int p = (b - 1) & 1;
+            HIP_TRY(hipEventSynchronize(w->pev[p]));
+            if (mir[p]->err) {
+                rc = CSRCOLOR_EHIP;
+                break;
+            }
+            long long left = 0;
+            for (int q = 0; q < NB; ++q) left += mir[p]->cnt[1][q];
+            if (left == 0) break;
+            if (rend[p] > (long long)J.n + 2) {
+                rc = CSRCOLOR_ELIMIT;
+                break;
+            }
+        }
         k = std::min(k * 2, std::max(1, J.opt.sync_every / 2));
     }
-    return CSRCOLOR_OK;
+    HIP_TRY(hipStreamSynchronize(w->gstream));
+    return rc;
+}
+
+// Graph mode with wake flags: two rounds (parity 1 -> 0 -> 1) of the launches drive_wake
+// makes for a round, the round number kept on the device (the recolouring FirstFit
+// advances it, the kernels after it read it), captured once into a hipGraph on a private
+// stream and replayed; the control block is read back every few
+// replays, and the run ends once a round has tested no vertex (rounds after it return
+// at once).  The capture is reused while the kernel arguments stay the same.
+int drive_wake_graph(Workspace* w, Job& J, RoundArgs& a, int budget, bool big, int nhub, int nchunk) {
+    a.dev_plan = 1;
+    a.lbs_n = budget;
+    a.wround = 0;
+    a.wround_dev = &w->ctl->wr;
+    wake_shape(a, J.n, budget);
+    const int pgrid = std::max(std::min(nchunk, budget), 1);
+    if (!w->gstream) {
+        HIP_TRY(hipStreamCreateWithFlags(&w->gstream, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&w->gev, hipEventDisableTiming));
+    }
+    const bool reuse = w->gexec && w->gbudget == budget && memcmp(&w->gargs, &a, sizeof(a)) == 0;
+    if (!reuse) {
+        if (w->gexec) (void)hipGraphExecDestroy(w->gexec);
+        w->gexec = nullptr;
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(w->gstream, hipStreamCaptureModeThreadLocal));
+        RoundArgs r = a;
+        for (int par = 1, i = 0; i < 2; ++i, par ^= 1) {
+            r.par_in = par;
+            r.par_out = par ^ 1;
+            r.wl_in = w->wl[par];
+            r.wl_out = w->wl[par ^ 1];
+            k_wassign<false><<<a.gdense, WG, 0, w->gstream>>>(r);
+            k_detect_flags<false><<<a.gdense, WG, 0, w->gstream>>>(r);
+            if (big) k_detect<true><<<detect_grid(w->device, budget), WG, 0, w->gstream>>>(r);
+            if (nhub > 0) k_push<true><<<pgrid, WG, 0, w->gstream>>>(r);
+        }
+        hipError_t ce = hipStreamEndCapture(w->gstream, &g);
+        if (ce != hipSuccess) return CSRCOLOR_EHIP;
+        ce = hipGraphInstantiate(&w->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ce != hipSuccess) {
+            w->gexec = nullptr;
+            return CSRCOLOR_EHIP;
+        }
+        w->gargs = a;
+        w->gbudget = budget;
+    }
+    if (!w->ctl_h2) {
+        if (hipHostMalloc(&w->ctl_h2, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return CSRCOLOR_ENOMEM;
+        for (int i = 0; i < 2; ++i) HIP_TRY(hipEventCreateWithFlags(&w->pev[i], hipEventDisableTiming));
+    }
+    // the private stream waits for setup and round 1 on the caller's stream
+    HIP_TRY(hipEventRecord(w->gev, w->stream));
+    HIP_TRY(hipStreamWaitEvent(w->gstream, w->gev, 0));
+    // batches of k replays; the control block after batch b is copied back behind it and
+    // read while batch b+1 runs (as in drive_wake), so the GPU never waits for the host
+    Ctl* mir[2] = {w->ctl_h, w->ctl_h2};
+    long long rend[2] = {0, 0};
+    long long last = 1;      // the last round launched
+    int k = 1;
+    int rc = CSRCOLOR_OK;
+    for (int b = 0;; ++b) {
+        for (int i = 0; i < k; ++i) HIP_TRY(hipGraphLaunch(w->gexec, w->gstream));
+        last += 2 * k;
+        rend[b & 1] = last;
+        HIP_TRY(hipMemcpyAsync(mir[b & 1], w->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, w->gstream));
+        HIP_TRY(hipEventRecord(w->pev[b & 1], w->gstream));
+        if (b > 0) {
+            const int p = (b - 1) & 1;
+            HIP_TRY(hipEventSynchronize(w->pev[p]));
+            if (mir[p]->err) {
+                rc = CSRCOLOR_EHIP;
+                break;
+            }
+            if (mir[p]->rounds < rend[p]) break;    // a round tested no vertex: all settled
+            if (rend[p] > (long long)J.n + 2) {      // a colouring takes at most n rounds
+                rc = CSRCOLOR_ELIMIT;
+                break;
+            }
+        }
+        k = std::min(k * 2, std::max(1, J.opt.sync_every / 2));
+    }
+    // the batch still in flight only finds a finished colouring
+    HIP_TRY(hipStreamSynchronize(w->gstream));
+    return rc;
 }
 
 // Topology-driven rounds: FirstFit and the conflict test over all n vertices; the
@@ -777,7 +888,9 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     const bool wake_wanted = J.opt.wake > 0 || (J.opt.wake == 0 && w->ctl_h->bigarcs * 10 < w->ctl_h->nnz);
     // (colour words keep BIG at bit 30, so colours must stay below 2^30)
     const bool use_wake = wake_wanted && hint && J.opt.rule == 0 && J.opt.pushff && J.opt.algo == CSRCOLOR_ALGO_SGR &&
-                          J.opt.mode == CSRCOLOR_MODE_LOOP && !J.opt.ordered && J.maxdeg < CMASK - 1;
+                          (J.opt.mode == CSRCOLOR_MODE_LOOP ||
+                           (J.opt.mode == CSRCOLOR_MODE_GRAPH && !(J.stats && J.stats->kernel_bytes))) &&
+                          !J.opt.ordered && J.maxdeg < CMASK - 1;
     const bool longrows = hist[NTILE] + hist[NTILE + 1] + hist[BSPLIT] > 0;
     J.wake = use_wake;
     if (use_wake) {
@@ -913,7 +1026,7 @@ int run_rounds(Workspace* w, Job& J, const int hist[NB], const Seg& seg, int st_
     }
 
     if (J.opt.mode == CSRCOLOR_MODE_GRAPH) {
-        rc = drive_graph(w, J, a, budget);
+        rc = use_wake ? drive_wake_graph(w, J, a, budget, longrows, nhub, nchunk) : drive_graph(w, J, a, budget);
     } else if (use_wake) {
         rc = drive_wake(w, J, a, budget, longrows, nhub, nchunk, T);
     } else {

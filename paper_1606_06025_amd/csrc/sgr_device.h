@@ -289,7 +289,7 @@ struct Ctl {
     int tk1;            // ordered compaction: round-1 tickets
     int nsettled;       // push tasks (split row, chunk) of the rows that settled this round
     int pround;         // FirstFit phases run so far (the 0-based index of the current round)
-    int pad[1];
+    int wr;             // wake-flag rounds replayed from a captured graph (advanced by k_wassign)
     long long bigarcs;  // arcs of the rows longer than WAKE_DEG
     // device-wide barrier of the persistent mode, each counter on its own 128-byte line
     int bar[8][32];
@@ -374,8 +374,11 @@ struct RoundArgs {
     // (its hint) has changed, or every round while awake; longer ones stay on the
     // worklists.  rflag[v]: recolour v this round (set by pushes); aflag[v]: test v
     // this round (set by recolouring, kept by an awake loser); srnd[v]: the round v
-    // settled in; wround: this round's number
+    // settled in; wround: this round's number, or with wround_dev != nullptr one more than
+    // the count there (rounds replayed from a captured graph: the recolouring FirstFit
+    // advances it)
     int wround;
+    const int* wround_dev;
     unsigned char* rflag;
     unsigned char* aflag;
     int* srnd;
@@ -392,6 +395,13 @@ struct RoundArgs {
     int seg[NB + 1];    // bucket segment offsets inside the worklist arrays
     int boff[NB + 1];   // block offsets of each bucket inside the grid
 };
+
+// The number of the current wake-flag round, for the kernels after the recolouring
+// FirstFit of the round (which advances the device count when rounds are replayed from
+// a captured graph).
+__device__ __forceinline__ int wround_of(const RoundArgs& a) {
+    return a.wround_dev ? *a.wround_dev + 1 : a.wround;
+}
 
 // Tentative colour of worklist vertex v: the FirstFit result in X, or under JP the
 // colour of the round.

@@ -507,7 +507,7 @@ __device__ __forceinline__ void detect_flags_phase(const RoundArgs& a, int* ids,
             test_flagged<C>(a, ids, cnt, slot, cmax, nb);
         }
     }
-    if (any && __lane_id() == 0) a.ctl->rounds = a.wround;
+    if (any && __lane_id() == 0) a.ctl->rounds = wround_of(a);
     if (C) {
         const long long t = block_sum64(nb, red64);
         if (threadIdx.x == 0 && t) atomicAdd(&a.ubytes[1], (unsigned long long)t);
@@ -556,7 +556,7 @@ __global__ __launch_bounds__(WG) void k_detect_flags(RoundArgs a) {
     __shared__ int red[WAVES];
     __shared__ long long red64[WAVES];
     const int wv = threadIdx.x >> 6;
-    if (a.ctl->rounds < a.wround - 1) return;    // past the end of the colouring
+    if (a.ctl->rounds < wround_of(a) - 1) return;    // past the end of the colouring
     int cmax = 0;
     detect_flags_phase<C>(a, ids[wv], slot[wv], blockIdx.x, gridDim.x, cmax, red64);
     cmax = block_max(cmax, red);

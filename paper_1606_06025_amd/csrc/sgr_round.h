@@ -794,7 +794,7 @@ template <bool W>
 __device__ __forceinline__ void settle(const RoundArgs& a, int v, int cv, int& cmax) {
     a.X[v] = cv;
     a.out[v] = cv - 1;
-    if (W) a.srnd[v] = a.wround;           // wake flags: the settling round, for the statistics
+    if (W) a.srnd[v] = wround_of(a);       // wake flags: the settling round, for the statistics
     cmax = max(cmax, cv);
 }
 
@@ -1782,7 +1782,7 @@ __device__ __forceinline__ void detect_phase(const RoundArgs& a, RoundLds& s, in
             a.ctl->dyn[0][k] = 0;
         }
         // with wake flags the conflict test marks the rounds that test a vertex
-        if (tot > 0 && W) a.ctl->rounds = a.wround;
+        if (tot > 0 && W) a.ctl->rounds = wround_of(a);
         if (tot > 0 && !W) {
             const int ridx = a.ctl->rounds;
             if (a.st_wsize && ridx < a.st_cap) a.st_wsize[ridx] = tot;

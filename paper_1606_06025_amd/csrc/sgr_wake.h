@@ -169,8 +169,16 @@ __global__ __launch_bounds__(WG) void k_wassign(RoundArgs a) {
     const int lane = __lane_id();
     const int wv = threadIdx.x >> 6;
     // a previous round that tested nothing ended the colouring: rounds launched past the
-    // end return at once
-    if (a.ctl->rounds < a.wround - 1) return;
+    // end return at once.  Rounds replayed from a captured graph: this kernel advances the
+    // device round count (its first thread), so its other blocks read the old or the new
+    // count; taking the count as read before the advance, the test below fires at most one
+    // round late (never early), and the kernels after this one read the advanced count
+    int wround = a.wround;
+    if (a.wround_dev) {
+        wround = __hip_atomic_load(a.wround_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(const_cast<int*>(a.wround_dev), 1);
+    }
+    if (a.ctl->rounds < wround - 1) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         for (int k = 0; k < NB; ++k) {
             a.ctl->cnt[a.par_out][k] = 0;

@@ -550,20 +550,24 @@ def test_live_lists_on_and_off(dev, live, mode):
         _assert_parity(g, dev, mode=mode, live_lists=live, hints=-1, t_wave=128, t_split=1024)
 
 
+@pytest.mark.parametrize("mode", [1, 3])
 @pytest.mark.parametrize("wake", [-1, 1])
 @pytest.mark.parametrize("live", [-1, 1])
-def test_wake_flags_on_and_off(dev, wake, live):
+def test_wake_flags_on_and_off(dev, wake, live, mode):
     """A requeued vertex may be left untested until its colour or that of its conflict
     hint changes; on or off, with live lists on or off, bit or byte flags, every bucket
-    (tiles, lanes, wavefront, workgroup, split rows), sorted or unsorted rows, the
-    colouring, the rounds and the per-round worklist sizes are the oracle's."""
+    (tiles, lanes, wavefront, workgroup, split rows), sorted or unsorted rows, in the
+    host loop and in rounds replayed from a captured graph (whose kernels read the
+    round number from the device), the colouring, the rounds and the per-round worklist
+    sizes are the oracle's."""
     graphs = [gg.stencil27(24, 20, 16), gg.rmat(14, 16, 12), gg.complete(300),
               _degree_ladder([5, 13, 29, 61, 62, 300, 1024, 1025, 2500, 9000], 7),
               gg.star(3000, [i for i in range(6001) if i != 3000]),
               gg.shuffle_rows(gg.erdos_renyi(20000, 200000, 8), 4), gg.cycle(1001)]
     for g in graphs:
-        _assert_parity(g, dev, wake=wake, live_lists=live)
-        _assert_parity(g, dev, wake=wake, live_lists=live, firstfit=2, lane_detect=-1, t_wave=128, t_split=1024)
+        _assert_parity(g, dev, wake=wake, live_lists=live, mode=mode)
+        _assert_parity(g, dev, wake=wake, live_lists=live, mode=mode, firstfit=2, lane_detect=-1, t_wave=128,
+                       t_split=1024)
 
 
 def test_wake_flags_repeated_entries(dev):
