@@ -80,7 +80,8 @@ typedef enum {
     CSRCOLOR_MODE_PERSISTENT = 2,  /* device-planned: the setup results never reach the host and one
                                       kernel runs every round after the first with device-wide
                                       barriers (the kernel fusion of Sec. 3.3); wake flags do not apply */
-    CSRCOLOR_MODE_GRAPH = 3        /* blocks of rounds captured once in a hipGraph and replayed */
+    CSRCOLOR_MODE_GRAPH = 3        /* blocks of rounds captured once in a hipGraph and replayed (with wake
+                                      flags too: the round number is kept on the device) */
 } csrcolor_mode;
 
 /* Which endpoint of a same-colour adjacent pair of worklist vertices is requeued. */
@@ -143,8 +144,8 @@ typedef struct {
                                take tickets and place their losers after those of lower tickets (look-back
                                prefix), so every worklist keeps ascending id order (same colouring) */
     int32_t wake;           /* 0: default (auto: on when rows longer than 61 arcs hold under a tenth of the
-                               arcs); 1: on; -1: off.  Wake flags (id rule, push FirstFit, hints on, LOOP mode,
-                               unordered compaction): a requeued vertex is tested again only once its tentative
+                               arcs); 1: on; -1: off.  Wake flags (id rule, push FirstFit, hints on, LOOP or
+                               GRAPH mode, unordered compaction): a requeued vertex is tested again only once its tentative
                                colour or that of the neighbour that requeued it has changed; every other one
                                loses again without being read (same colouring and rounds) */
     int32_t tile_limits;    /* 0: default.  Largest degrees of the tile buckets 0, 1, 2 (2, 4, 8 lanes per vertex
